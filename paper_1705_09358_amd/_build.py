@@ -1,0 +1,69 @@
+"""In-tree build of the native parts: the HIP library (gfx950) and the C input generator."""
+from __future__ import annotations
+
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+REPO = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIBDIR = os.path.join(HERE, "_lib")
+INCLUDE = os.path.join(REPO, "include")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+
+SGE_SO = os.path.join(LIBDIR, "libsge.so")
+SYNTH_SO = os.path.join(LIBDIR, "libsynth_walk.so")
+
+# Host sources (plain C++) and device sources (HIP) of the search library.
+HOST_SRCS = ["sge_graph.cpp", "sge_plan.cpp", "sge_api.cpp", "sge_batch.cpp", "sge_serve.cpp"]
+HIP_SRCS = ["sge_search.hip"]
+
+HIP_FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    # packed fp32 instructions are kept out of every device object
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function",
+]
+
+
+def _run(cmd: list[str]) -> None:
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("build failed:\n" + " ".join(cmd) + "\n" + r.stdout + r.stderr)
+
+
+def _atomic_link(cmd_out: list[str], out: str) -> None:
+    tmp = out + ".tmp%d" % os.getpid()
+    _run(cmd_out + ["-o", tmp])
+    os.replace(tmp, out)
+
+
+def build_synth() -> str:
+    os.makedirs(LIBDIR, exist_ok=True)
+    src = os.path.join(CSRC, "synth_walk.c")
+    _atomic_link(["gcc", "-O2", "-shared", "-fPIC", src, "-lm"], SYNTH_SO)
+    return SYNTH_SO
+
+
+def build_sge() -> str:
+    os.makedirs(LIBDIR, exist_ok=True)
+    objdir = os.path.join(LIBDIR, "obj")
+    os.makedirs(objdir, exist_ok=True)
+    objs = []
+    for s in HOST_SRCS + HIP_SRCS:
+        src = os.path.join(CSRC, s)
+        obj = os.path.join(objdir, s + ".o")
+        cmd = [os.path.join(ROCM, "bin", "hipcc"), *HIP_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
+        if s.endswith(".cpp"):
+            cmd.insert(1, "-x")
+            cmd.insert(2, "hip") if s.endswith(".hip") else None
+        _run(cmd)
+        objs.append(obj)
+    _atomic_link([os.path.join(ROCM, "bin", "hipcc"), "--offload-arch=gfx950", "-shared", "-fPIC", *objs,
+                  "-lpthread"], SGE_SO)
+    return SGE_SO
+
+
+def build_all() -> None:
+    build_synth()
+    build_sge()
