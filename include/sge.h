@@ -1,0 +1,173 @@
+/*
+ * sge.h -- C ABI of the MI355X (gfx950) subgraph-enumeration library.
+ *
+ * The library enumerates or counts every non-induced, label-preserving
+ * embedding of a pattern graph in a target graph: every injective
+ * M : V_p -> V_t with lab(u) = lab(M u) (when labelled) and (M u, M w) in E_t
+ * for every pattern edge (u, w) -- Kimmig, Meyerhenke, Strash, "Shared Memory
+ * Parallel Subgraph Enumeration" (arXiv 1705.09358), Section 2.1, eqs. (2)-(3)
+ * and the remark after them that the subgraphs are non-induced.
+ *
+ * The search is RI (Bonnici et al.) as the paper restates it: a depth-first
+ * search over a static constraint-first order of the pattern nodes, taking the
+ * candidates for each pattern node from the target neighbours of its already
+ * mapped parent and pruning with four rules (unused, equal label, degree,
+ * edges to mapped nodes).  RI-DS adds domains (Section 4.1): per pattern node
+ * the compatible target nodes, filtered by arc-consistency.  The paper's
+ * improvements (Section 4.2) are the domain-size tie-break of the order (SI)
+ * and forward checking on singleton domains (FC).
+ *
+ * Conventions for every call:
+ *  - Return value: SGE_OK (0) or a negative sge_status; the context keeps a
+ *    message for the last error (sge_last_error).
+ *  - Graphs are undirected and simple.  They are passed as symmetric CSR:
+ *    row_ptr[n+1] (row_ptr[0] = 0, non-decreasing) and col[row_ptr[n]] with
+ *    every id < n.  Rows may be unsorted and may hold duplicates (both are
+ *    normalised); a self-loop or an asymmetric entry is SGE_E_INVAL.
+ *  - Input arrays are host pointers, borrowed for the duration of the call
+ *    and copied in.  Output buffers belong to the caller.
+ *  - Handles belong to the context and die with it.
+ *  - One context per host thread.  The serve calls are internally
+ *    synchronised.
+ *  - Pattern size k <= 64.  k = 0 has exactly one (empty) match; k > n has
+ *    none.
+ *  - Rows: a match is written as k uint32 values in pattern-id order,
+ *    row[u] = M(u).  Rows come out in an unspecified order.
+ */
+#ifndef SGE_H
+#define SGE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sge_status;
+enum {
+    SGE_OK = 0,
+    SGE_E_INVAL = -1,     /* bad argument or malformed graph                          */
+    SGE_E_NOMEM = -2,     /* host or device allocation failed                         */
+    SGE_E_DEVICE = -3,    /* a HIP call failed (message holds the HIP error string)   */
+    SGE_E_OVERFLOW = -4,  /* more matches than rows given: counts are complete, the
+                             first cap_rows rows are valid                             */
+    SGE_E_ABORTED = -5,   /* states exceeded the cap: counters are partial            */
+    SGE_E_BUSY = -6,      /* serve: not admissible now / result not ready yet         */
+    SGE_E_HANDLE = -7     /* unknown target, pattern or ticket handle                 */
+};
+
+/* Search variants.  RI: Section "RI" (candidates from the parent, rules 1-4).
+ * RIDS: Section 4.1 domains with arc-consistency, singleton domains first in
+ * the order, roots from the first node's domain, domain test before the rules.
+ * RIDS_SI: plus the domain-size tie-break of the order (Section 4.2.1).
+ * RIDS_SI_FC: plus forward checking on singleton domains (Section 4.2.2). */
+enum { SGE_RI = 0, SGE_RIDS = 1, SGE_RIDS_SI = 2, SGE_RIDS_SI_FC = 3 };
+
+/* Counters of one search.
+ *  matches     complete embeddings found;
+ *  states      accepted (pattern node, target node) pairs, i.e. consistent
+ *              partial mappings summed over their lengths -- independent of
+ *              the traversal order and the parallel schedule;
+ *  candidates  pairs examined (implementation-dependent, for reporting);
+ *  steals      tasks moved between search units through the work queue;
+ *  ms_prep     host preparation time (order, parents, domains, upload);
+ *  ms_search   device time of the search launch. */
+typedef struct {
+    uint64_t matches, states, candidates, steals;
+    double ms_prep, ms_search;
+} sge_result;
+
+typedef struct sge_ctx sge_ctx;
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * (NULL = the null stream); every device operation of the context is ordered
+ * on it.  *out receives the context. */
+sge_status sge_create(int device, void *hip_stream, sge_ctx **out);
+void sge_destroy(sge_ctx *ctx);
+const char *sge_last_error(const sge_ctx *ctx);
+
+/* Load a target graph and keep it resident in device memory (CSR, per-node
+ * records and, when the graph is small enough, a dense adjacency bitset).
+ * labels: n uint32 or NULL (all nodes equivalent).  *handle receives the id. */
+sge_status sge_load_target(sge_ctx *ctx, uint32_t n, const uint32_t *row_ptr, const uint32_t *col,
+                           const uint32_t *labels, uint32_t *handle);
+sge_status sge_unload_target(sge_ctx *ctx, uint32_t handle);
+
+/* Load a pattern graph (k <= 64 nodes, same CSR conventions). */
+sge_status sge_load_pattern(sge_ctx *ctx, uint32_t k, const uint32_t *row_ptr, const uint32_t *col,
+                            const uint32_t *labels, uint32_t *handle);
+sge_status sge_unload_pattern(sge_ctx *ctx, uint32_t handle);
+
+/* labelled = 0: labels are ignored (every node equivalent, Section 2.1). */
+sge_status sge_set_labelled(sge_ctx *ctx, int labelled);
+/* mode: SGE_RI | SGE_RIDS | SGE_RIDS_SI | SGE_RIDS_SI_FC. */
+sge_status sge_set_mode(sge_ctx *ctx, int mode);
+/* cap = 0: no cap.  Otherwise a search whose states exceed cap stops with
+ * SGE_E_ABORTED; "exceeds" is decided on the schedule-independent count. */
+sge_status sge_set_state_cap(sge_ctx *ctx, uint64_t cap);
+/* Restrict the first pattern node of the order to target nodes in [lo, hi)
+ * (a shard of the root candidates; lo = 0, hi = UINT32_MAX restores all).
+ * Counters then cover that shard only. */
+sge_status sge_set_root_range(sge_ctx *ctx, uint32_t lo, uint32_t hi);
+
+/* Count the embeddings of `pattern` in `target`. */
+sge_status sge_count(sge_ctx *ctx, uint32_t target, uint32_t pattern, sge_result *res);
+
+/* Enumerate: as sge_count, and write up to cap_rows rows of k uint32 to
+ * `rows` (host or device pointer; device memory must be on the context's
+ * device).  More matches than cap_rows: SGE_E_OVERFLOW with full counts. */
+sge_status sge_enumerate(sge_ctx *ctx, uint32_t target, uint32_t pattern, uint32_t *rows, uint64_t cap_rows,
+                         sge_result *res);
+
+/* ---------------------------------------------------------------- batching */
+/* One (target, pattern) pair of a batch with its own mode and labelling. */
+typedef struct {
+    uint32_t target, pattern;
+    int32_t mode, labelled;
+} sge_job;
+
+/* Search all jobs in one persistent launch (captured in a HIP graph and
+ * replayed).  results[njobs] receives each job's counters; the state cap of
+ * the context applies per job.  Returns SGE_E_ABORTED if any job was capped
+ * (its counters are partial); the others are complete. */
+sge_status sge_batch_run(sge_ctx *ctx, uint32_t njobs, const sge_job *jobs, sge_result *results);
+
+/* Batch launch policy: 0 = autotuned (default), 1 = one search unit takes a
+ * whole job, 2 = jobs are split into root chunks shared by all units. */
+sge_status sge_set_batch_policy(sge_ctx *ctx, int policy);
+
+/* ----------------------------------------------------------------- serving */
+/* Start the resident server: a persistent kernel that takes queries from a
+ * ring as they arrive.  slots = maximum queries in flight; arena_bytes =
+ * device memory for per-query plans and domains (admission is by this
+ * memory and by free slots). */
+sge_status sge_serve_start(sge_ctx *ctx, uint32_t slots, uint64_t arena_bytes);
+/* Submit one query (job->mode / labelled apply).  SGE_E_BUSY when no slot
+ * or memory is free now.  *ticket identifies the query. */
+sge_status sge_serve_submit(sge_ctx *ctx, const sge_job *job, uint64_t *ticket);
+/* Poll a query: SGE_E_BUSY while it runs, else its final status with *res
+ * filled and the ticket released. */
+sge_status sge_serve_poll(sge_ctx *ctx, uint64_t ticket, sge_result *res);
+/* Stop the server after the queries in flight complete. */
+sge_status sge_serve_stop(sge_ctx *ctx);
+
+/* ------------------------------------------------------------- inspection */
+/* The host plan the library computes for a (pattern, target) pair, for
+ * checking against an independent reference.  Host arrays only; no device is
+ * touched.  order[k]: position -> pattern node; parent[k]: position ->
+ * earlier position or -1; dom (may be NULL): k * ceil(n/64) uint64 words of
+ * the final domains indexed by pattern node (unused in SGE_RI).  *empty = 1
+ * when a domain became empty (no matches; order is then not written). */
+sge_status sge_plan_host(uint32_t k, const uint32_t *p_row_ptr, const uint32_t *p_col, const uint32_t *p_labels,
+                         uint32_t n, const uint32_t *t_row_ptr, const uint32_t *t_col, const uint32_t *t_labels,
+                         int mode, int labelled, uint32_t *order, int32_t *parent, uint64_t *dom, int *empty);
+
+/* Tuning knobs (for measurement): lanes per search unit (8, 16, 32 or 64;
+ * 0 = automatic), root chunk size (0 = automatic), work donation on/off,
+ * dense-bitset search (-1 = automatic, 0 = off, 1 = on). */
+sge_status sge_set_tuning(sge_ctx *ctx, int lanes_per_unit, uint32_t root_chunk, int donate, int dense);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SGE_H */

@@ -40,7 +40,7 @@ def lib():
         p = ctypes.c_void_p
         L.oracle_run.restype = ctypes.c_int
         L.oracle_run.argtypes = [ctypes.c_uint32, p, p, p, ctypes.c_uint32, p, p, p, ctypes.c_int, ctypes.c_int,
-                                 ctypes.c_uint64, p, ctypes.c_uint64, p]
+                                 ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, p, ctypes.c_uint64, p]
         L.oracle_plan.restype = ctypes.c_int
         L.oracle_plan.argtypes = [ctypes.c_uint32, p, p, p, ctypes.c_uint32, p, p, p, ctypes.c_int, ctypes.c_int,
                                   p, p, p, p]
@@ -62,13 +62,15 @@ def _graph_args(g):
 
 
 def run(pattern, target, mode: int, labelled: bool, state_cap: int = 0, rows: bool = False,
-        cap_rows: int = 1 << 20) -> dict:
-    """Enumerate; returns {status, matches, states, candidates, alg_bytes, rows?}."""
+        cap_rows: int = 1 << 20, root_range=(0, 0xFFFFFFFF)) -> dict:
+    """Enumerate; returns {status, matches, states, candidates, alg_bytes, rows?}.
+    root_range restricts the first node of the order to target nodes in [lo, hi)."""
     keep_p, pa = _graph_args(pattern)
     keep_t, ta = _graph_args(target)
     cnt = np.zeros(4, dtype=np.uint64)
     buf = np.zeros((cap_rows if rows else 0, max(pattern.n, 1)), dtype=np.uint32)
     rc = lib().oracle_run(pattern.n, *pa, target.n, *ta, int(mode), int(bool(labelled)), int(state_cap),
+                          int(root_range[0]), int(root_range[1]),
                           buf.ctypes.data if rows else None, cap_rows if rows else 0, cnt.ctypes.data)
     if rc < 0:
         raise ValueError(f"oracle rejected the input (code {rc})")

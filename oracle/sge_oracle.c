@@ -103,6 +103,7 @@ typedef struct {
     uint64_t matches, states, candidates, alg_bytes;
     uint32_t *rows;
     uint64_t cap_rows;
+    uint32_t root_lo, root_hi;  /* first position restricted to target nodes in [lo, hi) */
     int aborted;
 } oracle_t;
 
@@ -262,6 +263,7 @@ static void search(oracle_t *o, uint32_t i) {
     }
     for (uint32_t e = lo; e < hi; e++) {
         uint32_t v = list ? list[e] : e;
+        if (i == 0 && (v < o->root_lo || v >= o->root_hi)) continue;   /* root shard */
         if (!list && use_dom) {
             /* parentless RI-DS position: candidates are the members of D(u) */
             if (!o->dom[(size_t)u * o->n + v]) continue;
@@ -348,17 +350,21 @@ int oracle_plan(uint32_t k, const uint32_t *prp, const uint32_t *pcol, const uin
 /*
  * Full run.  counters[0..3] = matches, states, candidates, alg_bytes.  Rows
  * (pattern-id order) are written for the first cap_rows matches when rows is
- * given.  Returns OR_OK, OR_ABORTED when states exceed state_cap (> 0), or a
- * negative error.
+ * given.  The first pattern node of the order is restricted to target nodes in
+ * [root_lo, root_hi) (a shard of the search; 0 and UINT32_MAX for all).
+ * Returns OR_OK, OR_ABORTED when states exceed state_cap (> 0), or a negative
+ * error.
  */
 int oracle_run(uint32_t k, const uint32_t *prp, const uint32_t *pcol, const uint32_t *plab,
                uint32_t n, const uint32_t *trp, const uint32_t *tcol, const uint32_t *tlab,
-               int mode, int labelled, uint64_t state_cap, uint32_t *rows, uint64_t cap_rows,
-               uint64_t *counters) {
+               int mode, int labelled, uint64_t state_cap, uint32_t root_lo, uint32_t root_hi,
+               uint32_t *rows, uint64_t cap_rows, uint64_t *counters) {
     oracle_t o;
     int empty = 0;
     int rc = oracle_setup(&o, k, prp, pcol, plab, n, trp, tcol, tlab, mode, labelled, &empty);
     if (rc != OR_OK) return rc;
+    o.root_lo = root_lo;
+    o.root_hi = root_hi;
     o.cap = state_cap;
     o.rows = rows;
     o.cap_rows = rows ? cap_rows : 0;

@@ -16,6 +16,7 @@ SYNTH_SO = os.path.join(LIBDIR, "libsynth_walk.so")
 
 # Host sources (plain C++) and device sources (HIP) of the search library.
 HOST_SRCS = ["sge_graph.cpp", "sge_plan.cpp", "sge_api.cpp", "sge_batch.cpp", "sge_serve.cpp"]
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__"]
 HIP_SRCS = ["sge_search.hip"]
 
 HIP_FLAGS = [
@@ -50,17 +51,23 @@ def build_sge() -> str:
     objdir = os.path.join(LIBDIR, "obj")
     os.makedirs(objdir, exist_ok=True)
     objs = []
+    inc = ["-I", INCLUDE, "-I", CSRC, "-I", os.path.join(ROCM, "include")]
+    procs = []
     for s in HOST_SRCS + HIP_SRCS:
         src = os.path.join(CSRC, s)
         obj = os.path.join(objdir, s + ".o")
-        cmd = [os.path.join(ROCM, "bin", "hipcc"), *HIP_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
         if s.endswith(".cpp"):
-            cmd.insert(1, "-x")
-            cmd.insert(2, "hip") if s.endswith(".hip") else None
-        _run(cmd)
+            cmd = ["g++", *HOST_FLAGS, *inc, "-c", src, "-o", obj]
+        else:
+            cmd = [os.path.join(ROCM, "bin", "hipcc"), *HIP_FLAGS, *inc, "-c", src, "-o", obj]
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
         objs.append(obj)
+    for cmd, p in procs:
+        outp, _ = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError("build failed:\n" + " ".join(cmd) + "\n" + outp)
     _atomic_link([os.path.join(ROCM, "bin", "hipcc"), "--offload-arch=gfx950", "-shared", "-fPIC", *objs,
-                  "-lpthread"], SGE_SO)
+                  "-lpthread", "-Wl,-rpath," + os.path.join(ROCM, "lib")], SGE_SO)
     return SGE_SO
 
 

@@ -1,0 +1,101 @@
+// Batching: many (pattern, target) jobs of uneven size in one persistent
+// launch captured in a HIP graph, with an autotuner that picks between one
+// search unit per job and root chunks of every job shared by all units, and
+// the unit width (lanes per unit).
+#include <algorithm>
+#include <chrono>
+
+#include "sge_ctx.h"
+
+using namespace sge;
+
+namespace {
+
+struct TuneChoice {
+    int policy = 2;
+    int lanes = 16;
+    uint32_t njobs = 0;
+    bool valid = false;
+};
+
+// Keyed by the batch size: repeated runs of the same workload reuse the choice.
+std::mutex tune_mu;
+std::map<std::pair<const sge_ctx *, uint32_t>, TuneChoice> tune_cache;
+
+}  // namespace
+
+extern "C" {
+
+sge_status sge_set_batch_policy(sge_ctx *c, int policy) {
+    if (!c) return SGE_E_INVAL;
+    if (policy < 0 || policy > 2) return fail(c, SGE_E_INVAL, "batch policy must be 0, 1 or 2");
+    c->batch_policy = policy;
+    return SGE_OK;
+}
+
+sge_status sge_batch_run(sge_ctx *c, uint32_t njobs, const sge_job *jobs, sge_result *results) {
+    if (!c || (njobs && (!jobs || !results))) return SGE_E_INVAL;
+    (void)hipSetDevice(c->device);
+    std::vector<InstanceSpec> specs(njobs);
+    for (uint32_t i = 0; i < njobs; i++) {
+        auto it = c->targets.find(jobs[i].target);
+        if (it == c->targets.end()) return fail(c, SGE_E_HANDLE, "job " + std::to_string(i) + ": unknown target");
+        auto ip = c->patterns.find(jobs[i].pattern);
+        if (ip == c->patterns.end()) return fail(c, SGE_E_HANDLE, "job " + std::to_string(i) + ": unknown pattern");
+        if (jobs[i].mode < SGE_RI || jobs[i].mode > SGE_RIDS_SI_FC)
+            return fail(c, SGE_E_INVAL, "job " + std::to_string(i) + ": unknown mode");
+        specs[i].t = it->second.get();
+        specs[i].p = ip->second.get();
+        specs[i].mode = jobs[i].mode;
+        specs[i].labelled = jobs[i].labelled != 0;
+    }
+    std::vector<InstanceOut> out;
+    double mp = 0, ms = 0;
+    int policy = c->batch_policy;
+    int saved_lanes = c->lanes;
+    if (policy == 0) {
+        TuneChoice tc;
+        {
+            std::lock_guard<std::mutex> g(tune_mu);
+            auto it = tune_cache.find({c, njobs});
+            if (it != tune_cache.end()) tc = it->second;
+        }
+        if (!tc.valid) {
+            // autotune: time each candidate launch shape on this batch
+            double best = 1e300;
+            const int policies[2] = {1, 2};
+            const int lanes[3] = {8, 16, 32};
+            for (int p : policies)
+                for (int l : lanes) {
+                    if (saved_lanes && l != saved_lanes) continue;
+                    c->lanes = l;
+                    sge_status st = run_instances(c, specs, out, mp, ms, true, p);
+                    if (st != SGE_OK) { c->lanes = saved_lanes; return st; }
+                    if (ms < best) { best = ms; tc.policy = p; tc.lanes = l; }
+                }
+            tc.valid = true;
+            tc.njobs = njobs;
+            std::lock_guard<std::mutex> g(tune_mu);
+            tune_cache[{c, njobs}] = tc;
+        }
+        policy = tc.policy;
+        c->lanes = saved_lanes ? saved_lanes : tc.lanes;
+    }
+    sge_status st = run_instances(c, specs, out, mp, ms, true, policy);
+    c->lanes = saved_lanes;
+    if (st != SGE_OK) return st;
+    bool aborted = false;
+    for (uint32_t i = 0; i < njobs; i++) {
+        results[i].matches = out[i].matches;
+        results[i].states = out[i].states;
+        results[i].candidates = out[i].candidates;
+        results[i].steals = out[i].steals;
+        results[i].ms_prep = mp;
+        results[i].ms_search = ms;
+        aborted |= out[i].status == SGE_E_ABORTED;
+    }
+    if (aborted) return fail(c, SGE_E_ABORTED, "state cap exceeded by at least one job");
+    return SGE_OK;
+}
+
+}  // extern "C"

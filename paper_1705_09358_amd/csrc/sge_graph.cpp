@@ -1,0 +1,76 @@
+// Graph ingest: validation and normalisation of symmetric CSR input, and the
+// per-target label index the planner reads.  Graphs are undirected and simple
+// (Section 2.1 with undirected edges); labels are compared for equality only.
+#include <algorithm>
+#include <unordered_map>
+
+#include "sge_internal.h"
+
+namespace sge {
+
+std::string normalise_graph(uint32_t n, const uint32_t *row_ptr, const uint32_t *col, const uint32_t *labels,
+                            HostGraph &out) {
+    if (!row_ptr) return "row_ptr is NULL";
+    if (row_ptr[0] != 0) return "row_ptr[0] must be 0";
+    for (uint32_t v = 0; v < n; v++)
+        if (row_ptr[v + 1] < row_ptr[v]) return "row_ptr is decreasing at node " + std::to_string(v);
+    uint64_t m = row_ptr[n];
+    if (m && !col) return "col is NULL";
+    if (m > 0xFFFFFFF0ull) return "too many adjacency entries";
+    out.n = n;
+    out.rp.assign(n + 1, 0);
+    out.col.clear();
+    out.col.reserve(m);
+    std::vector<uint32_t> row;
+    for (uint32_t v = 0; v < n; v++) {
+        row.assign(col + row_ptr[v], col + row_ptr[v + 1]);
+        for (uint32_t w : row) {
+            if (w >= n) return "neighbour id out of range at node " + std::to_string(v);
+            if (w == v) return "self-loop at node " + std::to_string(v);
+        }
+        std::sort(row.begin(), row.end());
+        row.erase(std::unique(row.begin(), row.end()), row.end());
+        out.col.insert(out.col.end(), row.begin(), row.end());
+        out.rp[v + 1] = (uint32_t)out.col.size();
+    }
+    // symmetry: every (v, w) needs (w, v)
+    for (uint32_t v = 0; v < n; v++) {
+        for (uint32_t e = out.rp[v]; e < out.rp[v + 1]; e++) {
+            uint32_t w = out.col[e];
+            if (!std::binary_search(out.col.begin() + out.rp[w], out.col.begin() + out.rp[w + 1], v))
+                return "asymmetric adjacency: " + std::to_string(v) + " -> " + std::to_string(w) +
+                       " has no reverse entry";
+        }
+    }
+    out.has_labels = labels != nullptr;
+    out.lab.assign(n, 0);
+    if (labels) std::copy(labels, labels + n, out.lab.begin());
+    return "";
+}
+
+void index_target(Target &t) {
+    const HostGraph &g = t.g;
+    std::unordered_map<uint32_t, uint32_t> ids;
+    t.dlab.resize(g.n);
+    t.label_keys.clear();
+    t.by_label.clear();
+    for (uint32_t v = 0; v < g.n; v++) {
+        auto it = ids.find(g.lab[v]);
+        uint32_t id;
+        if (it == ids.end()) {
+            id = (uint32_t)t.label_keys.size();
+            ids.emplace(g.lab[v], id);
+            t.label_keys.push_back(g.lab[v]);
+            t.by_label.emplace_back();
+        } else {
+            id = it->second;
+        }
+        t.dlab[v] = id;
+        t.by_label[id].push_back(v);
+    }
+    t.W = (g.n + 63) / 64;
+    t.max_deg = 0;
+    for (uint32_t v = 0; v < g.n; v++) t.max_deg = std::max(t.max_deg, g.rp[v + 1] - g.rp[v]);
+}
+
+}  // namespace sge

@@ -1,0 +1,165 @@
+// Internal declarations shared by the host code and the HIP search kernels.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "sge.h"
+
+namespace sge {
+
+constexpr uint32_t KMAX = 64;              // largest pattern (positions held in 64-bit masks)
+constexpr uint32_t LABEL_ANY = 0xFFFFFFFEu;  // unlabelled search: every label matches
+constexpr uint32_t LABEL_NONE = 0xFFFFFFFFu; // pattern label absent from the target
+constexpr uint32_t QUEUE_SLOTS = 4096;     // work-queue capacity (tasks)
+
+// ---------------------------------------------------------------- host graphs
+struct HostGraph {
+    uint32_t n = 0;
+    std::vector<uint32_t> rp, col, lab;  // lab: raw labels as given (0 if none)
+    bool has_labels = false;
+};
+
+// Validate and normalise symmetric CSR input (sort rows, merge duplicates).
+// Returns an empty string on success, else the reason.
+std::string normalise_graph(uint32_t n, const uint32_t *row_ptr, const uint32_t *col, const uint32_t *labels,
+                            HostGraph &out);
+
+// Per-node record read by the search: row start and degree in the CSR, and
+// the dense label id.
+struct NodeRec {
+    uint32_t begin, deg, label, pad;
+};
+
+// A target resident on the device, with the host copies the planner reads.
+struct Target {
+    HostGraph g;
+    std::vector<uint32_t> dlab;                  // dense label id per node
+    std::vector<uint32_t> label_keys;            // dense id -> raw label
+    std::vector<std::vector<uint32_t>> by_label; // dense id -> nodes
+    uint32_t W = 0;                              // 64-bit words per bitset row
+    uint32_t max_deg = 0;
+    // device
+    uint32_t *d_col = nullptr;
+    NodeRec *d_node = nullptr;
+    uint64_t *d_adj = nullptr;                   // n * W, or null when too large
+    uint64_t dev_bytes = 0;
+};
+
+struct Pattern {
+    HostGraph g;
+};
+
+// Search plan of one (pattern, target, mode, labelled) instance.
+struct Plan {
+    uint32_t k = 0, n = 0, W = 0;
+    int mode = SGE_RI;
+    bool labelled = true;
+    bool empty = false;        // a domain became empty: no match, nothing to search
+    uint32_t order[KMAX];      // position -> pattern node
+    int32_t parent[KMAX];      // position -> earlier position or -1
+    uint64_t back[KMAX];       // earlier adjacent positions other than the parent
+    uint32_t plabel[KMAX];     // dense target label id, LABEL_ANY or LABEL_NONE
+    uint32_t pdeg[KMAX];
+    std::vector<uint64_t> dom_node;   // RI-DS: k * W final domains by pattern node
+    std::vector<uint32_t> lists;      // candidate lists of parentless positions
+    uint32_t list_off[KMAX], list_len[KMAX];
+};
+
+// Build the plan.  When want_pos_bitsets is set, `pos_bits` receives k * W
+// words by position: the domain (RI-DS) or the label/degree-compatible set
+// (RI), as the dense search reads them.
+void build_plan(const Target &t, const HostGraph &p, int mode, bool labelled, uint32_t root_lo, uint32_t root_hi,
+                Plan &plan, bool want_pos_bitsets, std::vector<uint64_t> &pos_bits);
+
+// Dense label ids of a target (fills dlab, label_keys, by_label, W, max_deg).
+void index_target(Target &t);
+
+// ------------------------------------------------------------ device structs
+// Everything one instance of the search needs, as the kernels read it.
+struct DevPlan {
+    uint32_t k, W, n, use_dom;
+    uint32_t labelled, pad0, pad1, pad2;
+    int32_t parent[KMAX];
+    uint64_t back[KMAX];
+    uint32_t plabel[KMAX];
+    uint32_t pdeg[KMAX];
+    uint32_t order[KMAX];
+    uint32_t list_off[KMAX];
+    uint32_t list_len[KMAX];
+};
+
+struct InstDesc {
+    const uint32_t *col;      // target CSR column array
+    const NodeRec *node;      // target node records
+    const uint64_t *adj;      // target adjacency bitsets (n*W) or null
+    const DevPlan *plan;
+    const uint64_t *bits;     // k*W by position: domains (CSR RI-DS) or dense-mode sets, or null
+    const uint32_t *lists;    // candidate lists of parentless positions
+    uint32_t *rows;           // output rows or null
+    unsigned long long cap_rows;
+    uint32_t nchunks;         // root chunks of this instance
+    uint32_t chunk;           // root candidates per chunk
+    uint32_t nroot;           // candidates of position 0
+    uint32_t pad;
+};
+
+// Per-instance device counters.
+struct InstCounters {
+    unsigned long long matches, states, candidates, steals, row_next, pad0, pad1, pad2;
+};
+
+// Global scheduling words of one launch.
+struct Sched {
+    unsigned int chunk_next;   // next root chunk (flattened over instances)
+    unsigned int work;         // outstanding tasks: queued + in progress
+    unsigned int q_tail, q_head, q_avail, q_free;
+    unsigned int idle;         // units without a task
+    unsigned int abort;        // set when a state cap is exceeded
+    unsigned long long total_states;
+    unsigned long long state_cap;  // 0 = none (applies per instance via counters)
+    unsigned int pad[4];
+};
+
+// One queued task: instance, prefix length L, prefix mapping M[0..L-1] and the
+// candidate range [lo, hi) of position L (hi = 0xFFFFFFFF: the whole list).
+struct QTask {
+    unsigned int seq;
+    unsigned int inst, L, lo, hi, pad[3];
+    unsigned int M[KMAX];
+};
+
+struct LaunchCfg {
+    int lanes = 16;           // lanes per search unit
+    int dense = 0;            // dense-bitset kernel
+    int donate = 1;
+    uint32_t kmax = 0, nmax = 0, wmax = 0;
+    int blocks = 0;           // 0 = fill the device
+    int used_bitset = 1;
+};
+
+// Device-side work state of a context (allocated once, reused per launch).
+struct DevWork {
+    Sched *sched = nullptr;
+    QTask *queue = nullptr;
+    unsigned int *chunk_prefix = nullptr;  // per instance: exclusive prefix of chunks (ninst+1)
+    size_t chunk_prefix_cap = 0;
+    InstDesc *inst = nullptr;
+    size_t inst_cap = 0;
+    InstCounters *ctr = nullptr;
+    size_t ctr_cap = 0;
+};
+
+// Launch one persistent search over `ninst` instances (already on the device).
+// Returns a HIP error code.
+hipError_t launch_search(const LaunchCfg &cfg, DevWork &w, uint32_t ninst, uint64_t state_cap, hipStream_t s,
+                         int num_cus, size_t lds_per_cu);
+// Shared memory a block of the search kernel needs.
+size_t search_lds_bytes(const LaunchCfg &cfg);
+// Clear the scheduling words of a launch (a fill kernel; usable in a captured graph).
+hipError_t launch_reset(DevWork &w, uint32_t ninst, hipStream_t s);
+
+}  // namespace sge

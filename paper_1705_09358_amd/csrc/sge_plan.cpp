@@ -1,0 +1,220 @@
+// Host preparation of one search: RI-DS domains (Section 4.1), forward
+// checking (Section 4.2.2), the constraint-first order with its domain-size
+// tie-break (Section "RI" ordering; Section 4.2.1), parents and back-edges.
+//
+// Pattern neighbourhoods are 64-bit masks (k <= 64); domains are bitsets of
+// ceil(n/64) words.  Arc-consistency is evaluated in its support form: v stays
+// in D(u) iff for every pattern neighbour w of u, v is a target neighbour of
+// some member of D(w) (the graph is undirected), i.e. v lies in the union of
+// the target rows of D(w).  Rounds recompute every support set from the
+// current domains until nothing changes, which reaches the same greatest
+// arc-consistent domains as revising one value at a time.
+#include <algorithm>
+#include <cstring>
+
+#include "sge_internal.h"
+
+namespace sge {
+
+static inline uint32_t popcount_row(const uint64_t *r, uint32_t W) {
+    uint32_t c = 0;
+    for (uint32_t i = 0; i < W; i++) c += (uint32_t)__builtin_popcountll(r[i]);
+    return c;
+}
+
+static inline bool test_bit(const uint64_t *r, uint32_t v) { return (r[v >> 6] >> (v & 63)) & 1; }
+
+void build_plan(const Target &t, const HostGraph &p, int mode, bool labelled, uint32_t root_lo, uint32_t root_hi,
+                Plan &pl, bool want_pos_bits, std::vector<uint64_t> &pos_bits) {
+    const HostGraph &tg = t.g;
+    const uint32_t k = p.n, n = tg.n, W = t.W;
+    pl.k = k;
+    pl.n = n;
+    pl.W = W;
+    pl.mode = mode;
+    pl.labelled = labelled;
+    pl.empty = false;
+    pl.dom_node.clear();
+    pl.lists.clear();
+
+    // pattern node data: neighbourhood mask, degree, target label id
+    uint64_t nb[KMAX];
+    uint32_t deg[KMAX], lab[KMAX];
+    for (uint32_t u = 0; u < k; u++) {
+        nb[u] = 0;
+        for (uint32_t e = p.rp[u]; e < p.rp[u + 1]; e++) nb[u] |= 1ull << p.col[e];
+        deg[u] = p.rp[u + 1] - p.rp[u];
+        if (!labelled) {
+            lab[u] = LABEL_ANY;
+        } else {
+            lab[u] = LABEL_NONE;
+            for (uint32_t id = 0; id < t.label_keys.size(); id++)
+                if (t.label_keys[id] == p.lab[u]) { lab[u] = id; break; }
+        }
+    }
+    auto tdeg = [&](uint32_t v) { return tg.rp[v + 1] - tg.rp[v]; };
+    // nodes of V_t passing the label and degree rules for pattern node u
+    auto compat_nodes = [&](uint32_t u, auto &&fn) {
+        if (lab[u] == LABEL_NONE) return;
+        if (lab[u] == LABEL_ANY) {
+            for (uint32_t v = 0; v < n; v++)
+                if (tdeg(v) >= deg[u]) fn(v);
+        } else {
+            for (uint32_t v : t.by_label[lab[u]])
+                if (tdeg(v) >= deg[u]) fn(v);
+        }
+    };
+
+    const bool use_dom = mode != SGE_RI;
+    std::vector<uint64_t> &D = pl.dom_node;
+    uint32_t dsize[KMAX] = {0};
+    if (use_dom) {
+        D.assign((size_t)k * W, 0);
+        for (uint32_t u = 0; u < k; u++) compat_nodes(u, [&](uint32_t v) { D[(size_t)u * W + (v >> 6)] |= 1ull << (v & 63); });
+        // arc-consistency, support form, to the fixpoint
+        std::vector<uint64_t> S((size_t)k * W);
+        for (bool changed = true; changed;) {
+            changed = false;
+            std::fill(S.begin(), S.end(), 0);
+            for (uint32_t w = 0; w < k; w++) {
+                if (!nb[w]) continue;  // no pattern node has w as a neighbour
+                uint64_t *s = &S[(size_t)w * W];
+                const uint64_t *d = &D[(size_t)w * W];
+                for (uint32_t i = 0; i < W; i++) {
+                    for (uint64_t bits = d[i]; bits; bits &= bits - 1) {
+                        uint32_t x = i * 64 + (uint32_t)__builtin_ctzll(bits);
+                        for (uint32_t e = tg.rp[x]; e < tg.rp[x + 1]; e++) {
+                            uint32_t y = tg.col[e];
+                            s[y >> 6] |= 1ull << (y & 63);
+                        }
+                    }
+                }
+            }
+            for (uint32_t u = 0; u < k; u++) {
+                uint64_t *d = &D[(size_t)u * W];
+                for (uint64_t m = nb[u]; m; m &= m - 1) {
+                    const uint64_t *s = &S[(size_t)__builtin_ctzll(m) * W];
+                    for (uint32_t i = 0; i < W; i++) {
+                        uint64_t x = d[i] & s[i];
+                        if (x != d[i]) { d[i] = x; changed = true; }
+                    }
+                }
+            }
+        }
+        for (uint32_t u = 0; u < k; u++) {
+            dsize[u] = popcount_row(&D[(size_t)u * W], W);
+            if (!dsize[u]) pl.empty = true;
+        }
+        if (!pl.empty && mode == SGE_RIDS_SI_FC) {
+            // forward checking: a singleton's node leaves every other domain,
+            // repeated for singletons this creates
+            uint64_t done = 0;
+            for (bool progress = true; progress && !pl.empty;) {
+                progress = false;
+                for (uint32_t u = 0; u < k && !pl.empty; u++) {
+                    if (((done >> u) & 1) || dsize[u] != 1) continue;
+                    done |= 1ull << u;
+                    progress = true;
+                    const uint64_t *du = &D[(size_t)u * W];
+                    uint32_t word = 0;
+                    while (!du[word]) word++;
+                    uint64_t bit = du[word];
+                    for (uint32_t w = 0; w < k; w++) {
+                        if (w == u) continue;
+                        uint64_t &x = D[(size_t)w * W + word];
+                        if (x & bit) {
+                            x &= ~bit;
+                            if (--dsize[w] == 0) pl.empty = true;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (pl.empty) return;
+
+    // constraint-first order
+    const bool use_si = mode == SGE_RIDS_SI || mode == SGE_RIDS_SI_FC;
+    uint64_t placed = 0;
+    uint32_t len = 0;
+    if (use_dom)
+        for (uint32_t u = 0; u < k; u++)
+            if (dsize[u] == 1) { pl.order[len++] = u; placed |= 1ull << u; }
+    while (len < k) {
+        int best = -1;
+        uint32_t bwm = 0, bwn = 0, bdeg = 0, bdom = 0;
+        for (uint32_t u = 0; u < k; u++) {
+            if ((placed >> u) & 1) continue;
+            uint32_t wm = (uint32_t)__builtin_popcountll(nb[u] & placed);
+            uint32_t wn = 0;
+            for (uint64_t m = placed; m; m &= m - 1) {
+                uint32_t w = (uint32_t)__builtin_ctzll(m);
+                if (nb[u] & nb[w] & ~placed) wn++;
+            }
+            bool take;
+            if (best < 0) take = true;
+            else if (wm != bwm) take = wm > bwm;
+            else if (wn != bwn) take = wn > bwn;
+            else if (deg[u] != bdeg) take = deg[u] > bdeg;
+            else take = use_si && dsize[u] < bdom;
+            if (take) { best = (int)u; bwm = wm; bwn = wn; bdeg = deg[u]; bdom = dsize[u]; }
+        }
+        pl.order[len++] = (uint32_t)best;
+        placed |= 1ull << best;
+    }
+
+    uint32_t pos_of[KMAX];
+    for (uint32_t i = 0; i < k; i++) pos_of[pl.order[i]] = i;
+    for (uint32_t i = 0; i < k; i++) {
+        uint32_t u = pl.order[i];
+        uint64_t earlier = 0;
+        for (uint64_t m = nb[u]; m; m &= m - 1) {
+            uint32_t j = pos_of[__builtin_ctzll(m)];
+            if (j < i) earlier |= 1ull << j;
+        }
+        pl.parent[i] = earlier ? (int32_t)__builtin_ctzll(earlier) : -1;
+        pl.back[i] = earlier ? (earlier & (earlier - 1)) : 0;
+        pl.plabel[i] = lab[u];
+        pl.pdeg[i] = deg[u];
+        pl.list_off[i] = pl.list_len[i] = 0;
+        if (pl.parent[i] >= 0) continue;
+        // parentless position: candidates are V_t (RI) or D(u) (RI-DS), here
+        // pre-filtered by the label and degree rules, which every candidate
+        // must pass anyway; the first position is limited to [root_lo, root_hi)
+        uint32_t lo = i == 0 ? root_lo : 0, hi = i == 0 ? root_hi : 0xFFFFFFFFu;
+        pl.list_off[i] = (uint32_t)pl.lists.size();
+        if (use_dom) {
+            const uint64_t *d = &D[(size_t)u * W];
+            for (uint32_t w = 0; w < W; w++)
+                for (uint64_t bits = d[w]; bits; bits &= bits - 1) {
+                    uint32_t v = w * 64 + (uint32_t)__builtin_ctzll(bits);
+                    if (v >= lo && v < hi) pl.lists.push_back(v);
+                }
+        } else {
+            std::vector<uint32_t> tmp;
+            compat_nodes(u, [&](uint32_t v) { if (v >= lo && v < hi) tmp.push_back(v); });
+            std::sort(tmp.begin(), tmp.end());
+            pl.lists.insert(pl.lists.end(), tmp.begin(), tmp.end());
+        }
+        pl.list_len[i] = (uint32_t)pl.lists.size() - pl.list_off[i];
+    }
+
+    if (want_pos_bits) {
+        pos_bits.assign((size_t)k * W, 0);
+        for (uint32_t i = 0; i < k; i++) {
+            uint64_t *dst = &pos_bits[(size_t)i * W];
+            uint32_t u = pl.order[i];
+            if (use_dom) {
+                std::memcpy(dst, &D[(size_t)u * W], W * sizeof(uint64_t));
+            } else {
+                compat_nodes(u, [&](uint32_t v) { dst[v >> 6] |= 1ull << (v & 63); });
+            }
+            if (i == 0 && (root_lo > 0 || root_hi < n)) {
+                for (uint32_t v = 0; v < n; v++)
+                    if (v < root_lo || v >= root_hi) dst[v >> 6] &= ~(1ull << (v & 63));
+            }
+        }
+    }
+}
+
+}  // namespace sge

@@ -1,0 +1,559 @@
+// Persistent depth-first search kernels for RI / RI-DS subgraph enumeration on
+// gfx950.
+//
+// Search unit.  A unit is a group of G lanes of a 64-lane wavefront (G = 8,
+// 16, 32 or 64); a wave holds 64/G units that advance in lock-step through
+// one loop, each on its own subtree.  A unit owns, in LDS, the mapping M of
+// the current prefix (by order position), one frame per position and a small
+// stack of accepted-but-unexplored candidates.  This is the state space of
+// Section 2.2.1 traversed depth-first, with RI's candidate generation (the
+// target neighbours of the mapped parent; all nodes, or the domain, for a
+// node without a parent) and pruning rules in the paper's order (unused,
+// label, degree, edges to mapped nodes), plus the RI-DS domain test first
+// (Section 4.1).
+//
+// One step of a unit: pop exhausted frames; if the current frame has an
+// accepted candidate left, map it and open the next position's frame; then
+// evaluate the next G candidates of the current frame, one per lane, and push
+// the accepted ones (at the last position, count and emit them instead).
+// States are counted when a candidate is pushed (or, at the last position,
+// accepted), so a candidate that did not fit in the stack is evaluated again
+// later without being counted twice.
+//
+// Load balance.  Root candidates (position 0) are handed out in chunks from
+// an atomic counter (the paper's initial distribution, Section 3.3; chunks
+// play the role of task groups, Section 3.4).  Busy units donate work to a
+// global queue when units are idle: the untried remainder of their shallowest
+// open frame, or one accepted candidate of it -- near the root, as in the
+// paper's stealing from the back of a deque (Section 3.2).  A queued task
+// carries its prefix mapping, so only stolen work copies a mapping.
+// Termination: `work` counts queued plus running tasks; it reaches zero only
+// when no unit holds or can create work (replacing the token ring of
+// Section 3.5).
+#include <hip/hip_runtime.h>
+
+#include "sge_internal.h"
+
+namespace sge {
+
+namespace {
+
+struct SearchArgs {
+    const InstDesc *inst;
+    const unsigned *chunk_prefix;  // ninst + 1 exclusive prefix of root chunks
+    InstCounters *ctr;
+    Sched *sched;
+    QTask *queue;
+    unsigned ninst;
+    unsigned kmax, E, UW, unit_words;
+    int donate;
+    unsigned long long state_cap;
+};
+
+constexpr unsigned FULL_RANGE = 0xFFFFFFFFu;
+constexpr unsigned NO_TASK = 0xFFFFFFFFu;
+
+__device__ __forceinline__ unsigned ld_rlx(const unsigned *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned ld_acq(const unsigned *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel(unsigned *p, unsigned v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned fadd(unsigned *p, unsigned v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long fadd64(unsigned long long *p, unsigned long long v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool cas_dec_if_pos(unsigned *p) {
+    unsigned v = ld_rlx(p);
+    while (v > 0) {
+        if (__hip_atomic_compare_exchange_strong(p, &v, v - 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            return true;
+    }
+    return false;
+}
+
+// Orders LDS accesses between lanes of one wavefront (no instruction is
+// emitted beyond the compiler barrier: a wave's LDS operations execute in order).
+#define WAVE_SYNC()                                               \
+    do {                                                          \
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");    \
+        __builtin_amdgcn_wave_barrier();                          \
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");    \
+    } while (0)
+
+template <int G>
+__device__ __forceinline__ unsigned long long group_mask(unsigned long long ballot, int gbase) {
+    if constexpr (G == 64) return ballot;
+    else return (ballot >> gbase) & ((1ull << G) - 1);
+}
+
+// Per-unit LDS arrays.
+struct UnitLds {
+    unsigned *M, *MB, *MD;        // mapping by position, row start and degree of M[i]
+    unsigned *cur, *end, *lb;     // frame: next candidate index, list length, list start
+    unsigned *eb, *dn;            // frame: first stack entry, entries given away from the bottom
+    unsigned *ev, *ebg, *edg;     // stack of accepted candidates: node, row start, degree
+    unsigned *used;               // bitset of mapped target nodes
+    unsigned *misc;               // group broadcast scratch
+};
+
+__device__ __forceinline__ UnitLds carve(unsigned *base, unsigned kmax, unsigned E, unsigned UW) {
+    UnitLds u;
+    u.M = base;
+    u.MB = u.M + kmax;
+    u.MD = u.MB + kmax;
+    u.cur = u.MD + kmax;
+    u.end = u.cur + kmax;
+    u.lb = u.end + kmax;
+    u.eb = u.lb + kmax;
+    u.dn = u.eb + kmax;
+    u.ev = u.dn + kmax;
+    u.ebg = u.ev + E;
+    u.edg = u.ebg + E;
+    u.used = u.edg + E;
+    u.misc = u.used + UW;
+    return u;
+}
+
+__device__ __forceinline__ bool used_test(const unsigned *used, unsigned v) { return (used[v >> 5] >> (v & 31)) & 1u; }
+
+// is v a target neighbour of node a (row [b, b+deg))
+__device__ __forceinline__ bool adjacent(const InstDesc &d, unsigned W, unsigned a, unsigned b, unsigned deg,
+                                         unsigned v) {
+    if (d.adj) return (d.adj[(size_t)a * W + (v >> 6)] >> (v & 63)) & 1ull;
+    unsigned lo = b, hi = b + deg;
+    while (lo < hi) {
+        unsigned mid = (lo + hi) >> 1;
+        unsigned x = d.col[mid];
+        if (x < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < b + deg && d.col[lo] == v;
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) search_csr(SearchArgs a) {
+    extern __shared__ unsigned lds[];
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (G - 1);
+    const int gbase = lane & ~(G - 1);
+    const int unit = threadIdx.x / G;
+    UnitLds L = carve(lds + (size_t)unit * a.unit_words, a.kmax, a.E, a.UW);
+    for (unsigned i = gl; i < a.UW; i += G) L.used[i] = 0;
+
+    Sched *S = a.sched;
+    const unsigned nchunks = a.chunk_prefix[a.ninst];
+
+    // unit state (identical in the G lanes of a unit)
+    unsigned inst = NO_TASK, cinst = NO_TASK, lvl = 0, base = 0, etop = 0, k = 0, W = 0;
+    InstDesc d{};
+    const DevPlan *P = nullptr;
+    unsigned long long c_states = 0, c_matches = 0, c_cands = 0, c_steals = 0;
+    bool finished = false, roots_done = false, idle_counted = false;
+    unsigned iter = 0;
+    bool donate_hint = false;
+
+    auto flush = [&]() {
+        if (cinst != NO_TASK && gl == 0) {
+            InstCounters *c = a.ctr + cinst;
+            if (c_matches) fadd64(&c->matches, c_matches);
+            if (c_cands) fadd64(&c->candidates, c_cands);
+            if (c_steals) fadd64(&c->steals, c_steals);
+            if (c_states) {
+                unsigned long long before = fadd64(&c->states, c_states);
+                if (a.state_cap && before + c_states > a.state_cap)
+                    __hip_atomic_store(&c->pad0, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        c_states = c_matches = c_cands = c_steals = 0;
+    };
+    auto inst_aborted = [&](unsigned i) -> bool {
+        unsigned long long f = 0;
+        if (gl == 0) f = __hip_atomic_load(&a.ctr[i].pad0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return __shfl(f, gbase) != 0;
+    };
+
+    // open the frame of position `pos` (lists follow the mapped parent)
+    auto open_frame = [&](unsigned pos, unsigned lo, unsigned hi) {
+        int p = P->parent[pos];
+        unsigned start, len;
+        if (p >= 0) { start = L.MB[p]; len = L.MD[p]; }
+        else { start = P->list_off[pos]; len = P->list_len[pos]; }
+        unsigned e = (hi == FULL_RANGE || hi > len) ? len : hi;
+        L.cur[pos] = lo;
+        L.end[pos] = e;
+        L.lb[pos] = start;
+        L.eb[pos] = etop;
+        L.dn[pos] = 0;
+    };
+
+    while (true) {
+        iter++;
+        // ------------------------------------------------ task acquisition
+        bool want = (inst == NO_TASK) && !finished;
+        unsigned long long want_b = __ballot(want);
+        bool wave_busy = __ballot(inst != NO_TASK) != 0;
+        if (want_b && (!wave_busy || (iter & 7) == 0)) {
+            for (int g = 0; g < 64 / G; g++) {
+                if (!(want && (lane / G) == g)) continue;
+                // leader: queue first, then a root chunk
+                unsigned kind = 0, val = 0;
+                if (gl == 0) {
+                    if (cas_dec_if_pos(&S->q_avail)) {
+                        unsigned t = fadd(&S->q_head, 1);
+                        unsigned slot = t % QUEUE_SLOTS;
+                        while (ld_acq(&a.queue[slot].seq) != 2 * t + 1) __builtin_amdgcn_s_sleep(1);
+                        kind = 1;
+                        val = t;
+                    } else if (!roots_done) {
+                        fadd(&S->work, 1);
+                        unsigned c = fadd(&S->chunk_next, 1);
+                        if (c < nchunks) { kind = 2; val = c; }
+                        else { fadd(&S->work, (unsigned)-1); roots_done = true; }
+                    }
+                }
+                kind = __shfl(kind, gbase);
+                val = __shfl(val, gbase);
+                roots_done = __shfl((int)roots_done, gbase) != 0;
+                unsigned ti = 0, tL = 0, tlo = 0, thi = 0;
+                if (kind == 1) {
+                    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+                    QTask *q = a.queue + (val % QUEUE_SLOTS);
+                    ti = q->inst; tL = q->L; tlo = q->lo; thi = q->hi;
+                    for (unsigned i = gl; i < tL; i += G) L.M[i] = q->M[i];
+                    __atomic_thread_fence(__ATOMIC_RELEASE);
+                    if (gl == 0) {
+                        st_rel(&q->seq, 2 * (val + QUEUE_SLOTS));
+                        fadd(&S->q_free, 1);
+                    }
+                } else if (kind == 2) {
+                    unsigned lo = 0, hi = a.ninst;   // largest i with prefix[i] <= val
+                    if (gl == 0) {
+                        while (hi - lo > 1) {
+                            unsigned mid = (lo + hi) >> 1;
+                            if (a.chunk_prefix[mid] <= val) lo = mid;
+                            else hi = mid;
+                        }
+                    }
+                    ti = __shfl(lo, gbase);
+                    const InstDesc &dd = a.inst[ti];
+                    tL = 0;
+                    tlo = (val - a.chunk_prefix[ti]) * dd.chunk;
+                    thi = min(tlo + dd.chunk, dd.nroot);
+                }
+                if (kind == 0) {
+                    if (gl == 0 && !idle_counted) fadd(&S->idle, 1);
+                    idle_counted = true;
+                    if (roots_done) {
+                        unsigned w = 0;
+                        if (gl == 0) w = ld_acq(&S->work);
+                        if (__shfl(w, gbase) == 0) finished = true;
+                    }
+                    continue;
+                }
+                if (idle_counted && gl == 0) fadd(&S->idle, (unsigned)-1);
+                idle_counted = false;
+                // start the task
+                if (ti != cinst) {
+                    flush();
+                    cinst = ti;
+                    d = a.inst[ti];
+                    P = d.plan;
+                    k = P->k;
+                    W = P->W;
+                }
+                inst = ti;
+                if (kind == 1) c_steals++;
+                if (inst_aborted(inst)) {
+                    // capped instance: drop the task
+                    if (gl == 0) fadd(&S->work, (unsigned)-1);
+                    inst = NO_TASK;
+                    continue;
+                }
+                etop = 0;
+                for (unsigned i = gl; i < tL; i += G) {
+                    unsigned v = L.M[i];
+                    NodeRec r = d.node[v];
+                    L.MB[i] = r.begin;
+                    L.MD[i] = r.deg;
+                    atomicOr(&L.used[v >> 5], 1u << (v & 31));
+                }
+                WAVE_SYNC();
+                base = lvl = tL;
+                open_frame(tL, tlo, thi);
+            }
+        }
+        if (__ballot(!finished) == 0) break;
+        if (inst == NO_TASK) {
+            if (!wave_busy) __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
+
+        // ------------------------------------------------ one search step
+        WAVE_SYNC();
+        // pop exhausted frames
+        bool task_done = false;
+        while (true) {
+            if (etop > L.eb[lvl] + L.dn[lvl]) break;
+            etop = L.eb[lvl];   // reclaim entries given away from this frame
+            L.dn[lvl] = 0;
+            if (L.cur[lvl] < L.end[lvl]) break;
+            if (lvl == base) { task_done = true; break; }
+            lvl--;
+            unsigned v = L.M[lvl];
+            if (gl == 0) atomicAnd(&L.used[v >> 5], ~(1u << (v & 31)));
+        }
+        if (task_done) {
+            // release the prefix and the task
+            for (unsigned i = gl; i < base; i += G) {
+                unsigned v = L.M[i];
+                atomicAnd(&L.used[v >> 5], ~(1u << (v & 31)));
+            }
+            if (gl == 0) fadd(&S->work, (unsigned)-1);
+            if (c_states >= 4096) flush();
+            inst = NO_TASK;
+            continue;
+        }
+        // map the top accepted candidate and open the next frame
+        if (etop > L.eb[lvl] + L.dn[lvl]) {
+            etop--;
+            unsigned v = L.ev[etop];
+            L.M[lvl] = v;
+            L.MB[lvl] = L.ebg[etop];
+            L.MD[lvl] = L.edg[etop];
+            if (gl == 0) atomicOr(&L.used[v >> 5], 1u << (v & 31));
+            lvl++;
+            open_frame(lvl, 0, FULL_RANGE);
+        }
+        // evaluate up to G candidates of the current frame
+        {
+            const unsigned c0 = L.cur[lvl], e = L.end[lvl], lb = L.lb[lvl];
+            const unsigned idx = c0 + gl;
+            bool ok = idx < e;
+            const bool has_parent = P->parent[lvl] >= 0;
+            unsigned v = 0;
+            NodeRec r{0, 0, 0, 0};
+            if (ok) {
+                v = has_parent ? d.col[lb + idx] : d.lists[lb + idx];
+                r = d.node[v];
+            }
+            if (ok && d.bits) ok = (d.bits[(size_t)lvl * W + (v >> 6)] >> (v & 63)) & 1ull;
+            if (ok) ok = !used_test(L.used, v);
+            const unsigned pl = P->plabel[lvl];
+            if (ok && pl != LABEL_ANY) ok = r.label == pl;
+            if (ok) ok = r.deg >= P->pdeg[lvl];
+            unsigned long long bm = P->back[lvl];
+            while (bm) {
+                unsigned j = (unsigned)__builtin_ctzll(bm);
+                bm &= bm - 1;
+                if (ok) ok = adjacent(d, W, L.M[j], L.MB[j], L.MD[j], v);
+            }
+            c_cands += min((unsigned)G, e - c0);
+            unsigned long long acc = group_mask<G>(__ballot(ok), gbase);
+            unsigned cnt = (unsigned)__popcll(acc);
+            if (lvl + 1 == k) {
+                c_states += cnt;
+                c_matches += cnt;
+                if (d.rows && ok) {
+                    unsigned long long slot = atomicAdd(&a.ctr[inst].row_next, 1ull);
+                    if (slot < d.cap_rows) {
+                        uint32_t *row = d.rows + slot * k;
+                        for (unsigned i = 0; i + 1 < k; i++) row[P->order[i]] = L.M[i];
+                        row[P->order[k - 1]] = v;
+                    }
+                }
+                L.cur[lvl] = c0 + G;
+            } else {
+                int room = (int)a.E - (int)etop - (int)(k - 2 - lvl);
+                unsigned take = cnt;
+                unsigned long long keep = acc;
+                unsigned ncur = c0 + G;
+                if ((int)take > room) {
+                    take = (unsigned)room;
+                    unsigned long long m = acc;
+                    for (unsigned i = 0; i < take; i++) m &= m - 1;
+                    keep = acc & ~m;                       // the first `take` accepted lanes
+                    ncur = c0 + (63u - (unsigned)__clzll(keep)) + 1;
+                }
+                if ((keep >> gl) & 1ull) {
+                    unsigned rank = (unsigned)__popcll(keep & ((1ull << gl) - 1));
+                    L.ev[etop + rank] = v;
+                    L.ebg[etop + rank] = r.begin;
+                    L.edg[etop + rank] = r.deg;
+                }
+                etop += take;
+                c_states += take;
+                L.cur[lvl] = ncur;
+            }
+        }
+
+        // counters: flush now and then so a state cap takes effect
+        if (c_states >= 8192) {
+            flush();
+            if (a.state_cap && inst_aborted(inst)) {
+                WAVE_SYNC();
+                for (unsigned i = gl; i < lvl; i += G) {
+                    unsigned v = L.M[i];
+                    atomicAnd(&L.used[v >> 5], ~(1u << (v & 31)));
+                }
+                if (gl == 0) fadd(&S->work, (unsigned)-1);
+                inst = NO_TASK;
+                etop = 0;
+                continue;
+            }
+        }
+
+        // ------------------------------------------------ donation
+        if (a.donate && (iter & 15) == 0) {
+            unsigned hint = 0;
+            if (lane == 0) {
+                unsigned idle = ld_rlx(&S->idle), av = ld_rlx(&S->q_avail), fr = ld_rlx(&S->q_free);
+                hint = (idle > av && fr > 64) ? 1u : 0u;
+            }
+            donate_hint = __shfl(hint, 0) != 0;
+        }
+        if (donate_hint && (iter & 15) == 0) {
+            for (int g = 0; g < 64 / G; g++) {
+                if (!((lane / G) == g && inst != NO_TASK)) continue;
+                // shallowest frame with untried candidates or a spare accepted one
+                unsigned f = base, kind = 0;
+                for (; f <= lvl; f++) {
+                    if (L.cur[f] < L.end[f]) { kind = 1; break; }
+                    unsigned top = f < lvl ? L.eb[f + 1] : etop;
+                    unsigned live = top - (L.eb[f] + L.dn[f]);
+                    if (live > (f == lvl ? 1u : 0u)) { kind = 2; break; }
+                }
+                if (!kind) continue;
+                unsigned t = 0, okr = 0;
+                if (gl == 0) {
+                    if (cas_dec_if_pos(&S->q_free)) {
+                        fadd(&S->work, 1);
+                        t = fadd(&S->q_tail, 1);
+                        while (ld_acq(&a.queue[t % QUEUE_SLOTS].seq) != 2 * t) __builtin_amdgcn_s_sleep(1);
+                        okr = 1;
+                    }
+                }
+                if (!__shfl(okr, gbase)) continue;
+                t = __shfl(t, gbase);
+                WAVE_SYNC();
+                QTask *q = a.queue + (t % QUEUE_SLOTS);
+                unsigned tL, tlo, thi, extra = 0;
+                if (kind == 1) {
+                    unsigned c = L.cur[f], e = L.end[f];
+                    unsigned mid = c + (e - c) / 2;
+                    tL = f; tlo = mid; thi = e;
+                    L.end[f] = mid;
+                } else {
+                    unsigned idx = L.eb[f] + L.dn[f];
+                    L.dn[f] = L.dn[f] + 1;
+                    extra = L.ev[idx];
+                    tL = f + 1; tlo = 0; thi = FULL_RANGE;
+                }
+                for (unsigned i = gl; i < f; i += G) q->M[i] = L.M[i];
+                if (kind == 2 && gl == 0) q->M[f] = extra;
+                if (gl == 0) { q->inst = inst; q->L = tL; q->lo = tlo; q->hi = thi; }
+                __atomic_thread_fence(__ATOMIC_RELEASE);
+                if (gl == 0) {
+                    st_rel(&q->seq, 2 * t + 1);
+                    fadd(&S->q_avail, 1);
+                }
+            }
+        }
+    }
+    flush();
+}
+
+__global__ void reset_kernel(Sched *s, InstCounters *c, unsigned ninst, QTask *q) {
+    unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned stride = gridDim.x * blockDim.x;
+    if (i == 0) {
+        s->chunk_next = 0;
+        s->work = 0;
+        s->q_tail = 0;
+        s->q_head = 0;
+        s->q_avail = 0;
+        s->q_free = QUEUE_SLOTS;
+        s->idle = 0;
+        s->abort = 0;
+        s->total_states = 0;
+        s->state_cap = 0;
+    }
+    for (unsigned j = i; j < ninst; j += stride) c[j] = InstCounters{0, 0, 0, 0, 0, 0, 0, 0};
+    for (unsigned j = i; j < QUEUE_SLOTS; j += stride) q[j].seq = 2 * j;
+}
+
+template <int G>
+hipError_t launch_csr(const SearchArgs &args, int blocks, int threads, size_t lds, hipStream_t s, int num_cus) {
+    if (blocks <= 0) {
+        int per_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_csr<G>, threads, lds);
+        if (e != hipSuccess) return e;
+        if (per_cu < 1) per_cu = 1;
+        blocks = per_cu * num_cus;
+    }
+    hipLaunchKernelGGL(search_csr<G>, dim3(blocks), dim3(threads), lds, s, args);
+    return hipGetLastError();
+}
+
+unsigned unit_words(const LaunchCfg &cfg) {
+    unsigned E = cfg.kmax + cfg.lanes;
+    unsigned UW = (cfg.nmax + 31) / 32;
+    return 8 * cfg.kmax + 3 * E + UW + 8;
+}
+
+// Largest block (256, 128 or 64 threads) whose units fit in 64 KiB of LDS.
+int block_threads(const LaunchCfg &cfg) {
+    size_t per_unit = (size_t)unit_words(cfg) * 4;
+    for (int t = 256; t >= 64; t /= 2)
+        if (per_unit * (t / cfg.lanes) <= 65536) return t;
+    return 0;
+}
+
+}  // namespace
+
+size_t search_lds_bytes(const LaunchCfg &cfg) {
+    int t = block_threads(cfg);
+    return (size_t)unit_words(cfg) * 4 * (size_t)((t ? t : 64) / cfg.lanes);
+}
+
+hipError_t launch_reset(DevWork &w, uint32_t ninst, hipStream_t s) {
+    hipLaunchKernelGGL(reset_kernel, dim3(64), dim3(256), 0, s, w.sched, w.ctr, ninst, w.queue);
+    return hipGetLastError();
+}
+
+hipError_t launch_search(const LaunchCfg &cfg, DevWork &w, uint32_t ninst, uint64_t state_cap, hipStream_t s,
+                         int num_cus, size_t lds_per_cu) {
+    SearchArgs a{};
+    a.inst = w.inst;
+    a.chunk_prefix = w.chunk_prefix;
+    a.ctr = w.ctr;
+    a.sched = w.sched;
+    a.queue = w.queue;
+    a.ninst = ninst;
+    a.kmax = cfg.kmax;
+    a.E = cfg.kmax + cfg.lanes;
+    a.UW = (cfg.nmax + 31) / 32;
+    a.unit_words = unit_words(cfg);
+    a.donate = cfg.donate;
+    a.state_cap = state_cap;
+    const int threads = block_threads(cfg);
+    if (!threads) return hipErrorInvalidValue;   // one unit's LDS does not fit
+    size_t lds = search_lds_bytes(cfg);
+    (void)lds_per_cu;
+    int blocks = cfg.blocks;
+    switch (cfg.lanes) {
+        case 8: return launch_csr<8>(a, blocks, threads, lds, s, num_cus);
+        case 16: return launch_csr<16>(a, blocks, threads, lds, s, num_cus);
+        case 32: return launch_csr<32>(a, blocks, threads, lds, s, num_cus);
+        case 64: return launch_csr<64>(a, blocks, threads, lds, s, num_cus);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace sge

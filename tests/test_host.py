@@ -1,0 +1,129 @@
+"""CPU tests of the library's host side: exported symbols, the host plan
+(order, parents, domains) against the oracle's, and input validation.
+No GPU is used."""
+from __future__ import annotations
+
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import graphs as G
+from paper_1705_09358_amd import sge, synth
+
+HEADER = __import__("os").path.join(__import__("os").path.dirname(__file__), "..", "include", "sge.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(sge_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    sge.lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", sge.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (sge_\w+)", out))
+    declared = set(_declared())
+    assert declared, "no declarations found"
+    assert declared <= exported, declared - exported
+    assert set(sge.EXPORTS) == declared
+    # nothing undeclared leaks out under the sge_ prefix
+    assert exported <= declared, exported - declared
+
+
+def _cmp_plan(P, T, mode, labelled, orc):
+    a = orc.plan(P, T, mode, labelled)
+    b = sge.plan_host(P, T, mode, labelled)
+    assert a["empty"] == b["empty"]
+    if a["empty"]:
+        return
+    assert a["order"].tolist() == b["order"].tolist()
+    assert a["parent"].tolist() == b["parent"].tolist()
+    if mode != 0 and P.n:
+        assert np.array_equal(a["domains"], b["domains"])
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_plan_matches_oracle_tiny(orc, seed):
+    g = np.random.default_rng(1000 + seed)
+    n = int(g.integers(2, 12))
+    k = int(g.integers(1, min(8, n) + 1))
+    nlab = int(g.integers(1, 4))
+    T = G.random_graph(g, n, float(g.uniform(0.2, 0.9)), nlab)
+    P = G.random_graph(g, k, float(g.uniform(0.2, 1.0)), nlab)
+    for mode in range(4):
+        for labelled in (False, True):
+            _cmp_plan(P, T, mode, labelled, orc)
+
+
+@pytest.mark.parametrize("j", range(0, 100, 9))
+def test_plan_matches_oracle_c1(orc, j):
+    inst = synth.c1_instance(j)
+    for mode in range(4):
+        _cmp_plan(inst.pattern, inst.target, mode, True, orc)
+
+
+@pytest.mark.parametrize("j", range(0, 100, 13))
+def test_plan_matches_oracle_c2(orc, j):
+    inst = synth.c2_instance(j)
+    for mode in range(4):
+        _cmp_plan(inst.pattern, inst.target, mode, True, orc)
+
+
+@pytest.mark.parametrize("j", [0, 3, 17])
+def test_plan_matches_oracle_c4(orc, j):
+    inst = synth.c4_instance(j)
+    for mode in (0, 3):
+        _cmp_plan(inst.pattern, inst.target, mode, True, orc)
+
+
+def test_plan_paper_orderings(orc):
+    # the hand-checked orderings of the oracle tests, through the library
+    P = G.from_edges(5, [(0, 1), (0, 2), (0, 4), (2, 4), (1, 3)])
+    assert sge.plan_host(P, G.complete(6), 0, False)["order"].tolist() == [0, 2, 4, 1, 3]
+    X, Y, Z = 0, 1, 2
+    T = G.from_edges(6, [(0, i) for i in range(1, 6)], [Z, X, X, X, Y, Y])
+    P = G.from_edges(3, [(0, 1), (1, 2)], [X, Z, Y])
+    assert sge.plan_host(P, T, 1, True)["order"].tolist() == [1, 0, 2]
+    assert sge.plan_host(P, T, 3, True)["order"].tolist() == [1, 2, 0]
+
+
+def test_plan_rejects_bad_graphs():
+    good = G.path(3)
+    loop = synth.Graph(2, np.array([0, 2, 3], np.uint32), np.array([0, 1, 0], np.uint32), np.zeros(2, np.uint32))
+    asym = synth.Graph(2, np.array([0, 1, 1], np.uint32), np.array([1], np.uint32), np.zeros(2, np.uint32))
+    oob = synth.Graph(2, np.array([0, 1, 2], np.uint32), np.array([5, 0], np.uint32), np.zeros(2, np.uint32))
+    for bad in (loop, asym, oob):
+        with pytest.raises(sge.SgeError):
+            sge.plan_host(good, bad, 0, False)
+        with pytest.raises(sge.SgeError):
+            sge.plan_host(bad, good, 0, False)
+    big = G.path(65)
+    with pytest.raises(sge.SgeError):
+        sge.plan_host(big, G.complete(70), 0, False)
+
+
+def test_plan_merges_duplicate_entries(orc):
+    T = G.cycle(5)
+    dup = synth.Graph(5, np.array([0, 3, 5, 7, 9, 12], np.uint32),
+                      np.array([1, 4, 1, 0, 2, 1, 3, 2, 4, 0, 3, 3], np.uint32), np.zeros(5, np.uint32))
+    a = sge.plan_host(G.path(3), T, 1, False)
+    b = sge.plan_host(G.path(3), dup, 1, False)
+    assert a["order"].tolist() == b["order"].tolist()
+    assert np.array_equal(a["domains"], b["domains"])
+
+
+def _has_gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-device error path")
+def test_create_without_device_fails_cleanly():
+    with pytest.raises(sge.SgeError) as e:
+        sge.Context(0)
+    assert e.value.code in (sge.E_DEVICE, sge.E_INVAL)

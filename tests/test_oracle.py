@@ -323,3 +323,19 @@ def test_row_capacity(orc):
     assert part["rows"].shape == (7, 3)
     fullset = {tuple(r) for r in full["rows"].tolist()}
     assert all(tuple(r) in fullset for r in part["rows"].tolist())
+
+
+def test_root_shards_partition_the_search(orc):
+    """Restricting the first node of the order to disjoint ranges of target ids
+    splits the search tree by its first level: counts add up to the whole."""
+    inst = synth.c2_instance(5)
+    full = orc.run(inst.pattern, inst.target, 0, True, rows=True)
+    parts = [orc.run(inst.pattern, inst.target, 0, True, rows=True, root_range=(lo, hi))
+             for lo, hi in [(0, 1000), (1000, 1001), (1001, 3000)]]
+    assert sum(p["matches"] for p in parts) == full["matches"]
+    assert sum(p["states"] for p in parts) == full["states"]
+    allrows = np.concatenate([p["rows"] for p in parts])
+    assert np.array_equal(_sorted(allrows), _sorted(full["rows"]))
+    order0 = orc.plan(inst.pattern, inst.target, 0, True)["order"][0]
+    for p, (lo, hi) in zip(parts, [(0, 1000), (1000, 1001), (1001, 3000)]):
+        assert all(lo <= r[order0] < hi for r in p["rows"])
