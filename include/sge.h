@@ -105,6 +105,10 @@ sge_status sge_set_mode(sge_ctx *ctx, int mode);
 /* cap = 0: no cap.  Otherwise a search whose states exceed cap stops with
  * SGE_E_ABORTED; "exceeds" is decided on the schedule-independent count. */
 sge_status sge_set_state_cap(sge_ctx *ctx, uint64_t cap);
+/* Every search launch ends by this wall-clock limit (ms; 0 = none; default
+ * 120000).  A launch that reaches it returns SGE_E_ABORTED with partial
+ * counters. */
+sge_status sge_set_time_limit(sge_ctx *ctx, uint64_t ms);
 /* Restrict the first pattern node of the order to target nodes in [lo, hi)
  * (a shard of the root candidates; lo = 0, hi = UINT32_MAX restores all).
  * Counters then cover that shard only. */

@@ -183,7 +183,8 @@ sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std
     hipError_t e;
     if ((e = c->d_blob.reserve(blob)) != hipSuccess) return hip_fail(c, e, "device plan buffer");
     if ((e = c->h_blob.reserve(blob)) != hipSuccess) return hip_fail(c, e, "pinned plan buffer");
-    if ((e = c->h_ctr.reserve(m * sizeof(InstCounters))) != hipSuccess) return hip_fail(c, e, "pinned counters");
+    const size_t ctr_bytes = align_up(m * sizeof(InstCounters), 64);
+    if ((e = c->h_ctr.reserve(ctr_bytes + sizeof(Sched))) != hipSuccess) return hip_fail(c, e, "pinned counters");
     char *hb = (char *)c->h_blob.p;
     char *db = (char *)c->d_blob.p;
 
@@ -248,50 +249,67 @@ sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std
     }
 
     hipStream_t s = c->stream;
-    auto enqueue = [&]() -> hipError_t {
+    // the search kernel is bracketed by ev0/ev1, so ms_search is kernel-only time
+    auto enqueue = [&](bool timed) -> hipError_t {
         hipError_t r;
         if ((r = hipMemcpyAsync(db, hb, blob, hipMemcpyHostToDevice, s)) != hipSuccess) return r;
         if ((r = launch_reset(w, m, s)) != hipSuccess) return r;
-        if ((r = launch_search(cfg, w, m, c->cap, s, c->num_cus, c->lds_per_cu)) != hipSuccess) return r;
-        return hipMemcpyAsync(c->h_ctr.p, w.ctr, m * sizeof(InstCounters), hipMemcpyDeviceToHost, s);
+        if (timed && (r = hipEventRecord(c->ev0, s)) != hipSuccess) return r;
+        if ((r = launch_search(cfg, w, m, pref[m], c->cap, c->time_limit_ms, s, c->num_cus)) != hipSuccess) return r;
+        if (timed && (r = hipEventRecord(c->ev1, s)) != hipSuccess) return r;
+        if ((r = hipMemcpyAsync(c->h_ctr.p, w.ctr, m * sizeof(InstCounters), hipMemcpyDeviceToHost, s)) != hipSuccess)
+            return r;
+        return hipMemcpyAsync((char *)c->h_ctr.p + ctr_bytes, w.sched, sizeof(Sched), hipMemcpyDeviceToHost, s);
     };
     auto t1 = clk::now();
     ms_prep = std::chrono::duration<double, std::milli>(t1 - t0).count();
-    if ((e = hipEventRecord(c->ev0, s)) != hipSuccess) return hip_fail(c, e, "hipEventRecord");
     if (graph) {
+        // one graph: plan upload, scheduler reset, the persistent search, read-back
         hipGraph_t g = nullptr;
         hipGraphExec_t ge = nullptr;
         if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return hip_fail(c, e, "hipStreamBeginCapture");
-        hipError_t er = enqueue();
+        hipError_t er = enqueue(false);
         e = hipStreamEndCapture(s, &g);
-        if (er != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip_fail(c, er, "capture search"); }
-        if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
-        if ((e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0)) != hipSuccess) {
-            (void)hipGraphDestroy(g);
-            return hip_fail(c, e, "hipGraphInstantiate");
+        if (er != hipSuccess || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_fail(c, er != hipSuccess ? er : e, "capture search graph");
         }
-        e = hipGraphLaunch(ge, s);
-        (void)hipGraphExecDestroy(ge);
+        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+        // the executable graph owns the launch's kernel arguments: it is destroyed
+        // only after the stream has drained
+        if ((e = hipEventRecord(c->ev0, s)) == hipSuccess && (e = hipGraphLaunch(ge, s)) == hipSuccess)
+            e = hipEventRecord(c->ev1, s);
+        hipError_t es = hipStreamSynchronize(s);
+        (void)hipGraphExecDestroy(ge);
         if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+        if (es != hipSuccess) return hip_fail(c, es, "search");
     } else {
-        if ((e = enqueue()) != hipSuccess) return hip_fail(c, e, "search launch");
+        if ((e = enqueue(true)) != hipSuccess) return hip_fail(c, e, "search launch");
     }
-    if ((e = hipEventRecord(c->ev1, s)) != hipSuccess) return hip_fail(c, e, "hipEventRecord");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "search");
     float ms = 0;
     (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
-    ms_search = ms;
 
     const InstCounters *hc = (const InstCounters *)c->h_ctr.p;
+    const Sched *hs = (const Sched *)((char *)c->h_ctr.p + ctr_bytes);
+    if (hs->abort) c->err = "search stopped at the time limit; counters are partial";
+    // kernel time from the device clock (100 MHz): first block start to last wave exit
+    ms_search = hs->t_end > hs->t_start ? (double)(hs->t_end - hs->t_start) / 1e5 : (double)ms;
     for (uint32_t j = 0; j < m; j++) {
         InstanceOut &o = out[idx[j]];
         o.matches = hc[j].matches;
         o.states = hc[j].states;
         o.candidates = hc[j].candidates;
         o.steals = hc[j].steals;
-        if (c->cap && o.states > c->cap) o.status = SGE_E_ABORTED;
+        if (hs->abort) {
+            o.status = SGE_E_ABORTED;
+            o.timed_out = true;
+        } else if (c->cap && o.states > c->cap) {
+            o.status = SGE_E_ABORTED;
+        }
         else if (specs[idx[j]].rows && o.matches > specs[idx[j]].cap_rows) o.status = SGE_E_OVERFLOW;
     }
     return SGE_OK;
@@ -418,6 +436,12 @@ sge_status sge_set_state_cap(sge_ctx *c, uint64_t cap) {
     return SGE_OK;
 }
 
+sge_status sge_set_time_limit(sge_ctx *c, uint64_t ms) {
+    if (!c) return SGE_E_INVAL;
+    c->time_limit_ms = ms;
+    return SGE_OK;
+}
+
 sge_status sge_set_root_range(sge_ctx *c, uint32_t lo, uint32_t hi) {
     if (!c) return SGE_E_INVAL;
     if (lo > hi) return fail(c, SGE_E_INVAL, "root range lo > hi");
@@ -483,6 +507,7 @@ static sge_status single(sge_ctx *c, uint32_t target, uint32_t pattern, uint32_t
         hipError_t e = hipMemcpy(host_rows, s.rows, nr * k * 4, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(c, e, "copy rows");
     }
+    if (out[0].timed_out) return fail(c, SGE_E_ABORTED, "search stopped at the time limit; counters are partial");
     if (out[0].status == SGE_E_ABORTED) return fail(c, SGE_E_ABORTED, "state cap exceeded");
     if (rows && k && res->matches > cap_rows) return fail(c, SGE_E_OVERFLOW, "more matches than rows");
     return SGE_OK;

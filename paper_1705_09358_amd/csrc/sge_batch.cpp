@@ -84,7 +84,7 @@ sge_status sge_batch_run(sge_ctx *c, uint32_t njobs, const sge_job *jobs, sge_re
     sge_status st = run_instances(c, specs, out, mp, ms, true, policy);
     c->lanes = saved_lanes;
     if (st != SGE_OK) return st;
-    bool aborted = false;
+    bool aborted = false, timed_out = false;
     for (uint32_t i = 0; i < njobs; i++) {
         results[i].matches = out[i].matches;
         results[i].states = out[i].states;
@@ -93,7 +93,9 @@ sge_status sge_batch_run(sge_ctx *c, uint32_t njobs, const sge_job *jobs, sge_re
         results[i].ms_prep = mp;
         results[i].ms_search = ms;
         aborted |= out[i].status == SGE_E_ABORTED;
+        timed_out |= out[i].timed_out;
     }
+    if (timed_out) return fail(c, SGE_E_ABORTED, "batch stopped at the time limit; counters are partial");
     if (aborted) return fail(c, SGE_E_ABORTED, "state cap exceeded by at least one job");
     return SGE_OK;
 }

@@ -39,6 +39,7 @@ struct InstanceSpec {
 
 struct InstanceOut {
     sge_status status = SGE_OK;
+    bool timed_out = false;
     uint64_t matches = 0, states = 0, candidates = 0, steals = 0;
 };
 
@@ -56,6 +57,7 @@ struct sge_ctx {
     int labelled = 1;
     int mode = SGE_RI;
     uint64_t cap = 0;
+    uint64_t time_limit_ms = 120000;   // every search launch ends by this time
     uint32_t root_lo = 0, root_hi = 0xFFFFFFFFu;
     int lanes = 0, dense = -1, donate = 1;
     uint32_t root_chunk = 0;

@@ -112,16 +112,27 @@ struct InstCounters {
     unsigned long long matches, states, candidates, steals, row_next, pad0, pad1, pad2;
 };
 
-// Global scheduling words of one launch.
+// Global scheduling words of one launch.  Each word that many waves touch
+// sits on its own 128-byte line.
 struct Sched {
     unsigned int chunk_next;   // next root chunk (flattened over instances)
-    unsigned int work;         // outstanding tasks: queued + in progress
-    unsigned int q_tail, q_head, q_avail, q_free;
-    unsigned int idle;         // units without a task
-    unsigned int abort;        // set when a state cap is exceeded
-    unsigned long long total_states;
-    unsigned long long state_cap;  // 0 = none (applies per instance via counters)
-    unsigned int pad[4];
+    unsigned int p0[31];
+    unsigned int work;         // outstanding tasks: queued plus in progress
+    unsigned int p1[31];
+    unsigned int q_tail;       // producer tickets of the work queue
+    unsigned int p2[31];
+    unsigned int q_head;       // consumer tickets
+    unsigned int p3[31];
+    unsigned int q_avail;      // published, not yet taken
+    unsigned int p4[31];
+    unsigned int q_free;       // free slots
+    unsigned int p5[31];
+    unsigned int done;         // set once no task is queued, running or unclaimed
+    unsigned int abort;        // set when the launch's time limit is reached
+    unsigned int p6[30];
+    unsigned long long t_start;  // earliest block start (s_memrealtime, 100 MHz)
+    unsigned long long t_end;    // latest wave exit
+    unsigned long long p7[14];
 };
 
 // One queued task: instance, prefix length L, prefix mapping M[0..L-1] and the
@@ -155,8 +166,8 @@ struct DevWork {
 
 // Launch one persistent search over `ninst` instances (already on the device).
 // Returns a HIP error code.
-hipError_t launch_search(const LaunchCfg &cfg, DevWork &w, uint32_t ninst, uint64_t state_cap, hipStream_t s,
-                         int num_cus, size_t lds_per_cu);
+hipError_t launch_search(const LaunchCfg &cfg, DevWork &w, uint32_t ninst, uint32_t total_chunks,
+                         uint64_t state_cap, uint64_t time_limit_ms, hipStream_t s, int num_cus);
 // Shared memory a block of the search kernel needs.
 size_t search_lds_bytes(const LaunchCfg &cfg);
 // Clear the scheduling words of a launch (a fill kernel; usable in a captured graph).

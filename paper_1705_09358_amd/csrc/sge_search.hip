@@ -32,6 +32,8 @@
 // Section 3.5).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "sge_internal.h"
 
 namespace sge {
@@ -48,6 +50,7 @@ struct SearchArgs {
     unsigned kmax, E, UW, unit_words;
     int donate;
     unsigned long long state_cap;
+    unsigned long long limit_ticks;   // time limit in s_memrealtime ticks (100 MHz); 0 = none
 };
 
 constexpr unsigned FULL_RANGE = 0xFFFFFFFFu;
@@ -59,10 +62,16 @@ __device__ __forceinline__ unsigned ld_rlx(const unsigned *p) {
 __device__ __forceinline__ unsigned ld_acq(const unsigned *p) {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void st_rlx(unsigned *p, unsigned v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ void st_rel(unsigned *p, unsigned v) {
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ unsigned fadd(unsigned *p, unsigned v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned fadd_ar(unsigned *p, unsigned v) {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ unsigned long long fadd64(unsigned long long *p, unsigned long long v) {
@@ -71,11 +80,24 @@ __device__ __forceinline__ unsigned long long fadd64(unsigned long long *p, unsi
 __device__ __forceinline__ bool cas_dec_if_pos(unsigned *p) {
     unsigned v = ld_rlx(p);
     while (v > 0) {
-        if (__hip_atomic_compare_exchange_strong(p, &v, v - 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+        if (__hip_atomic_compare_exchange_strong(p, &v, v - 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT))
             return true;
     }
     return false;
+}
+__device__ __forceinline__ void fence_acq() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+__device__ __forceinline__ void fence_rel() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+
+// Termination.  `work` counts queued plus running tasks; a root chunk is
+// counted before it is claimed.  The unit whose decrement empties `work`
+// checks, in this order, that every root chunk has been claimed and that
+// `work` is still zero: a claim seen by the first load had already counted
+// itself, so a zero after it means no task is left anywhere.
+__device__ __forceinline__ void release_task(Sched *S, unsigned nchunks) {
+    if (fadd(&S->work, (unsigned)-1) == 1) {
+        if (ld_acq(&S->chunk_next) >= nchunks && ld_acq(&S->work) == 0) st_rel(&S->done, 1u);
+    }
 }
 
 // Orders LDS accesses between lanes of one wavefront (no instruction is
@@ -86,6 +108,8 @@ __device__ __forceinline__ bool cas_dec_if_pos(unsigned *p) {
         __builtin_amdgcn_wave_barrier();                          \
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");    \
     } while (0)
+
+__device__ __forceinline__ unsigned long long now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
 
 template <int G>
 __device__ __forceinline__ unsigned long long group_mask(unsigned long long ballot, int gbase) {
@@ -149,15 +173,23 @@ __global__ void __launch_bounds__(256) search_csr(SearchArgs a) {
 
     Sched *S = a.sched;
     const unsigned nchunks = a.chunk_prefix[a.ninst];
+    if (threadIdx.x == 0) atomicMin(&S->t_start, now_ticks());
+    if (nchunks == 0) {   // no root candidate anywhere: nothing to search
+        if (lane == 0) atomicMax(&S->t_end, now_ticks());
+        return;
+    }
 
     // unit state (identical in the G lanes of a unit)
     unsigned inst = NO_TASK, cinst = NO_TASK, lvl = 0, base = 0, etop = 0, k = 0, W = 0;
     InstDesc d{};
     const DevPlan *P = nullptr;
     unsigned long long c_states = 0, c_matches = 0, c_cands = 0, c_steals = 0;
-    bool finished = false, roots_done = false, idle_counted = false;
-    unsigned iter = 0;
+    bool roots_done = false;
+    unsigned since_donate = 0;     // steps since this unit's task began or it last gave work away
+    unsigned iter = 0, backoff = 0;
     bool donate_hint = false;
+    // every wave ends by the deadline, whatever the state of the search
+    const unsigned long long deadline = a.limit_ticks ? now_ticks() + a.limit_ticks : ~0ull;
 
     auto flush = [&]() {
         if (cinst != NO_TASK && gl == 0) {
@@ -178,7 +210,6 @@ __global__ void __launch_bounds__(256) search_csr(SearchArgs a) {
         if (gl == 0) f = __hip_atomic_load(&a.ctr[i].pad0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return __shfl(f, gbase) != 0;
     };
-
     // open the frame of position `pos` (lists follow the mapped parent)
     auto open_frame = [&](unsigned pos, unsigned lo, unsigned hi) {
         int p = P->parent[pos];
@@ -192,111 +223,147 @@ __global__ void __launch_bounds__(256) search_csr(SearchArgs a) {
         L.eb[pos] = etop;
         L.dn[pos] = 0;
     };
+    // give up the current task (used bits of the mapped prefix are cleared)
+    auto drop_task = [&](unsigned mapped) {
+        WAVE_SYNC();
+        for (unsigned i = gl; i < mapped; i += G) {
+            unsigned v = L.M[i];
+            atomicAnd(&L.used[v >> 5], ~(1u << (v & 31)));
+        }
+        if (gl == 0) release_task(S, nchunks);
+        inst = NO_TASK;
+        etop = 0;
+    };
 
     while (true) {
         iter++;
-        // ------------------------------------------------ task acquisition
-        bool want = (inst == NO_TASK) && !finished;
-        unsigned long long want_b = __ballot(want);
-        bool wave_busy = __ballot(inst != NO_TASK) != 0;
-        if (want_b && (!wave_busy || (iter & 7) == 0)) {
-            for (int g = 0; g < 64 / G; g++) {
-                if (!(want && (lane / G) == g)) continue;
-                // leader: queue first, then a root chunk
-                unsigned kind = 0, val = 0;
-                if (gl == 0) {
-                    if (cas_dec_if_pos(&S->q_avail)) {
-                        unsigned t = fadd(&S->q_head, 1);
-                        unsigned slot = t % QUEUE_SLOTS;
-                        while (ld_acq(&a.queue[slot].seq) != 2 * t + 1) __builtin_amdgcn_s_sleep(1);
-                        kind = 1;
-                        val = t;
-                    } else if (!roots_done) {
-                        fadd(&S->work, 1);
-                        unsigned c = fadd(&S->chunk_next, 1);
-                        if (c < nchunks) { kind = 2; val = c; }
-                        else { fadd(&S->work, (unsigned)-1); roots_done = true; }
-                    }
+        const unsigned long long idle_b = __ballot(inst == NO_TASK);
+        const bool wave_idle = idle_b == ~0ull;
+        // ------------------------------------------------ poll the scheduler (one lane per wave)
+        const bool poll = idle_b != 0 && (wave_idle || (iter & 31) == 0);
+        if (poll || (iter & 63) == 0) {
+            unsigned flags = 0, av = 0, cn = 0, fr = 0;
+            if (lane == 0) {
+                if (now_ticks() > deadline) {
+                    st_rlx(&S->abort, 1u);
+                    flags |= 1;
                 }
-                kind = __shfl(kind, gbase);
-                val = __shfl(val, gbase);
-                roots_done = __shfl((int)roots_done, gbase) != 0;
-                unsigned ti = 0, tL = 0, tlo = 0, thi = 0;
-                if (kind == 1) {
-                    __atomic_thread_fence(__ATOMIC_ACQUIRE);
-                    QTask *q = a.queue + (val % QUEUE_SLOTS);
-                    ti = q->inst; tL = q->L; tlo = q->lo; thi = q->hi;
-                    for (unsigned i = gl; i < tL; i += G) L.M[i] = q->M[i];
-                    __atomic_thread_fence(__ATOMIC_RELEASE);
+                if (ld_rlx(&S->abort)) flags |= 1;
+                if (ld_rlx(&S->done)) flags |= 2;
+                av = ld_rlx(&S->q_avail);
+                cn = ld_rlx(&S->chunk_next);
+                fr = ld_rlx(&S->q_free);
+            }
+            flags = __shfl(flags, 0);
+            av = __shfl(av, 0);
+            cn = __shfl(cn, 0);
+            fr = __shfl(fr, 0);
+            if (flags & 1) break;                    // time limit: every wave stops
+            if ((flags & 2) && wave_idle) break;     // the search is complete
+            // give work away only once the roots are all claimed and the queue runs low
+            donate_hint = a.donate && cn >= nchunks && av < 64 && fr > 256;
+            if (poll && (av > 0 || cn < nchunks)) {
+                // ---------------------------------------- task acquisition, one unit at a time
+                for (int g = 0; g < 64 / G; g++) {
+                    if (!(inst == NO_TASK && (lane / G) == g)) continue;
+                    unsigned kind = 0, val = 0;
                     if (gl == 0) {
-                        st_rel(&q->seq, 2 * (val + QUEUE_SLOTS));
-                        fadd(&S->q_free, 1);
-                    }
-                } else if (kind == 2) {
-                    unsigned lo = 0, hi = a.ninst;   // largest i with prefix[i] <= val
-                    if (gl == 0) {
-                        while (hi - lo > 1) {
-                            unsigned mid = (lo + hi) >> 1;
-                            if (a.chunk_prefix[mid] <= val) lo = mid;
-                            else hi = mid;
+                        if (av > 0 && cas_dec_if_pos(&S->q_avail)) {
+                            unsigned t = fadd(&S->q_head, 1);
+                            unsigned slot = t % QUEUE_SLOTS;
+                            kind = 1;
+                            while (ld_rlx(&a.queue[slot].seq) != 2 * t + 1) {
+                                __builtin_amdgcn_s_sleep(1);
+                                if (now_ticks() > deadline) { kind = 0; break; }
+                            }
+                            fence_acq();
+                            val = t;
+                        } else if (!roots_done && cn < nchunks) {
+                            fadd(&S->work, 1);
+                            unsigned c = fadd_ar(&S->chunk_next, 1);
+                            if (c < nchunks) {
+                                kind = 2;
+                                val = c;
+                            } else {
+                                roots_done = true;
+                                release_task(S, nchunks);
+                            }
                         }
                     }
-                    ti = __shfl(lo, gbase);
-                    const InstDesc &dd = a.inst[ti];
-                    tL = 0;
-                    tlo = (val - a.chunk_prefix[ti]) * dd.chunk;
-                    thi = min(tlo + dd.chunk, dd.nroot);
-                }
-                if (kind == 0) {
-                    if (gl == 0 && !idle_counted) fadd(&S->idle, 1);
-                    idle_counted = true;
-                    if (roots_done) {
-                        unsigned w = 0;
-                        if (gl == 0) w = ld_acq(&S->work);
-                        if (__shfl(w, gbase) == 0) finished = true;
+                    kind = __shfl(kind, gbase);
+                    val = __shfl(val, gbase);
+                    roots_done = __shfl((int)roots_done, gbase) != 0;
+                    if (kind == 0) continue;
+                    unsigned ti = 0, tL = 0, tlo = 0, thi = 0;
+                    if (kind == 1) {
+                        QTask *q = a.queue + (val % QUEUE_SLOTS);
+                        ti = q->inst;
+                        tL = q->L;
+                        tlo = q->lo;
+                        thi = q->hi;
+                        for (unsigned i = gl; i < tL; i += G) L.M[i] = q->M[i];
+                        fence_rel();
+                        if (gl == 0) {
+                            st_rlx(&q->seq, 2 * (val + QUEUE_SLOTS));
+                            fadd(&S->q_free, 1);
+                        }
+                    } else {
+                        unsigned lo = 0, hi = a.ninst;   // largest i with prefix[i] <= val
+                        if (gl == 0) {
+                            while (hi - lo > 1) {
+                                unsigned mid = (lo + hi) >> 1;
+                                if (a.chunk_prefix[mid] <= val) lo = mid;
+                                else hi = mid;
+                            }
+                        }
+                        ti = __shfl(lo, gbase);
+                        const InstDesc &dd = a.inst[ti];
+                        tlo = (val - a.chunk_prefix[ti]) * dd.chunk;
+                        thi = min(tlo + dd.chunk, dd.nroot);
                     }
-                    continue;
+                    // start the task
+                    if (ti != cinst) {
+                        flush();
+                        cinst = ti;
+                        d = a.inst[ti];
+                        P = d.plan;
+                        k = P->k;
+                        W = P->W;
+                    }
+                    inst = ti;
+                    since_donate = 0;
+                    if (kind == 1) c_steals++;
+                    etop = 0;
+                    if (a.state_cap && inst_aborted(inst)) {   // capped instance: drop the task
+                        if (gl == 0) release_task(S, nchunks);
+                        inst = NO_TASK;
+                        continue;
+                    }
+                    for (unsigned i = gl; i < tL; i += G) {
+                        unsigned v = L.M[i];
+                        NodeRec r = d.node[v];
+                        L.MB[i] = r.begin;
+                        L.MD[i] = r.deg;
+                        atomicOr(&L.used[v >> 5], 1u << (v & 31));
+                    }
+                    WAVE_SYNC();
+                    base = lvl = tL;
+                    open_frame(tL, tlo, thi);
                 }
-                if (idle_counted && gl == 0) fadd(&S->idle, (unsigned)-1);
-                idle_counted = false;
-                // start the task
-                if (ti != cinst) {
-                    flush();
-                    cinst = ti;
-                    d = a.inst[ti];
-                    P = d.plan;
-                    k = P->k;
-                    W = P->W;
-                }
-                inst = ti;
-                if (kind == 1) c_steals++;
-                if (inst_aborted(inst)) {
-                    // capped instance: drop the task
-                    if (gl == 0) fadd(&S->work, (unsigned)-1);
-                    inst = NO_TASK;
-                    continue;
-                }
-                etop = 0;
-                for (unsigned i = gl; i < tL; i += G) {
-                    unsigned v = L.M[i];
-                    NodeRec r = d.node[v];
-                    L.MB[i] = r.begin;
-                    L.MD[i] = r.deg;
-                    atomicOr(&L.used[v >> 5], 1u << (v & 31));
-                }
-                WAVE_SYNC();
-                base = lvl = tL;
-                open_frame(tL, tlo, thi);
             }
         }
-        if (__ballot(!finished) == 0) break;
-        if (inst == NO_TASK) {
-            if (!wave_busy) __builtin_amdgcn_s_sleep(2);
+        if (__ballot(inst != NO_TASK) == 0) {
+            // the whole wave is idle: back off before polling again
+            backoff = backoff < 8 ? backoff + 1 : 8;
+            for (unsigned z = 0; z < backoff; z++) __builtin_amdgcn_s_sleep(32);
             continue;
         }
+        backoff = 0;
+        if (inst == NO_TASK) continue;
 
         // ------------------------------------------------ one search step
         WAVE_SYNC();
+        since_donate++;
         // pop exhausted frames
         bool task_done = false;
         while (true) {
@@ -310,14 +377,8 @@ __global__ void __launch_bounds__(256) search_csr(SearchArgs a) {
             if (gl == 0) atomicAnd(&L.used[v >> 5], ~(1u << (v & 31)));
         }
         if (task_done) {
-            // release the prefix and the task
-            for (unsigned i = gl; i < base; i += G) {
-                unsigned v = L.M[i];
-                atomicAnd(&L.used[v >> 5], ~(1u << (v & 31)));
-            }
-            if (gl == 0) fadd(&S->work, (unsigned)-1);
             if (c_states >= 4096) flush();
-            inst = NO_TASK;
+            drop_task(base);
             continue;
         }
         // map the top accepted candidate and open the next frame
@@ -397,30 +458,15 @@ __global__ void __launch_bounds__(256) search_csr(SearchArgs a) {
         if (c_states >= 8192) {
             flush();
             if (a.state_cap && inst_aborted(inst)) {
-                WAVE_SYNC();
-                for (unsigned i = gl; i < lvl; i += G) {
-                    unsigned v = L.M[i];
-                    atomicAnd(&L.used[v >> 5], ~(1u << (v & 31)));
-                }
-                if (gl == 0) fadd(&S->work, (unsigned)-1);
-                inst = NO_TASK;
-                etop = 0;
+                drop_task(lvl);
                 continue;
             }
         }
 
-        // ------------------------------------------------ donation
-        if (a.donate && (iter & 15) == 0) {
-            unsigned hint = 0;
-            if (lane == 0) {
-                unsigned idle = ld_rlx(&S->idle), av = ld_rlx(&S->q_avail), fr = ld_rlx(&S->q_free);
-                hint = (idle > av && fr > 64) ? 1u : 0u;
-            }
-            donate_hint = __shfl(hint, 0) != 0;
-        }
-        if (donate_hint && (iter & 15) == 0) {
+        // ------------------------------------------------ donation (one unit at a time)
+        if (donate_hint && (iter & 15) == 0 && __ballot(since_donate >= 256) != 0) {
             for (int g = 0; g < 64 / G; g++) {
-                if (!((lane / G) == g && inst != NO_TASK)) continue;
+                if (!((lane / G) == g && inst != NO_TASK && since_donate >= 256)) continue;
                 // shallowest frame with untried candidates or a spare accepted one
                 unsigned f = base, kind = 0;
                 for (; f <= lvl; f++) {
@@ -435,67 +481,85 @@ __global__ void __launch_bounds__(256) search_csr(SearchArgs a) {
                     if (cas_dec_if_pos(&S->q_free)) {
                         fadd(&S->work, 1);
                         t = fadd(&S->q_tail, 1);
-                        while (ld_acq(&a.queue[t % QUEUE_SLOTS].seq) != 2 * t) __builtin_amdgcn_s_sleep(1);
                         okr = 1;
+                        while (ld_rlx(&a.queue[t % QUEUE_SLOTS].seq) != 2 * t) {
+                            __builtin_amdgcn_s_sleep(1);
+                            if (now_ticks() > deadline) { okr = 0; break; }
+                        }
+                        fence_acq();
                     }
                 }
                 if (!__shfl(okr, gbase)) continue;
                 t = __shfl(t, gbase);
                 WAVE_SYNC();
+                since_donate = 0;
                 QTask *q = a.queue + (t % QUEUE_SLOTS);
                 unsigned tL, tlo, thi, extra = 0;
                 if (kind == 1) {
                     unsigned c = L.cur[f], e = L.end[f];
                     unsigned mid = c + (e - c) / 2;
-                    tL = f; tlo = mid; thi = e;
+                    tL = f;
+                    tlo = mid;
+                    thi = e;
                     L.end[f] = mid;
                 } else {
                     unsigned idx = L.eb[f] + L.dn[f];
                     L.dn[f] = L.dn[f] + 1;
                     extra = L.ev[idx];
-                    tL = f + 1; tlo = 0; thi = FULL_RANGE;
+                    tL = f + 1;
+                    tlo = 0;
+                    thi = FULL_RANGE;
                 }
                 for (unsigned i = gl; i < f; i += G) q->M[i] = L.M[i];
                 if (kind == 2 && gl == 0) q->M[f] = extra;
-                if (gl == 0) { q->inst = inst; q->L = tL; q->lo = tlo; q->hi = thi; }
-                __atomic_thread_fence(__ATOMIC_RELEASE);
                 if (gl == 0) {
-                    st_rel(&q->seq, 2 * t + 1);
+                    q->inst = inst;
+                    q->L = tL;
+                    q->lo = tlo;
+                    q->hi = thi;
+                }
+                fence_rel();
+                if (gl == 0) {
+                    st_rlx(&q->seq, 2 * t + 1);
                     fadd(&S->q_avail, 1);
                 }
             }
         }
     }
     flush();
+    if (lane == 0) atomicMax(&S->t_end, now_ticks());
 }
 
 __global__ void reset_kernel(Sched *s, InstCounters *c, unsigned ninst, QTask *q) {
     unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned stride = gridDim.x * blockDim.x;
-    if (i == 0) {
-        s->chunk_next = 0;
-        s->work = 0;
-        s->q_tail = 0;
-        s->q_head = 0;
-        s->q_avail = 0;
-        s->q_free = QUEUE_SLOTS;
-        s->idle = 0;
-        s->abort = 0;
-        s->total_states = 0;
-        s->state_cap = 0;
+    if (blockIdx.x == 0) {
+        unsigned *w = reinterpret_cast<unsigned *>(s);
+        for (unsigned j = threadIdx.x; j < sizeof(Sched) / 4; j += blockDim.x) w[j] = 0;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s->q_free = QUEUE_SLOTS;
+            s->t_start = ~0ull;
+        }
     }
     for (unsigned j = i; j < ninst; j += stride) c[j] = InstCounters{0, 0, 0, 0, 0, 0, 0, 0};
     for (unsigned j = i; j < QUEUE_SLOTS; j += stride) q[j].seq = 2 * j;
 }
 
 template <int G>
-hipError_t launch_csr(const SearchArgs &args, int blocks, int threads, size_t lds, hipStream_t s, int num_cus) {
+hipError_t launch_csr(const SearchArgs &args, int blocks, int threads, size_t lds, hipStream_t s, int num_cus,
+                      uint32_t total_chunks) {
     if (blocks <= 0) {
+        // resident blocks only (a persistent grid), and no more than the root
+        // chunks can keep busy before work is handed around
         int per_cu = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_csr<G>, threads, lds);
         if (e != hipSuccess) return e;
         if (per_cu < 1) per_cu = 1;
-        blocks = per_cu * num_cus;
+        int units_per_block = threads / G;
+        long want = (4L * total_chunks + units_per_block - 1) / units_per_block;
+        if (want < 2L * num_cus) want = 2L * num_cus;
+        blocks = (int)std::min<long>((long)per_cu * num_cus, want);
     }
     hipLaunchKernelGGL(search_csr<G>, dim3(blocks), dim3(threads), lds, s, args);
     return hipGetLastError();
@@ -527,8 +591,8 @@ hipError_t launch_reset(DevWork &w, uint32_t ninst, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_search(const LaunchCfg &cfg, DevWork &w, uint32_t ninst, uint64_t state_cap, hipStream_t s,
-                         int num_cus, size_t lds_per_cu) {
+hipError_t launch_search(const LaunchCfg &cfg, DevWork &w, uint32_t ninst, uint32_t total_chunks,
+                         uint64_t state_cap, uint64_t time_limit_ms, hipStream_t s, int num_cus) {
     SearchArgs a{};
     a.inst = w.inst;
     a.chunk_prefix = w.chunk_prefix;
@@ -542,16 +606,16 @@ hipError_t launch_search(const LaunchCfg &cfg, DevWork &w, uint32_t ninst, uint6
     a.unit_words = unit_words(cfg);
     a.donate = cfg.donate;
     a.state_cap = state_cap;
+    a.limit_ticks = time_limit_ms * 100000ull;   // s_memrealtime runs at 100 MHz
     const int threads = block_threads(cfg);
     if (!threads) return hipErrorInvalidValue;   // one unit's LDS does not fit
     size_t lds = search_lds_bytes(cfg);
-    (void)lds_per_cu;
     int blocks = cfg.blocks;
     switch (cfg.lanes) {
-        case 8: return launch_csr<8>(a, blocks, threads, lds, s, num_cus);
-        case 16: return launch_csr<16>(a, blocks, threads, lds, s, num_cus);
-        case 32: return launch_csr<32>(a, blocks, threads, lds, s, num_cus);
-        case 64: return launch_csr<64>(a, blocks, threads, lds, s, num_cus);
+        case 8: return launch_csr<8>(a, blocks, threads, lds, s, num_cus, total_chunks);
+        case 16: return launch_csr<16>(a, blocks, threads, lds, s, num_cus, total_chunks);
+        case 32: return launch_csr<32>(a, blocks, threads, lds, s, num_cus, total_chunks);
+        case 64: return launch_csr<64>(a, blocks, threads, lds, s, num_cus, total_chunks);
         default: return hipErrorInvalidValue;
     }
 }

@@ -25,7 +25,7 @@ EXPORTS = [
     "sge_create", "sge_destroy", "sge_last_error", "sge_load_target", "sge_unload_target", "sge_load_pattern",
     "sge_unload_pattern", "sge_set_labelled", "sge_set_mode", "sge_set_state_cap", "sge_set_root_range",
     "sge_count", "sge_enumerate", "sge_batch_run", "sge_set_batch_policy", "sge_serve_start", "sge_serve_submit",
-    "sge_serve_poll", "sge_serve_stop", "sge_plan_host", "sge_set_tuning",
+    "sge_serve_poll", "sge_serve_stop", "sge_plan_host", "sge_set_tuning", "sge_set_time_limit",
 ]
 
 
@@ -93,6 +93,7 @@ def lib() -> ctypes.CDLL:
             "sge_serve_stop": (I32, [P]),
             "sge_plan_host": (I32, [U32, P, P, P, U32, P, P, P, I32, I32, P, P, P, ctypes.POINTER(I32)]),
             "sge_set_tuning": (I32, [P, I32, U32, I32, I32]),
+            "sge_set_time_limit": (I32, [P, U64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -199,6 +200,9 @@ class Context:
 
     def set_state_cap(self, cap: int):
         self._check(self._L.sge_set_state_cap(self._h, int(cap)), "sge_set_state_cap")
+
+    def set_time_limit(self, ms: int):
+        self._check(self._L.sge_set_time_limit(self._h, int(ms)), "sge_set_time_limit")
 
     def set_root_range(self, lo: int = 0, hi: int = 0xFFFFFFFF):
         self._check(self._L.sge_set_root_range(self._h, int(lo), int(hi)), "sge_set_root_range")

@@ -1,0 +1,143 @@
+"""GPU parity of the batched path (many jobs in one persistent launch in a HIP
+graph) against the oracle's stored results for the full workloads."""
+from __future__ import annotations
+
+import json
+import os
+import sys
+
+import pytest
+
+import oracle
+from paper_1705_09358_amd import sge, synth
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def manifest(cfg):
+    with open(os.path.join(GOLDEN, f"{cfg}.json")) as f:
+        return json.load(f)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = sge.Context(0)
+    c.set_time_limit(60000)   # any launch ends within a minute
+    yield c
+    c.close()
+
+
+def load_jobs(ctx, insts):
+    tcache = {}
+    jobs = []
+    for inst in insts:
+        key = id(inst.target)
+        if key not in tcache:
+            tcache[key] = ctx.load_target(inst.target)
+        jobs.append((tcache[key], ctx.load_pattern(inst.pattern), inst.mode, inst.labelled))
+    return jobs
+
+
+def unload(ctx, jobs):
+    for t in {j[0] for j in jobs}:
+        ctx.unload_target(t)
+    for j in jobs:
+        ctx.unload_pattern(j[1])
+
+
+@pytest.mark.parametrize("policy", [2, 1])
+def test_small_batch_c1(ctx, policy):
+    man = manifest("c1")
+    rows = man["instances"][:6]
+    _note(f"batch c1 x{len(rows)} policy {policy}")
+    insts = [synth.c1_instance(r["j"], r["attempt"]) for r in rows]
+    jobs = load_jobs(ctx, insts)
+    ctx.set_batch_policy(policy)
+    try:
+        st, res = ctx.batch_run(jobs)
+    finally:
+        ctx.set_batch_policy(0)
+        unload(ctx, jobs)
+    assert st == sge.OK
+    assert [(r.matches, r.states) for r in res] == [(w["matches"], w["states"]) for w in rows]
+
+
+def test_batch_mixed_modes_vs_live_oracle(ctx):
+    import graphs as G
+    insts = [synth.c1_instance(j) for j in range(8)]
+    for i, inst in enumerate(insts):
+        inst.mode = i % 4
+    # two small unlabelled jobs (an unlabelled 8-node pattern has ~1e9 embeddings here)
+    for i, P in enumerate([G.path(3), G.cycle(4)]):
+        insts.append(synth.Instance(insts[i].target, P, i * 3, False, None))
+    jobs = load_jobs(ctx, insts)
+    try:
+        st, res = ctx.batch_run(jobs)
+    finally:
+        unload(ctx, jobs)
+    for inst, r in zip(insts, res):
+        w = oracle.run(inst.pattern, inst.target, inst.mode, inst.labelled)
+        assert (r.matches, r.states) == (w["matches"], w["states"])
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2"])
+@pytest.mark.parametrize("policy", [0, 1, 2])
+def test_full_batch(ctx, cfg, policy):
+    man = manifest(cfg)
+    _note(f"batch {cfg} full x{len(man['instances'])} policy {policy}")
+    make = {"c1": synth.c1_instance, "c2": synth.c2_instance}[cfg]
+    insts = [make(r["j"], r["attempt"]) for r in man["instances"]]
+    jobs = load_jobs(ctx, insts)
+    ctx.set_batch_policy(policy)
+    try:
+        st, res = ctx.batch_run(jobs)
+    finally:
+        ctx.set_batch_policy(0)
+        unload(ctx, jobs)
+    assert st == sge.OK
+    got = [(r.matches, r.states) for r in res]
+    want = [(w["matches"], w["states"]) for w in man["instances"]]
+    assert got == want
+
+
+def test_c4_full_batch(ctx):
+    """All 4096 pairs of the batching workload in one launch."""
+    man = manifest("c4")
+    _note("batch c4 x4096: generating")
+    insts = [synth.c4_instance(r["j"], r["attempt"]) for r in man["instances"]]
+    jobs = load_jobs(ctx, insts)
+    _note("batch c4: running")
+    try:
+        st, res = ctx.batch_run(jobs)
+    finally:
+        unload(ctx, jobs)
+    assert st == sge.OK
+    bad = [(i, r.matches, r.states, w["matches"], w["states"])
+           for i, (r, w) in enumerate(zip(res, man["instances"])) if (r.matches, r.states) != (w["matches"], w["states"])]
+    assert not bad, bad[:10]
+
+
+def test_batch_state_cap(ctx):
+    man = manifest("c2")
+    rows = man["instances"][:10]
+    insts = [synth.c2_instance(r["j"], r["attempt"]) for r in rows]
+    jobs = load_jobs(ctx, insts)
+    cap = sorted(r["states"] for r in rows)[5]
+    ctx.set_state_cap(cap)
+    try:
+        st, res = ctx.batch_run(jobs, allow=(sge.OK, sge.E_ABORTED))
+    finally:
+        ctx.set_state_cap(0)
+        unload(ctx, jobs)
+    assert st == sge.E_ABORTED
+    for r, w in zip(res, rows):
+        if w["states"] <= cap:
+            assert (r.matches, r.states) == (w["matches"], w["states"])
+        else:
+            assert r.states > cap

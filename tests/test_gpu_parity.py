@@ -23,6 +23,7 @@ def _note(msg):
 @pytest.fixture(scope="module")
 def ctx():
     c = sge.Context(0)
+    c.set_time_limit(60000)   # any launch ends within a minute
     yield c
     c.close()
 
