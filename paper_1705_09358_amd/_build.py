@@ -15,7 +15,7 @@ SGE_SO = os.path.join(LIBDIR, "libsge.so")
 SYNTH_SO = os.path.join(LIBDIR, "libsynth_walk.so")
 
 # Host sources (plain C++) and device sources (HIP) of the search library.
-HOST_SRCS = ["sge_graph.cpp", "sge_plan.cpp", "sge_api.cpp", "sge_batch.cpp", "sge_serve.cpp"]
+HOST_SRCS = ["sge_graph.cpp", "sge_plan.cpp", "sge_api.cpp", "sge_launch.cpp", "sge_batch.cpp", "sge_serve.cpp"]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__"]
 HIP_SRCS = ["sge_search.hip"]
 

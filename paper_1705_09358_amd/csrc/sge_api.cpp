@@ -93,228 +93,6 @@ void free_target(Target &t) {
     t.d_adj = nullptr;
 }
 
-static int auto_lanes(const std::vector<const Target *> &ts) {
-    double deg = 0;
-    uint64_t cnt = 0;
-    for (const Target *t : ts) {
-        deg += (double)t->g.col.size();
-        cnt += t->g.n;
-    }
-    double avg = cnt ? deg / (double)cnt : 0;
-    if (avg <= 12) return 16;
-    if (avg <= 24) return 32;
-    return 64;
-}
-
-static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std::vector<InstanceOut> &out,
-                         double &ms_prep, double &ms_search, bool graph, int policy) {
-    auto t0 = clk::now();
-    const size_t N = specs.size();
-    out.assign(N, InstanceOut{});
-    std::vector<Plan> plans(N);
-    std::vector<std::vector<uint64_t>> bits(N);
-    std::vector<char> active(N, 0);
-
-    auto plan_one = [&](size_t i) {
-        const InstanceSpec &s = specs[i];
-        if (s.p->g.n == 0) {          // the empty pattern has one (empty) match
-            out[i].matches = 1;
-            return;
-        }
-        bool want_bits = s.mode != SGE_RI;
-        uint32_t lo = c->root_lo, hi = c->root_hi;
-        build_plan(*s.t, s.p->g, s.mode, s.labelled, lo, hi, plans[i], want_bits, bits[i]);
-        active[i] = !plans[i].empty;
-    };
-    if (N >= 64) {
-        unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-        std::vector<std::thread> th;
-        for (unsigned w = 0; w < nt; w++)
-            th.emplace_back([&, w]() {
-                for (size_t i = w; i < N; i += nt) plan_one(i);
-            });
-        for (auto &x : th) x.join();
-    } else {
-        for (size_t i = 0; i < N; i++) plan_one(i);
-    }
-
-    std::vector<size_t> idx;
-    for (size_t i = 0; i < N; i++)
-        if (active[i]) idx.push_back(i);
-    const uint32_t m = (uint32_t)idx.size();
-    if (m == 0) {
-        ms_prep = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
-        ms_search = 0;
-        return SGE_OK;
-    }
-
-    // launch shape
-    LaunchCfg cfg;
-    std::vector<const Target *> ts;
-    for (size_t i : idx) {
-        cfg.kmax = std::max(cfg.kmax, plans[i].k);
-        cfg.nmax = std::max(cfg.nmax, plans[i].n);
-        ts.push_back(specs[i].t);
-    }
-    cfg.lanes = c->lanes ? c->lanes : auto_lanes(ts);
-    cfg.donate = c->donate;
-    // approximate number of search units (for the root chunk size)
-    uint64_t units = (uint64_t)c->num_cus * 4 * 8 * (64 / cfg.lanes) / 2;
-
-    // blob layout: plans | descs | chunk prefix | lists | bits
-    size_t off_plan = 0;
-    size_t off_desc = align_up(off_plan + m * sizeof(DevPlan), 256);
-    size_t off_pref = align_up(off_desc + m * sizeof(InstDesc), 256);
-    size_t off_list = align_up(off_pref + (m + 1) * sizeof(unsigned), 256);
-    std::vector<size_t> list_at(m), bits_at(m);
-    size_t cur = off_list;
-    for (uint32_t j = 0; j < m; j++) {
-        list_at[j] = cur;
-        cur = align_up(cur + plans[idx[j]].lists.size() * 4, 16);
-    }
-    cur = align_up(cur, 256);
-    for (uint32_t j = 0; j < m; j++) {
-        bits_at[j] = cur;
-        cur = align_up(cur + bits[idx[j]].size() * 8, 16);
-    }
-    const size_t blob = std::max<size_t>(cur, 256);
-    hipError_t e;
-    if ((e = c->d_blob.reserve(blob)) != hipSuccess) return hip_fail(c, e, "device plan buffer");
-    if ((e = c->h_blob.reserve(blob)) != hipSuccess) return hip_fail(c, e, "pinned plan buffer");
-    const size_t ctr_bytes = align_up(m * sizeof(InstCounters), 64);
-    if ((e = c->h_ctr.reserve(ctr_bytes + sizeof(Sched))) != hipSuccess) return hip_fail(c, e, "pinned counters");
-    char *hb = (char *)c->h_blob.p;
-    char *db = (char *)c->d_blob.p;
-
-    uint64_t total_roots = 0;
-    for (size_t i : idx) total_roots += plans[i].list_len[0];
-    unsigned *pref = (unsigned *)(hb + off_pref);
-    pref[0] = 0;
-    for (uint32_t j = 0; j < m; j++) {
-        const Plan &pl = plans[idx[j]];
-        const InstanceSpec &s = specs[idx[j]];
-        DevPlan &dp = ((DevPlan *)(hb + off_plan))[j];
-        std::memset(&dp, 0, sizeof(dp));
-        dp.k = pl.k;
-        dp.W = pl.W;
-        dp.n = pl.n;
-        dp.use_dom = pl.mode != SGE_RI;
-        dp.labelled = pl.labelled;
-        for (uint32_t i = 0; i < pl.k; i++) {
-            dp.parent[i] = pl.parent[i];
-            dp.back[i] = pl.back[i];
-            dp.plabel[i] = pl.plabel[i];
-            dp.pdeg[i] = pl.pdeg[i];
-            dp.order[i] = pl.order[i];
-            dp.list_off[i] = pl.list_off[i];
-            dp.list_len[i] = pl.list_len[i];
-        }
-        std::memcpy(hb + list_at[j], pl.lists.data(), pl.lists.size() * 4);
-        std::memcpy(hb + bits_at[j], bits[idx[j]].data(), bits[idx[j]].size() * 8);
-        InstDesc &d = ((InstDesc *)(hb + off_desc))[j];
-        d.col = s.t->d_col;
-        d.node = s.t->d_node;
-        d.adj = s.t->d_adj;
-        d.plan = (const DevPlan *)(db + off_plan) + j;
-        d.bits = bits[idx[j]].empty() ? nullptr : (const uint64_t *)(db + bits_at[j]);
-        d.lists = (const uint32_t *)(db + list_at[j]);
-        d.rows = s.rows;
-        d.cap_rows = s.rows ? s.cap_rows : 0;
-        d.nroot = pl.list_len[0];
-        uint32_t chunk;
-        if (policy == 1) chunk = std::max<uint32_t>(1, d.nroot);
-        else if (c->root_chunk) chunk = c->root_chunk;
-        else chunk = (uint32_t)std::max<uint64_t>(1, total_roots / (4 * units));
-        d.chunk = chunk;
-        d.nchunks = d.nroot ? (d.nroot + chunk - 1) / chunk : 0;
-        pref[j + 1] = pref[j] + d.nchunks;
-    }
-    // device work state
-    DevWork &w = c->work;
-    w.inst = (InstDesc *)(db + off_desc);
-    w.chunk_prefix = (unsigned *)(db + off_pref);
-    if (!w.sched) {
-        if ((e = hipMalloc(&w.sched, sizeof(Sched))) != hipSuccess) return hip_fail(c, e, "hipMalloc(sched)");
-        if ((e = hipMalloc(&w.queue, sizeof(QTask) * QUEUE_SLOTS)) != hipSuccess)
-            return hip_fail(c, e, "hipMalloc(queue)");
-    }
-    if (w.ctr_cap < m) {
-        if (w.ctr) (void)hipFree(w.ctr);
-        w.ctr = nullptr;
-        size_t cap = std::max<size_t>(m, 1024);
-        if ((e = hipMalloc(&w.ctr, cap * sizeof(InstCounters))) != hipSuccess) return hip_fail(c, e, "hipMalloc(ctr)");
-        w.ctr_cap = cap;
-    }
-
-    hipStream_t s = c->stream;
-    // the search kernel is bracketed by ev0/ev1, so ms_search is kernel-only time
-    auto enqueue = [&](bool timed) -> hipError_t {
-        hipError_t r;
-        if ((r = hipMemcpyAsync(db, hb, blob, hipMemcpyHostToDevice, s)) != hipSuccess) return r;
-        if ((r = launch_reset(w, m, s)) != hipSuccess) return r;
-        if (timed && (r = hipEventRecord(c->ev0, s)) != hipSuccess) return r;
-        if ((r = launch_search(cfg, w, m, pref[m], c->cap, c->time_limit_ms, s, c->num_cus)) != hipSuccess) return r;
-        if (timed && (r = hipEventRecord(c->ev1, s)) != hipSuccess) return r;
-        if ((r = hipMemcpyAsync(c->h_ctr.p, w.ctr, m * sizeof(InstCounters), hipMemcpyDeviceToHost, s)) != hipSuccess)
-            return r;
-        return hipMemcpyAsync((char *)c->h_ctr.p + ctr_bytes, w.sched, sizeof(Sched), hipMemcpyDeviceToHost, s);
-    };
-    auto t1 = clk::now();
-    ms_prep = std::chrono::duration<double, std::milli>(t1 - t0).count();
-    if (graph) {
-        // one graph: plan upload, scheduler reset, the persistent search, read-back
-        hipGraph_t g = nullptr;
-        hipGraphExec_t ge = nullptr;
-        if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-            return hip_fail(c, e, "hipStreamBeginCapture");
-        hipError_t er = enqueue(false);
-        e = hipStreamEndCapture(s, &g);
-        if (er != hipSuccess || e != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return hip_fail(c, er != hipSuccess ? er : e, "capture search graph");
-        }
-        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
-        // the executable graph owns the launch's kernel arguments: it is destroyed
-        // only after the stream has drained
-        if ((e = hipEventRecord(c->ev0, s)) == hipSuccess && (e = hipGraphLaunch(ge, s)) == hipSuccess)
-            e = hipEventRecord(c->ev1, s);
-        hipError_t es = hipStreamSynchronize(s);
-        (void)hipGraphExecDestroy(ge);
-        if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
-        if (es != hipSuccess) return hip_fail(c, es, "search");
-    } else {
-        if ((e = enqueue(true)) != hipSuccess) return hip_fail(c, e, "search launch");
-    }
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "search");
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
-
-    const InstCounters *hc = (const InstCounters *)c->h_ctr.p;
-    const Sched *hs = (const Sched *)((char *)c->h_ctr.p + ctr_bytes);
-    if (hs->abort) c->err = "search stopped at the time limit; counters are partial";
-    // kernel time from the device clock (100 MHz): first block start to last wave exit
-    ms_search = hs->t_end > hs->t_start ? (double)(hs->t_end - hs->t_start) / 1e5 : (double)ms;
-    for (uint32_t j = 0; j < m; j++) {
-        InstanceOut &o = out[idx[j]];
-        o.matches = hc[j].matches;
-        o.states = hc[j].states;
-        o.candidates = hc[j].candidates;
-        o.steals = hc[j].steals;
-        if (hs->abort) {
-            o.status = SGE_E_ABORTED;
-            o.timed_out = true;
-        } else if (c->cap && o.states > c->cap) {
-            o.status = SGE_E_ABORTED;
-        }
-        else if (specs[idx[j]].rows && o.matches > specs[idx[j]].cap_rows) o.status = SGE_E_OVERFLOW;
-    }
-    return SGE_OK;
-}
-
 }  // namespace sge
 
 // ------------------------------------------------------------------ C ABI
@@ -355,13 +133,8 @@ void sge_destroy(sge_ctx *c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     for (auto &kv : c->targets) free_target(*kv.second);
-    c->d_blob.release();
+    c->bufs.release();
     c->d_rows.release();
-    c->h_blob.release();
-    c->h_ctr.release();
-    if (c->work.sched) (void)hipFree(c->work.sched);
-    if (c->work.queue) (void)hipFree(c->work.queue);
-    if (c->work.ctr) (void)hipFree(c->work.ctr);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     delete c;

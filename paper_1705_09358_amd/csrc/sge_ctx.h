@@ -43,6 +43,14 @@ struct InstanceOut {
     uint64_t matches = 0, states = 0, candidates = 0, steals = 0;
 };
 
+// Buffers of one launch stream.
+struct LaunchBufs {
+    DevWork work;
+    DevBuf d_blob;
+    HostBuf h_blob, h_ctr;
+    void release();
+};
+
 struct Server;
 struct ServerDeleter {
     void operator()(Server *s) const;
@@ -67,9 +75,8 @@ struct sge_ctx {
     std::map<uint32_t, std::unique_ptr<sge::Target>> targets;
     std::map<uint32_t, std::unique_ptr<sge::Pattern>> patterns;
     uint32_t next_handle = 1;
-    sge::DevWork work;
-    sge::DevBuf d_blob, d_rows;
-    sge::HostBuf h_blob, h_ctr;
+    sge::LaunchBufs bufs;
+    sge::DevBuf d_rows;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::unique_ptr<sge::Server, sge::ServerDeleter> server;
     std::mutex serve_mu;
@@ -85,6 +92,33 @@ sge_status hip_fail(sge_ctx *c, hipError_t e, const char *what);
 // replayed.  Fills `out` and the prep / search times (ms).
 sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std::vector<InstanceOut> &out,
                          double &ms_prep, double &ms_search, bool graph, int policy);
+
+// The pieces of run_instances, also used by the server.
+// Whether these instances are searched by the dense-bitset kernel.
+bool choose_dense(const sge_ctx *c, const std::vector<InstanceSpec> &specs);
+// Plan one instance (k = 0 and empty domains are answered in `out`).
+// Returns whether the instance needs a search.
+bool plan_instance(const sge_ctx *c, const InstanceSpec &s, bool dense, Plan &plan, std::vector<uint64_t> &bits,
+                   InstanceOut &out);
+
+// The host layout of one launch: which plans, where in the blob.
+struct Pack {
+    LaunchCfg cfg;
+    uint32_t m = 0;
+    size_t blob = 0, ctr_bytes = 0;
+    uint32_t total_chunks = 0;
+};
+
+// Lay the plans out in the pinned blob (device addresses from bufs.d_blob);
+// `plans[j]`/`bits[j]` belong to `specs[j]`, all of which need a search.
+sge_status pack_instances(sge_ctx *c, const std::vector<const InstanceSpec *> &specs,
+                          const std::vector<const Plan *> &plans, const std::vector<const std::vector<uint64_t> *> &bits,
+                          bool dense, int policy, LaunchBufs &bufs, Pack &pk);
+// Upload, reset, search and read back on `s` (asynchronous).
+hipError_t enqueue_pack(sge_ctx *c, const Pack &pk, LaunchBufs &bufs, hipStream_t s);
+// After the stream has drained: per-instance results and the kernel time.
+void read_pack(const sge_ctx *c, const Pack &pk, const LaunchBufs &bufs, const std::vector<const InstanceSpec *> &specs,
+               std::vector<InstanceOut *> &out, double &ms_search);
 
 // Device memory for a target's resident data.
 sge_status upload_target(sge_ctx *c, Target &t);

@@ -1,0 +1,293 @@
+// One persistent search launch over a set of instances: plan on the host,
+// lay the plans out in one blob, upload, reset the scheduler, search, read
+// the counters back.  Used by the single-instance calls, by batches (in a HIP
+// graph) and by the server (asynchronously, one stream per launch lane).
+#include <algorithm>
+#include <cstring>
+#include <thread>
+
+#include "sge_ctx.h"
+
+using clk = std::chrono::steady_clock;
+
+namespace sge {
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+void LaunchBufs::release() {
+    d_blob.release();
+    h_blob.release();
+    h_ctr.release();
+    if (work.sched) (void)hipFree(work.sched);
+    if (work.queue) (void)hipFree(work.queue);
+    if (work.ctr) (void)hipFree(work.ctr);
+    work = DevWork{};
+}
+
+bool choose_dense(const sge_ctx *c, const std::vector<InstanceSpec> &specs) {
+    // dense-bitset search when every target has adjacency rows and is dense
+    // enough that a row of W words costs no more than walking a neighbour list
+    if (c->dense == 0 || specs.empty()) return false;
+    bool all_adj = true;
+    double deg = 0, words = 0;
+    for (const InstanceSpec &s : specs) {
+        all_adj &= s.t->d_adj != nullptr;
+        deg += s.t->g.n ? (double)s.t->g.col.size() / s.t->g.n : 0.0;
+        words += s.t->W;
+    }
+    if (!all_adj) return false;
+    return c->dense == 1 || deg >= 2.0 * words;
+}
+
+bool plan_instance(const sge_ctx *c, const InstanceSpec &s, bool dense, Plan &plan, std::vector<uint64_t> &bits,
+                   InstanceOut &out) {
+    if (s.p->g.n == 0) {   // the empty pattern has one (empty) match
+        out.matches = 1;
+        return false;
+    }
+    bool want_bits = dense || s.mode != SGE_RI;
+    build_plan(*s.t, s.p->g, s.mode, s.labelled, c->root_lo, c->root_hi, plan, want_bits, bits);
+    return !plan.empty;
+}
+
+static int auto_lanes(const std::vector<const InstanceSpec *> &specs) {
+    double deg = 0;
+    uint64_t cnt = 0;
+    for (const InstanceSpec *s : specs) {
+        deg += (double)s->t->g.col.size();
+        cnt += s->t->g.n;
+    }
+    double avg = cnt ? deg / (double)cnt : 0;
+    if (avg <= 12) return 32;
+    return 64;
+}
+
+static hipError_t ensure_work(DevWork &w, uint32_t m) {
+    hipError_t e;
+    if (!w.sched) {
+        if ((e = hipMalloc(&w.sched, sizeof(Sched))) != hipSuccess) return e;
+        if ((e = hipMalloc(&w.queue, sizeof(QTask) * QUEUE_SLOTS)) != hipSuccess) return e;
+    }
+    if (w.ctr_cap < m) {
+        if (w.ctr) (void)hipFree(w.ctr);
+        w.ctr = nullptr;
+        size_t cap = std::max<size_t>(m, 1024);
+        if ((e = hipMalloc(&w.ctr, cap * sizeof(InstCounters))) != hipSuccess) return e;
+        w.ctr_cap = cap;
+    }
+    return hipSuccess;
+}
+
+sge_status pack_instances(sge_ctx *c, const std::vector<const InstanceSpec *> &specs,
+                          const std::vector<const Plan *> &plans, const std::vector<const std::vector<uint64_t> *> &bits,
+                          bool dense, int policy, LaunchBufs &bufs, Pack &pk) {
+    const uint32_t m = (uint32_t)specs.size();
+    pk = Pack{};
+    pk.m = m;
+    LaunchCfg &cfg = pk.cfg;
+    for (uint32_t j = 0; j < m; j++) {
+        cfg.kmax = std::max(cfg.kmax, plans[j]->k);
+        cfg.nmax = std::max(cfg.nmax, plans[j]->n);
+        cfg.wmax = std::max(cfg.wmax, plans[j]->W);
+    }
+    cfg.dense = dense ? 1 : 0;
+    if (c->lanes) {
+        cfg.lanes = c->lanes;
+    } else if (dense) {
+        cfg.lanes = 8;
+        while (cfg.lanes < 64 && (uint32_t)cfg.lanes < cfg.wmax) cfg.lanes *= 2;
+    } else {
+        cfg.lanes = auto_lanes(specs);
+    }
+    cfg.donate = c->donate;
+    // approximate number of search units (for the root chunk size)
+    const uint64_t units = (uint64_t)c->num_cus * 4 * 8 * (64 / cfg.lanes) / 2;
+
+    // blob layout: plans | descs | chunk prefix | lists | bits
+    const size_t off_plan = 0;
+    const size_t off_desc = align_up(off_plan + m * sizeof(DevPlan), 256);
+    const size_t off_pref = align_up(off_desc + m * sizeof(InstDesc), 256);
+    const size_t off_list = align_up(off_pref + (m + 1) * sizeof(unsigned), 256);
+    std::vector<size_t> list_at(m), bits_at(m);
+    size_t cur = off_list;
+    for (uint32_t j = 0; j < m; j++) {
+        list_at[j] = cur;
+        cur = align_up(cur + plans[j]->lists.size() * 4, 16);
+    }
+    cur = align_up(cur, 256);
+    for (uint32_t j = 0; j < m; j++) {
+        bits_at[j] = cur;
+        cur = align_up(cur + bits[j]->size() * 8, 16);
+    }
+    pk.blob = std::max<size_t>(cur, 256);
+    pk.ctr_bytes = align_up(m * sizeof(InstCounters), 64);
+    hipError_t e;
+    if ((e = bufs.d_blob.reserve(pk.blob)) != hipSuccess) return hip_fail(c, e, "device plan buffer");
+    if ((e = bufs.h_blob.reserve(pk.blob)) != hipSuccess) return hip_fail(c, e, "pinned plan buffer");
+    if ((e = bufs.h_ctr.reserve(pk.ctr_bytes + sizeof(Sched))) != hipSuccess) return hip_fail(c, e, "pinned counters");
+    if ((e = ensure_work(bufs.work, m)) != hipSuccess) return hip_fail(c, e, "scheduler buffers");
+    char *hb = (char *)bufs.h_blob.p;
+    char *db = (char *)bufs.d_blob.p;
+
+    uint64_t total_roots = 0;
+    for (uint32_t j = 0; j < m; j++) total_roots += plans[j]->list_len[0];
+    unsigned *pref = (unsigned *)(hb + off_pref);
+    pref[0] = 0;
+    for (uint32_t j = 0; j < m; j++) {
+        const Plan &pl = *plans[j];
+        const InstanceSpec &s = *specs[j];
+        DevPlan &dp = ((DevPlan *)(hb + off_plan))[j];
+        std::memset(&dp, 0, sizeof(dp));
+        dp.k = pl.k;
+        dp.W = pl.W;
+        dp.n = pl.n;
+        dp.use_dom = pl.mode != SGE_RI;
+        dp.labelled = pl.labelled;
+        for (uint32_t i = 0; i < pl.k; i++) {
+            dp.parent[i] = pl.parent[i];
+            dp.back[i] = pl.back[i];
+            dp.plabel[i] = pl.plabel[i];
+            dp.pdeg[i] = pl.pdeg[i];
+            dp.order[i] = pl.order[i];
+            dp.list_off[i] = pl.list_off[i];
+            dp.list_len[i] = pl.list_len[i];
+        }
+        std::memcpy(hb + list_at[j], pl.lists.data(), pl.lists.size() * 4);
+        std::memcpy(hb + bits_at[j], bits[j]->data(), bits[j]->size() * 8);
+        InstDesc &d = ((InstDesc *)(hb + off_desc))[j];
+        d.col = s.t->d_col;
+        d.node = s.t->d_node;
+        d.adj = s.t->d_adj;
+        d.plan = (const DevPlan *)(db + off_plan) + j;
+        d.bits = bits[j]->empty() ? nullptr : (const uint64_t *)(db + bits_at[j]);
+        d.lists = (const uint32_t *)(db + list_at[j]);
+        d.rows = s.rows;
+        d.cap_rows = s.rows ? s.cap_rows : 0;
+        d.nroot = pl.list_len[0];
+        uint32_t chunk;
+        if (policy == 1) chunk = std::max<uint32_t>(1, d.nroot);
+        else if (c->root_chunk) chunk = c->root_chunk;
+        else chunk = (uint32_t)std::max<uint64_t>(1, total_roots / (4 * units));
+        d.chunk = chunk;
+        d.nchunks = d.nroot ? (d.nroot + chunk - 1) / chunk : 0;
+        pref[j + 1] = pref[j] + d.nchunks;
+    }
+    pk.total_chunks = pref[m];
+    bufs.work.inst = (InstDesc *)(db + off_desc);
+    bufs.work.chunk_prefix = (unsigned *)(db + off_pref);
+    return SGE_OK;
+}
+
+hipError_t enqueue_pack(sge_ctx *c, const Pack &pk, LaunchBufs &bufs, hipStream_t s) {
+    hipError_t r;
+    if ((r = hipMemcpyAsync(bufs.d_blob.p, bufs.h_blob.p, pk.blob, hipMemcpyHostToDevice, s)) != hipSuccess) return r;
+    if ((r = launch_reset(bufs.work, pk.m, s)) != hipSuccess) return r;
+    if ((r = launch_search(pk.cfg, bufs.work, pk.m, pk.total_chunks, c->cap, c->time_limit_ms, s, c->num_cus)) !=
+        hipSuccess)
+        return r;
+    if ((r = hipMemcpyAsync(bufs.h_ctr.p, bufs.work.ctr, pk.m * sizeof(InstCounters), hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+        return r;
+    return hipMemcpyAsync((char *)bufs.h_ctr.p + pk.ctr_bytes, bufs.work.sched, sizeof(Sched), hipMemcpyDeviceToHost,
+                          s);
+}
+
+void read_pack(const sge_ctx *c, const Pack &pk, const LaunchBufs &bufs, const std::vector<const InstanceSpec *> &specs,
+               std::vector<InstanceOut *> &out, double &ms_search) {
+    const InstCounters *hc = (const InstCounters *)bufs.h_ctr.p;
+    const Sched *hs = (const Sched *)((const char *)bufs.h_ctr.p + pk.ctr_bytes);
+    // kernel time from the device clock (100 MHz): first block start to last wave exit
+    ms_search = hs->t_end > hs->t_start ? (double)(hs->t_end - hs->t_start) / 1e5 : 0.0;
+    for (uint32_t j = 0; j < pk.m; j++) {
+        InstanceOut &o = *out[j];
+        o.matches = hc[j].matches;
+        o.states = hc[j].states;
+        o.candidates = hc[j].candidates;
+        o.steals = hc[j].steals;
+        o.status = SGE_OK;
+        if (hs->abort) {
+            o.status = SGE_E_ABORTED;
+            o.timed_out = true;
+        } else if (c->cap && o.states > c->cap) {
+            o.status = SGE_E_ABORTED;
+        } else if (specs[j]->rows && o.matches > specs[j]->cap_rows) {
+            o.status = SGE_E_OVERFLOW;
+        }
+    }
+}
+
+sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std::vector<InstanceOut> &out,
+                         double &ms_prep, double &ms_search, bool graph, int policy) {
+    auto t0 = clk::now();
+    const size_t N = specs.size();
+    out.assign(N, InstanceOut{});
+    std::vector<Plan> plans(N);
+    std::vector<std::vector<uint64_t>> bits(N);
+    std::vector<char> active(N, 0);
+    const bool dense = choose_dense(c, specs);
+    auto plan_one = [&](size_t i) { active[i] = plan_instance(c, specs[i], dense, plans[i], bits[i], out[i]); };
+    if (N >= 64) {
+        unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        std::vector<std::thread> th;
+        for (unsigned w = 0; w < nt; w++)
+            th.emplace_back([&, w]() {
+                for (size_t i = w; i < N; i += nt) plan_one(i);
+            });
+        for (auto &x : th) x.join();
+    } else {
+        for (size_t i = 0; i < N; i++) plan_one(i);
+    }
+    std::vector<const InstanceSpec *> sp;
+    std::vector<const Plan *> pp;
+    std::vector<const std::vector<uint64_t> *> bp;
+    std::vector<InstanceOut *> op;
+    for (size_t i = 0; i < N; i++)
+        if (active[i]) {
+            sp.push_back(&specs[i]);
+            pp.push_back(&plans[i]);
+            bp.push_back(&bits[i]);
+            op.push_back(&out[i]);
+        }
+    ms_search = 0;
+    if (sp.empty()) {
+        ms_prep = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+        return SGE_OK;
+    }
+    Pack pk;
+    sge_status st = pack_instances(c, sp, pp, bp, dense, policy, c->bufs, pk);
+    if (st != SGE_OK) return st;
+    hipStream_t s = c->stream;
+    ms_prep = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+    hipError_t e;
+    if (graph) {
+        // one graph: plan upload, scheduler reset, the persistent search, read-back
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return hip_fail(c, e, "hipStreamBeginCapture");
+        hipError_t er = enqueue_pack(c, pk, c->bufs, s);
+        e = hipStreamEndCapture(s, &g);
+        if (er != hipSuccess || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_fail(c, er != hipSuccess ? er : e, "capture search graph");
+        }
+        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+        // the executable graph owns the launch's kernel arguments: it is destroyed
+        // only after the stream has drained
+        e = hipGraphLaunch(ge, s);
+        hipError_t es = hipStreamSynchronize(s);
+        (void)hipGraphExecDestroy(ge);
+        if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+        if (es != hipSuccess) return hip_fail(c, es, "search");
+    } else {
+        if ((e = enqueue_pack(c, pk, c->bufs, s)) != hipSuccess) return hip_fail(c, e, "search launch");
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "search");
+    }
+    read_pack(c, pk, c->bufs, sp, op, ms_search);
+    if (op[0]->timed_out) c->err = "search stopped at the time limit; counters are partial";
+    return SGE_OK;
+}
+
+}  // namespace sge

@@ -47,7 +47,7 @@ struct SearchArgs {
     Sched *sched;
     QTask *queue;
     unsigned ninst;
-    unsigned kmax, E, UW, unit_words;
+    unsigned kmax, E, UW, W, unit_words;
     int donate;
     unsigned long long state_cap;
     unsigned long long limit_ticks;   // time limit in s_memrealtime ticks (100 MHz); 0 = none
@@ -145,6 +145,25 @@ __device__ __forceinline__ UnitLds carve(unsigned *base, unsigned kmax, unsigned
     return u;
 }
 
+// Per-unit LDS arrays of the dense kernel.
+struct DenseLds {
+    unsigned *M;                  // mapping by position
+    unsigned *fc;                 // frame: number of candidates left
+    unsigned long long *cand;     // frame: candidate set, kmax rows of W words
+    unsigned long long *used;     // bitset of mapped target nodes (W words)
+};
+
+__host__ __device__ inline unsigned even(unsigned x) { return x + (x & 1u); }
+
+__device__ __forceinline__ DenseLds carve_dense(unsigned *base, unsigned kmax, unsigned W) {
+    DenseLds u;
+    u.M = base;
+    u.fc = u.M + even(kmax);
+    u.cand = reinterpret_cast<unsigned long long *>(u.fc + even(kmax));
+    u.used = u.cand + (size_t)kmax * W;
+    return u;
+}
+
 __device__ __forceinline__ bool used_test(const unsigned *used, unsigned v) { return (used[v >> 5] >> (v & 31)) & 1u; }
 
 // is v a target neighbour of node a (row [b, b+deg))
@@ -161,15 +180,30 @@ __device__ __forceinline__ bool adjacent(const InstDesc &d, unsigned W, unsigned
     return lo < b + deg && d.col[lo] == v;
 }
 
-template <int G>
-__global__ void __launch_bounds__(256) search_csr(SearchArgs a) {
+// DENSE = false: candidate lists (CSR rows) evaluated G at a time, accepted
+// candidates kept on a per-unit stack.  DENSE = true: each frame holds the set
+// of accepted candidates as a bitset over the target nodes; expanding a mapped
+// node ANDs the parent's adjacency row, the position's domain (or label and
+// degree) row, the complement of the used set and every back-edge row, one
+// 64-bit word per lane, and counts the result with popcounts.
+template <int G, bool DENSE>
+__global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
     extern __shared__ unsigned lds[];
     const int lane = threadIdx.x & 63;
     const int gl = lane & (G - 1);
     const int gbase = lane & ~(G - 1);
     const int unit = threadIdx.x / G;
-    UnitLds L = carve(lds + (size_t)unit * a.unit_words, a.kmax, a.E, a.UW);
-    for (unsigned i = gl; i < a.UW; i += G) L.used[i] = 0;
+    UnitLds L{};
+    DenseLds D{};
+    if constexpr (DENSE) {
+        D = carve_dense(lds + (size_t)unit * a.unit_words, a.kmax, a.W);
+        for (unsigned i = gl; i < a.W; i += G) D.used[i] = 0;
+        L.M = D.M;
+    } else {
+        L = carve(lds + (size_t)unit * a.unit_words, a.kmax, a.E, a.UW);
+        for (unsigned i = gl; i < a.UW; i += G) L.used[i] = 0;
+    }
+    const unsigned WS = a.W;   // LDS row stride of the dense frames
 
     Sched *S = a.sched;
     const unsigned nchunks = a.chunk_prefix[a.ninst];
@@ -224,12 +258,86 @@ __global__ void __launch_bounds__(256) search_csr(SearchArgs a) {
         L.dn[pos] = 0;
     };
     // give up the current task (used bits of the mapped prefix are cleared)
+    auto mark = [&](unsigned v) {
+        if constexpr (DENSE) atomicOr(&D.used[v >> 6], 1ull << (v & 63));
+        else atomicOr(&L.used[v >> 5], 1u << (v & 31));
+    };
+    auto unmark = [&](unsigned v) {
+        if constexpr (DENSE) atomicAnd(&D.used[v >> 6], ~(1ull << (v & 63)));
+        else atomicAnd(&L.used[v >> 5], ~(1u << (v & 31)));
+    };
+    // dense: take the lowest member of frame f (group-uniform result)
+    auto pick_lowest = [&](unsigned f) -> unsigned {
+        unsigned v = 0xFFFFFFFFu;
+        for (unsigned r = 0; r * G < W; r++) {
+            const unsigned w = r * G + gl;
+            unsigned long long x = w < W ? D.cand[(size_t)f * WS + w] : 0ull;
+            unsigned long long b = group_mask<G>(__ballot(x != 0ull), gbase);
+            if (b) {
+                const unsigned j = (unsigned)__builtin_ctzll(b);
+                const unsigned long long xw = __shfl(x, gbase + j);
+                const unsigned word = r * G + j;
+                v = word * 64 + (unsigned)__builtin_ctzll(xw);
+                if ((unsigned)gl == j) D.cand[(size_t)f * WS + word] = xw & (xw - 1);
+                break;
+            }
+        }
+        // a frame is only read while its count is positive; should that ever
+        // disagree with its bits, stay on a valid node index
+        return v == 0xFFFFFFFFu ? 0u : v;
+    };
+    // dense: candidates of position `pos` given M[0..pos-1]; at the last position
+    // they are counted (and emitted) as matches, otherwise they become frame pos
+    auto expand = [&](unsigned pos) {
+        const int p = P->parent[pos];
+        const unsigned mp = p >= 0 ? D.M[p] : 0u;
+        const unsigned long long bmask = P->back[pos];
+        const bool last = pos + 1 == k;
+        unsigned cnt = 0;
+        for (unsigned r = 0; r * G < W; r++) {
+            const unsigned w = r * G + gl;
+            if (w < W) {
+                unsigned long long x = d.bits[(size_t)pos * W + w] & ~D.used[w];
+                if (p >= 0) x &= d.adj[(size_t)mp * W + w];
+                unsigned long long bm = bmask;
+                while (bm) {   // four back-edge rows per round, loads issued together
+                    const unsigned j0 = (unsigned)__builtin_ctzll(bm);
+                    bm &= bm - 1;
+                    const unsigned j1 = bm ? (unsigned)__builtin_ctzll(bm) : j0;
+                    bm &= bm ? bm - 1 : 0ull;
+                    const unsigned j2 = bm ? (unsigned)__builtin_ctzll(bm) : j0;
+                    bm &= bm ? bm - 1 : 0ull;
+                    const unsigned j3 = bm ? (unsigned)__builtin_ctzll(bm) : j0;
+                    bm &= bm ? bm - 1 : 0ull;
+                    const unsigned long long a0 = d.adj[(size_t)D.M[j0] * W + w];
+                    const unsigned long long a1 = d.adj[(size_t)D.M[j1] * W + w];
+                    const unsigned long long a2 = d.adj[(size_t)D.M[j2] * W + w];
+                    const unsigned long long a3 = d.adj[(size_t)D.M[j3] * W + w];
+                    x &= a0 & a1 & a2 & a3;
+                }
+                if (!last) D.cand[(size_t)pos * WS + w] = x;
+                cnt += (unsigned)__popcll(x);
+                if (last && d.rows) {
+                    for (unsigned long long y = x; y; y &= y - 1) {
+                        const unsigned v = w * 64 + (unsigned)__builtin_ctzll(y);
+                        unsigned long long slot = atomicAdd(&a.ctr[inst].row_next, 1ull);
+                        if (slot < d.cap_rows) {
+                            uint32_t *row = d.rows + slot * k;
+                            for (unsigned i = 0; i + 1 < k; i++) row[P->order[i]] = D.M[i];
+                            row[P->order[k - 1]] = v;
+                        }
+                    }
+                }
+            }
+        }
+        for (int o = G / 2; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+        c_states += cnt;
+        if (last) c_matches += cnt;
+        D.fc[pos] = last ? 0u : cnt;
+    };
     auto drop_task = [&](unsigned mapped) {
         WAVE_SYNC();
-        for (unsigned i = gl; i < mapped; i += G) {
-            unsigned v = L.M[i];
-            atomicAnd(&L.used[v >> 5], ~(1u << (v & 31)));
-        }
+        for (unsigned i = gl; i < mapped; i += G) unmark(L.M[i]);
         if (gl == 0) release_task(S, nchunks);
         inst = NO_TASK;
         etop = 0;
@@ -339,16 +447,43 @@ __global__ void __launch_bounds__(256) search_csr(SearchArgs a) {
                         inst = NO_TASK;
                         continue;
                     }
-                    for (unsigned i = gl; i < tL; i += G) {
-                        unsigned v = L.M[i];
-                        NodeRec r = d.node[v];
-                        L.MB[i] = r.begin;
-                        L.MD[i] = r.deg;
-                        atomicOr(&L.used[v >> 5], 1u << (v & 31));
+                    if constexpr (DENSE) {
+                        for (unsigned i = gl; i < tL; i += G) mark(D.M[i]);
+                        WAVE_SYNC();
+                        base = lvl = tL;
+                        if (tL == 0) {
+                            // a root chunk: its list entries are the accepted candidates of position 0
+                            for (unsigned w = gl; w < W; w += G) D.cand[w] = 0ull;
+                            WAVE_SYNC();
+                            const uint32_t *lst = d.lists + P->list_off[0] + tlo;
+                            const unsigned cnt = thi - tlo;
+                            for (unsigned i = gl; i < cnt; i += G) {
+                                const unsigned v = lst[i];
+                                atomicOr(&D.cand[v >> 6], 1ull << (v & 63));
+                                if (k == 1 && d.rows) {
+                                    unsigned long long slot = atomicAdd(&a.ctr[inst].row_next, 1ull);
+                                    if (slot < d.cap_rows) d.rows[slot] = v;
+                                }
+                            }
+                            c_states += cnt;
+                            if (k == 1) c_matches += cnt;
+                            D.fc[0] = k == 1 ? 0u : cnt;
+                        } else {
+                            expand(tL);
+                        }
+                        WAVE_SYNC();
+                    } else {
+                        for (unsigned i = gl; i < tL; i += G) {
+                            unsigned v = L.M[i];
+                            NodeRec r = d.node[v];
+                            L.MB[i] = r.begin;
+                            L.MD[i] = r.deg;
+                            mark(v);
+                        }
+                        WAVE_SYNC();
+                        base = lvl = tL;
+                        open_frame(tL, tlo, thi);
                     }
-                    WAVE_SYNC();
-                    base = lvl = tL;
-                    open_frame(tL, tlo, thi);
                 }
             }
         }
@@ -364,93 +499,120 @@ __global__ void __launch_bounds__(256) search_csr(SearchArgs a) {
         // ------------------------------------------------ one search step
         WAVE_SYNC();
         since_donate++;
-        // pop exhausted frames
-        bool task_done = false;
-        while (true) {
-            if (etop > L.eb[lvl] + L.dn[lvl]) break;
-            etop = L.eb[lvl];   // reclaim entries given away from this frame
-            L.dn[lvl] = 0;
-            if (L.cur[lvl] < L.end[lvl]) break;
-            if (lvl == base) { task_done = true; break; }
-            lvl--;
-            unsigned v = L.M[lvl];
-            if (gl == 0) atomicAnd(&L.used[v >> 5], ~(1u << (v & 31)));
-        }
-        if (task_done) {
-            if (c_states >= 4096) flush();
-            drop_task(base);
-            continue;
-        }
-        // map the top accepted candidate and open the next frame
-        if (etop > L.eb[lvl] + L.dn[lvl]) {
-            etop--;
-            unsigned v = L.ev[etop];
-            L.M[lvl] = v;
-            L.MB[lvl] = L.ebg[etop];
-            L.MD[lvl] = L.edg[etop];
-            if (gl == 0) atomicOr(&L.used[v >> 5], 1u << (v & 31));
-            lvl++;
-            open_frame(lvl, 0, FULL_RANGE);
-        }
-        // evaluate up to G candidates of the current frame
-        {
-            const unsigned c0 = L.cur[lvl], e = L.end[lvl], lb = L.lb[lvl];
-            const unsigned idx = c0 + gl;
-            bool ok = idx < e;
-            const bool has_parent = P->parent[lvl] >= 0;
-            unsigned v = 0;
-            NodeRec r{0, 0, 0, 0};
-            if (ok) {
-                v = has_parent ? d.col[lb + idx] : d.lists[lb + idx];
-                r = d.node[v];
+        if constexpr (DENSE) {
+            // pop exhausted frames
+            bool task_done = false;
+            while (true) {
+                if (D.fc[lvl] > 0) break;
+                if (lvl == base) { task_done = true; break; }
+                lvl--;
+                if (gl == 0) unmark(D.M[lvl]);
             }
-            if (ok && d.bits) ok = (d.bits[(size_t)lvl * W + (v >> 6)] >> (v & 63)) & 1ull;
-            if (ok) ok = !used_test(L.used, v);
-            const unsigned pl = P->plabel[lvl];
-            if (ok && pl != LABEL_ANY) ok = r.label == pl;
-            if (ok) ok = r.deg >= P->pdeg[lvl];
-            unsigned long long bm = P->back[lvl];
-            while (bm) {
-                unsigned j = (unsigned)__builtin_ctzll(bm);
-                bm &= bm - 1;
-                if (ok) ok = adjacent(d, W, L.M[j], L.MB[j], L.MD[j], v);
+            if (task_done) {
+                if (c_states >= 4096) flush();
+                drop_task(base);
+                continue;
             }
-            c_cands += min((unsigned)G, e - c0);
-            unsigned long long acc = group_mask<G>(__ballot(ok), gbase);
-            unsigned cnt = (unsigned)__popcll(acc);
-            if (lvl + 1 == k) {
-                c_states += cnt;
-                c_matches += cnt;
-                if (d.rows && ok) {
-                    unsigned long long slot = atomicAdd(&a.ctr[inst].row_next, 1ull);
-                    if (slot < d.cap_rows) {
-                        uint32_t *row = d.rows + slot * k;
-                        for (unsigned i = 0; i + 1 < k; i++) row[P->order[i]] = L.M[i];
-                        row[P->order[k - 1]] = v;
-                    }
-                }
-                L.cur[lvl] = c0 + G;
+            // map the lowest remaining candidate and expand the next position
+            const unsigned v = pick_lowest(lvl);
+            D.fc[lvl] = D.fc[lvl] - 1;
+            D.M[lvl] = v;
+            if (gl == 0) mark(v);
+            WAVE_SYNC();
+            expand(lvl + 1);
+            if (lvl + 2 == k) {
+                if (gl == 0) unmark(v);   // the last position was counted; stay on this frame
             } else {
-                int room = (int)a.E - (int)etop - (int)(k - 2 - lvl);
-                unsigned take = cnt;
-                unsigned long long keep = acc;
-                unsigned ncur = c0 + G;
-                if ((int)take > room) {
-                    take = (unsigned)room;
-                    unsigned long long m = acc;
-                    for (unsigned i = 0; i < take; i++) m &= m - 1;
-                    keep = acc & ~m;                       // the first `take` accepted lanes
-                    ncur = c0 + (63u - (unsigned)__clzll(keep)) + 1;
+                lvl++;
+            }
+        } else {
+            // pop exhausted frames
+            bool task_done = false;
+            while (true) {
+                if (etop > L.eb[lvl] + L.dn[lvl]) break;
+                etop = L.eb[lvl];   // reclaim entries given away from this frame
+                L.dn[lvl] = 0;
+                if (L.cur[lvl] < L.end[lvl]) break;
+                if (lvl == base) { task_done = true; break; }
+                lvl--;
+                if (gl == 0) unmark(L.M[lvl]);
+            }
+            if (task_done) {
+                if (c_states >= 4096) flush();
+                drop_task(base);
+                continue;
+            }
+            // map the top accepted candidate and open the next frame
+            if (etop > L.eb[lvl] + L.dn[lvl]) {
+                etop--;
+                unsigned v = L.ev[etop];
+                L.M[lvl] = v;
+                L.MB[lvl] = L.ebg[etop];
+                L.MD[lvl] = L.edg[etop];
+                if (gl == 0) mark(v);
+                lvl++;
+                open_frame(lvl, 0, FULL_RANGE);
+            }
+            // evaluate up to G candidates of the current frame
+            {
+                const unsigned c0 = L.cur[lvl], e = L.end[lvl], lb = L.lb[lvl];
+                const unsigned idx = c0 + gl;
+                bool ok = idx < e;
+                const bool has_parent = P->parent[lvl] >= 0;
+                unsigned v = 0;
+                NodeRec r{0, 0, 0, 0};
+                if (ok) {
+                    v = has_parent ? d.col[lb + idx] : d.lists[lb + idx];
+                    r = d.node[v];
                 }
-                if ((keep >> gl) & 1ull) {
-                    unsigned rank = (unsigned)__popcll(keep & ((1ull << gl) - 1));
-                    L.ev[etop + rank] = v;
-                    L.ebg[etop + rank] = r.begin;
-                    L.edg[etop + rank] = r.deg;
+                if (ok && d.bits) ok = (d.bits[(size_t)lvl * W + (v >> 6)] >> (v & 63)) & 1ull;
+                if (ok) ok = !used_test(L.used, v);
+                const unsigned pl = P->plabel[lvl];
+                if (ok && pl != LABEL_ANY) ok = r.label == pl;
+                if (ok) ok = r.deg >= P->pdeg[lvl];
+                unsigned long long bm = P->back[lvl];
+                while (bm) {
+                    unsigned j = (unsigned)__builtin_ctzll(bm);
+                    bm &= bm - 1;
+                    if (ok) ok = adjacent(d, W, L.M[j], L.MB[j], L.MD[j], v);
                 }
-                etop += take;
-                c_states += take;
-                L.cur[lvl] = ncur;
+                c_cands += min((unsigned)G, e - c0);
+                unsigned long long acc = group_mask<G>(__ballot(ok), gbase);
+                unsigned cnt = (unsigned)__popcll(acc);
+                if (lvl + 1 == k) {
+                    c_states += cnt;
+                    c_matches += cnt;
+                    if (d.rows && ok) {
+                        unsigned long long slot = atomicAdd(&a.ctr[inst].row_next, 1ull);
+                        if (slot < d.cap_rows) {
+                            uint32_t *row = d.rows + slot * k;
+                            for (unsigned i = 0; i + 1 < k; i++) row[P->order[i]] = L.M[i];
+                            row[P->order[k - 1]] = v;
+                        }
+                    }
+                    L.cur[lvl] = c0 + G;
+                } else {
+                    int room = (int)a.E - (int)etop - (int)(k - 2 - lvl);
+                    unsigned take = cnt;
+                    unsigned long long keep = acc;
+                    unsigned ncur = c0 + G;
+                    if ((int)take > room) {
+                        take = (unsigned)room;
+                        unsigned long long m = acc;
+                        for (unsigned i = 0; i < take; i++) m &= m - 1;
+                        keep = acc & ~m;                       // the first `take` accepted lanes
+                        ncur = c0 + (63u - (unsigned)__clzll(keep)) + 1;
+                    }
+                    if ((keep >> gl) & 1ull) {
+                        unsigned rank = (unsigned)__popcll(keep & ((1ull << gl) - 1));
+                        L.ev[etop + rank] = v;
+                        L.ebg[etop + rank] = r.begin;
+                        L.edg[etop + rank] = r.deg;
+                    }
+                    etop += take;
+                    c_states += take;
+                    L.cur[lvl] = ncur;
+                }
             }
         }
 
@@ -470,10 +632,14 @@ __global__ void __launch_bounds__(256) search_csr(SearchArgs a) {
                 // shallowest frame with untried candidates or a spare accepted one
                 unsigned f = base, kind = 0;
                 for (; f <= lvl; f++) {
-                    if (L.cur[f] < L.end[f]) { kind = 1; break; }
-                    unsigned top = f < lvl ? L.eb[f + 1] : etop;
-                    unsigned live = top - (L.eb[f] + L.dn[f]);
-                    if (live > (f == lvl ? 1u : 0u)) { kind = 2; break; }
+                    if constexpr (DENSE) {
+                        if (D.fc[f] > (f == lvl ? 1u : 0u)) { kind = 2; break; }
+                    } else {
+                        if (L.cur[f] < L.end[f]) { kind = 1; break; }
+                        unsigned top = f < lvl ? L.eb[f + 1] : etop;
+                        unsigned live = top - (L.eb[f] + L.dn[f]);
+                        if (live > (f == lvl ? 1u : 0u)) { kind = 2; break; }
+                    }
                 }
                 if (!kind) continue;
                 unsigned t = 0, okr = 0;
@@ -495,7 +661,13 @@ __global__ void __launch_bounds__(256) search_csr(SearchArgs a) {
                 since_donate = 0;
                 QTask *q = a.queue + (t % QUEUE_SLOTS);
                 unsigned tL, tlo, thi, extra = 0;
-                if (kind == 1) {
+                if constexpr (DENSE) {
+                    extra = pick_lowest(f);
+                    D.fc[f] = D.fc[f] - 1;
+                    tL = f + 1;
+                    tlo = 0;
+                    thi = FULL_RANGE;
+                } else if (kind == 1) {
                     unsigned c = L.cur[f], e = L.end[f];
                     unsigned mid = c + (e - c) / 2;
                     tL = f;
@@ -546,14 +718,14 @@ __global__ void reset_kernel(Sched *s, InstCounters *c, unsigned ninst, QTask *q
     for (unsigned j = i; j < QUEUE_SLOTS; j += stride) q[j].seq = 2 * j;
 }
 
-template <int G>
-hipError_t launch_csr(const SearchArgs &args, int blocks, int threads, size_t lds, hipStream_t s, int num_cus,
-                      uint32_t total_chunks) {
+template <int G, bool DENSE>
+hipError_t launch_g(const SearchArgs &args, int blocks, int threads, size_t lds, hipStream_t s, int num_cus,
+                    uint32_t total_chunks) {
     if (blocks <= 0) {
         // resident blocks only (a persistent grid), and no more than the root
         // chunks can keep busy before work is handed around
         int per_cu = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_csr<G>, threads, lds);
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel<G, DENSE>, threads, lds);
         if (e != hipSuccess) return e;
         if (per_cu < 1) per_cu = 1;
         int units_per_block = threads / G;
@@ -561,11 +733,12 @@ hipError_t launch_csr(const SearchArgs &args, int blocks, int threads, size_t ld
         if (want < 2L * num_cus) want = 2L * num_cus;
         blocks = (int)std::min<long>((long)per_cu * num_cus, want);
     }
-    hipLaunchKernelGGL(search_csr<G>, dim3(blocks), dim3(threads), lds, s, args);
+    hipLaunchKernelGGL((search_kernel<G, DENSE>), dim3(blocks), dim3(threads), lds, s, args);
     return hipGetLastError();
 }
 
 unsigned unit_words(const LaunchCfg &cfg) {
+    if (cfg.dense) return 2 * even(cfg.kmax) + 2 * cfg.kmax * cfg.wmax + 2 * cfg.wmax;
     unsigned E = cfg.kmax + cfg.lanes;
     unsigned UW = (cfg.nmax + 31) / 32;
     return 8 * cfg.kmax + 3 * E + UW + 8;
@@ -603,6 +776,7 @@ hipError_t launch_search(const LaunchCfg &cfg, DevWork &w, uint32_t ninst, uint3
     a.kmax = cfg.kmax;
     a.E = cfg.kmax + cfg.lanes;
     a.UW = (cfg.nmax + 31) / 32;
+    a.W = cfg.dense ? cfg.wmax : 0;
     a.unit_words = unit_words(cfg);
     a.donate = cfg.donate;
     a.state_cap = state_cap;
@@ -611,11 +785,20 @@ hipError_t launch_search(const LaunchCfg &cfg, DevWork &w, uint32_t ninst, uint3
     if (!threads) return hipErrorInvalidValue;   // one unit's LDS does not fit
     size_t lds = search_lds_bytes(cfg);
     int blocks = cfg.blocks;
+    if (cfg.dense) {
+        switch (cfg.lanes) {
+            case 8: return launch_g<8, true>(a, blocks, threads, lds, s, num_cus, total_chunks);
+            case 16: return launch_g<16, true>(a, blocks, threads, lds, s, num_cus, total_chunks);
+            case 32: return launch_g<32, true>(a, blocks, threads, lds, s, num_cus, total_chunks);
+            case 64: return launch_g<64, true>(a, blocks, threads, lds, s, num_cus, total_chunks);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (cfg.lanes) {
-        case 8: return launch_csr<8>(a, blocks, threads, lds, s, num_cus, total_chunks);
-        case 16: return launch_csr<16>(a, blocks, threads, lds, s, num_cus, total_chunks);
-        case 32: return launch_csr<32>(a, blocks, threads, lds, s, num_cus, total_chunks);
-        case 64: return launch_csr<64>(a, blocks, threads, lds, s, num_cus, total_chunks);
+        case 8: return launch_g<8, false>(a, blocks, threads, lds, s, num_cus, total_chunks);
+        case 16: return launch_g<16, false>(a, blocks, threads, lds, s, num_cus, total_chunks);
+        case 32: return launch_g<32, false>(a, blocks, threads, lds, s, num_cus, total_chunks);
+        case 64: return launch_g<64, false>(a, blocks, threads, lds, s, num_cus, total_chunks);
         default: return hipErrorInvalidValue;
     }
 }
