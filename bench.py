@@ -12,7 +12,8 @@ Also reported: the plain single-instance path (one sge_count per pattern) on
 the same patterns, the kernel's algorithmic-byte rate against the HBM peak,
 and the oracle's own rate on this host (a baseline, not the target).
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--extra c4,c1]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--extra c4,c1,c3]
+                    [--c3-patterns 8] [--serve-seconds 10]
 """
 from __future__ import annotations
 
@@ -94,6 +95,131 @@ def run_plain(ctx, torch, jobs, want_states, reps=1):
                 kernel_ms_per_pass=kms / reps)
 
 
+def run_dense(ctx, torch, npat, steps):
+    """Dense workload: the first `npat` RI-DS-SI-FC patterns on G(1000, 0.3),
+    full searches (the oracle checks them on root shards in the tests)."""
+    from paper_1705_09358_amd import synth
+    T = synth.c3_target()
+    th = ctx.load_target(T)
+    insts = [synth.c3_instance(j, 0) for j in range(npat)]
+    jobs = [(th, ctx.load_pattern(i.pattern), i.mode, i.labelled) for i in insts]
+    ctx.set_batch_policy(2)
+    log(f"c3: {npat} dense patterns, warmup")
+    st, res = ctx.batch_run(jobs)
+    ref = [(r.matches, r.states) for r in res]
+    if any(m < 1 for m, _ in ref):
+        raise SystemExit("c3: a planted embedding was not found")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kms = []
+    for _ in range(steps):
+        st, res = ctx.batch_run(jobs)
+        kms.append(res[0].ms_search)
+        if [(r.matches, r.states) for r in res] != ref:
+            raise SystemExit("c3: counts changed between runs")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    states = sum(s for _, s in ref)
+    log(f"c3: plain path")
+    ctx.set_mode(synth.MODE_RIDS_SI_FC)
+    ctx.set_labelled(True)
+    tp = time.perf_counter()
+    for (t, p, _, _), (m, s_) in zip(jobs, ref):
+        r = ctx.count(t, p)
+        if (r.matches, r.states) != (m, s_):
+            raise SystemExit("c3: plain path differs from the batch")
+    plain_el = time.perf_counter() - tp
+    ctx.set_batch_policy(0)
+    kernel_ms = sum(kms) / len(kms)
+    # algorithmic bytes of the dense search: per expansion (2 + back-edges) rows of W words
+    return dict(instances=npat, states_per_step=states, matches_per_step=sum(m for m, _ in ref),
+                states_per_s=states * steps / el, ms_per_step=1000 * el / steps, kernel_ms=kernel_ms,
+                plain_states_per_s=states / plain_el, vs_plain=(states * steps / el) / (states / plain_el))
+
+
+def run_serve(torch, seconds, rate):
+    """Serving workload: resident contact targets (5k-20k nodes), queries of
+    4-64 nodes arriving as a Poisson process; latency = result visible on the
+    host - scheduled arrival."""
+    import numpy as np
+
+    from paper_1705_09358_amd import sge, synth
+    man = load_manifest("c5")
+    log("serve: generating 50 resident targets")
+    targets = [synth.c5_target(t) for t in range(synth.C5_TARGETS)]
+    arrivals = synth.c5_arrivals(seconds, rate)
+    log(f"serve: generating {len(arrivals)} queries")
+    queries = [synth.c5_query(q, targets) for q in range(len(arrivals))]
+    ctx = sge.Context(0)
+    ctx.set_time_limit(30000)
+    ctx.set_state_cap(man["state_cap"])
+    th = [ctx.load_target(T) for T in targets]
+    ph = [ctx.load_pattern(P) for _, P, _ in queries]
+    ctx.serve_start(256, 2 << 30)
+    lat = np.zeros(len(arrivals))
+    res = [None] * len(arrivals)
+    pending = 0
+    tickets = {}
+    busy = 0
+    max_conc = 0
+    log(f"serve: {seconds:.0f} s of arrivals at {rate:.0f}/s")
+    t0 = time.perf_counter()
+    nxt = 0
+    last_print = t0
+    while nxt < len(arrivals) or tickets:
+        now = time.perf_counter() - t0
+        while nxt < len(arrivals) and arrivals[nxt] <= now:
+            t, _, _ = queries[nxt]
+            tk = ctx.serve_submit(th[t], ph[nxt], sge.RIDS_SI_FC, True)
+            if tk is None:
+                busy += 1
+                break                      # not admissible now: retried on the next pass
+            tickets[tk] = nxt
+            nxt += 1
+        max_conc = max(max_conc, len(tickets))
+        for tk in list(tickets):
+            r = ctx.serve_poll(tk)
+            if r is not None:
+                q = tickets.pop(tk)
+                lat[q] = (time.perf_counter() - t0) - arrivals[q]
+                res[q] = r
+        if time.perf_counter() - last_print > 5:
+            last_print = time.perf_counter()
+            log(f"serve: {nxt}/{len(arrivals)} submitted, {len(tickets)} in flight")
+        time.sleep(0.0002)
+    el = time.perf_counter() - t0
+    ctx.serve_stop()
+    for r, w in zip(res, man["instances"]):
+        want = sge.OK if w["status"] == "ok" else sge.E_ABORTED
+        if r.status != want or (want == sge.OK and (r.matches, r.states) != (w["matches"], w["states"])):
+            raise SystemExit("serve: a result differs from the oracle's stored value")
+    ctx.close()
+    ok = [r for r in res if r.status == sge.OK]
+    states = sum(r.states for r in ok)
+    ms = lat * 1000
+    return dict(seconds=seconds, rate_qps=rate, queries=len(arrivals), completed_qps=len(arrivals) / el,
+                p50_ms=float(np.percentile(ms, 50)), p99_ms=float(np.percentile(ms, 99)), max_ms=float(ms.max()),
+                mean_prep_ms=float(np.mean([r.ms_prep for r in res])),
+                states_per_s=states / el, matches_per_s=sum(r.matches for r in ok) / el,
+                aborted=sum(r.status == sge.E_ABORTED for r in res), busy_retries=busy, max_in_flight=max_conc)
+
+
+def measured_traffic():
+    """HBM bytes per launch of the search kernel on this workload, from the
+    committed counter summary -- only while the kernel source is the one that
+    was measured (else None)."""
+    import hashlib
+    import re
+    path = os.path.join(REPO, "profiles", "search_kernel_hbm_traffic_contact3000.md")
+    src = os.path.join(REPO, "paper_1705_09358_amd", "csrc", "sge_search.hip")
+    try:
+        m = re.search(r"traffic_bytes_per_launch=([0-9.eE+]+) kernel_source_sha256=([0-9a-f]+)", open(path).read())
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    return float(m.group(1)) if m and m.group(2) == h else None
+
+
 def cpu_baseline(insts, budget_s=12.0):
     import oracle
     oracle.lib()
@@ -121,9 +247,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--extra", default="", help="comma list of extra workloads: c1, c4")
+    ap.add_argument("--extra", default="c1,c4,c3", help="comma list of extra workloads: c1, c4, c3 ('' for none)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--c3-patterns", type=int, default=4)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only copy a buffer of this many MiB five times (calibrates the HBM byte counters)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of "
@@ -135,6 +265,15 @@ def main():
     from paper_1705_09358_amd import sge
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
+    if a.copy_probe:
+        n = a.copy_probe << 18        # float32 elements
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_MiB": a.copy_probe, "copies": 5}))
+        return
     stream = torch.cuda.Stream()
     man = load_manifest("c2")
     log("generating the c2 workload")
@@ -150,6 +289,11 @@ def main():
             plain = None
         extras = {}
         for cfg in [x for x in a.extra.split(",") if x]:
+            if cfg == "c3":
+                ctx3 = sge.Context(0, stream=stream)
+                extras["c3"] = run_dense(ctx3, torch, a.c3_patterns, max(1, a.steps // 10))
+                ctx3.close()
+                continue
             m2 = load_manifest(cfg)
             log(f"generating the {cfg} workload")
             i2 = instances(cfg, m2)
@@ -165,6 +309,7 @@ def main():
                 extras[cfg]["vs_plain"] = e["states_per_s"] / p2["states_per_s"]
             ctx2.close()
         ctx.close()
+    serve = run_serve(torch, a.serve_seconds, 200.0) if a.serve_seconds > 0 else None
     alg_bytes = man["total_alg_bytes"]
     achieved = alg_bytes / (b["kernel_ms"] / 1000.0) / 1e9
     res = {
@@ -192,7 +337,9 @@ def main():
                                              "kernel_ms_per_pass": plain["kernel_ms_per_pass"]},
         "vs_plain": None if plain is None else b["states_per_s"] / plain["states_per_s"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic()},
+        "p99_ms": None if serve is None else serve["p99_ms"],
+        "serve": serve,
         "extra": extras,
     }
     if not a.no_cpu:
