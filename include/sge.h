@@ -48,7 +48,8 @@ enum {
     SGE_OK = 0,
     SGE_E_INVAL = -1,     /* bad argument or malformed graph                          */
     SGE_E_NOMEM = -2,     /* host or device allocation failed                         */
-    SGE_E_DEVICE = -3,    /* a HIP call failed (message holds the HIP error string)   */
+    SGE_E_DEVICE = -3,    /* a HIP call failed (message holds the HIP error string),
+                             or the search kernel rejected a malformed queued task  */
     SGE_E_OVERFLOW = -4,  /* more matches than rows given: counts are complete, the
                              first cap_rows rows are valid                             */
     SGE_E_ABORTED = -5,   /* states exceeded the cap: counters are partial            */
@@ -70,10 +71,14 @@ enum { SGE_RI = 0, SGE_RIDS = 1, SGE_RIDS_SI = 2, SGE_RIDS_SI_FC = 3 };
  *              the traversal order and the parallel schedule;
  *  candidates  pairs examined (implementation-dependent, for reporting);
  *  steals      tasks moved between search units through the work queue;
+ *  steps       search-unit steps of the launch (a step maps one candidate
+ *              and/or evaluates one group of candidates), for profiling;
  *  ms_prep     host preparation time (order, parents, domains, upload);
- *  ms_search   device time of the search launch. */
+ *  ms_search   device time of the search launch (first block start to
+ *              last wave exit, device clock); for a batch or serve launch it
+ *              is the whole launch's. */
 typedef struct {
-    uint64_t matches, states, candidates, steals;
+    uint64_t matches, states, candidates, steals, steps;
     double ms_prep, ms_search;
 } sge_result;
 
@@ -85,6 +90,11 @@ typedef struct sge_ctx sge_ctx;
 sge_status sge_create(int device, void *hip_stream, sge_ctx **out);
 void sge_destroy(sge_ctx *ctx);
 const char *sge_last_error(const sge_ctx *ctx);
+/* Timing of the context's last count, enumerate or batch launch, from the
+ * device clock, in ms since its first block started: ms[0] until the last
+ * wave exited (the kernel), ms[1] until the last task finished, ms[2] until
+ * termination was detected. */
+sge_status sge_last_launch_timing(const sge_ctx *ctx, double *ms);
 
 /* Load a target graph and keep it resident in device memory (CSR, per-node
  * records and, when the graph is small enough, a dense adjacency bitset).
@@ -167,8 +177,10 @@ sge_status sge_plan_host(uint32_t k, const uint32_t *p_row_ptr, const uint32_t *
                          int mode, int labelled, uint32_t *order, int32_t *parent, uint64_t *dom, int *empty);
 
 /* Tuning knobs (for measurement): lanes per search unit (8, 16, 32 or 64;
- * 0 = automatic), root chunk size (0 = automatic), work donation on/off,
- * dense-bitset search (-1 = automatic, 0 = off, 1 = on). */
+ * 0 = automatic), root chunk size (0 = automatic), work donation (0 = off,
+ * 1 = on with the default period, N > 1 = a unit gives work away at most
+ * once per N of its steps), dense-bitset search (-1 = automatic, 0 = off,
+ * 1 = on). */
 sge_status sge_set_tuning(sge_ctx *ctx, int lanes_per_unit, uint32_t root_chunk, int donate, int dense);
 
 #ifdef __cplusplus

@@ -142,6 +142,12 @@ void sge_destroy(sge_ctx *c) {
 
 const char *sge_last_error(const sge_ctx *c) { return c ? c->err.c_str() : "no context"; }
 
+sge_status sge_last_launch_timing(const sge_ctx *c, double *ms) {
+    if (!c || !ms) return SGE_E_INVAL;
+    for (int i = 0; i < 3; i++) ms[i] = c->last_ms[i];
+    return SGE_OK;
+}
+
 sge_status sge_load_target(sge_ctx *c, uint32_t n, const uint32_t *row_ptr, const uint32_t *col,
                            const uint32_t *labels, uint32_t *handle) {
     if (!c || !handle) return SGE_E_INVAL;
@@ -230,8 +236,9 @@ sge_status sge_set_tuning(sge_ctx *c, int lanes, uint32_t root_chunk, int donate
     if (dense < -1 || dense > 1) return fail(c, SGE_E_INVAL, "dense must be -1, 0 or 1");
     c->lanes = lanes;
     c->root_chunk = root_chunk;
-    c->donate = donate ? 1 : 0;
+    c->donate = donate < 0 ? 0 : donate;
     c->dense = dense;
+    c->batch_tune.clear();
     return SGE_OK;
 }
 
@@ -272,6 +279,7 @@ static sge_status single(sge_ctx *c, uint32_t target, uint32_t pattern, uint32_t
     res->states = out[0].states;
     res->candidates = out[0].candidates;
     res->steals = out[0].steals;
+    res->steps = out[0].steps;
     res->ms_prep = mp;
     res->ms_search = ms;
     if (k == 0 && rows) { /* one empty row: nothing to write */ }

@@ -9,20 +9,6 @@
 
 using namespace sge;
 
-namespace {
-
-struct TuneChoice {
-    int policy = 2;
-    int lanes = 16;
-    uint32_t njobs = 0;
-    bool valid = false;
-};
-
-// Keyed by the batch size: repeated runs of the same workload reuse the choice.
-std::mutex tune_mu;
-std::map<std::pair<const sge_ctx *, uint32_t>, TuneChoice> tune_cache;
-
-}  // namespace
 
 extern "C" {
 
@@ -54,32 +40,27 @@ sge_status sge_batch_run(sge_ctx *c, uint32_t njobs, const sge_job *jobs, sge_re
     int policy = c->batch_policy;
     int saved_lanes = c->lanes;
     if (policy == 0) {
-        TuneChoice tc;
-        {
-            std::lock_guard<std::mutex> g(tune_mu);
-            auto it = tune_cache.find({c, njobs});
-            if (it != tune_cache.end()) tc = it->second;
-        }
-        if (!tc.valid) {
-            // autotune: time each candidate launch shape on this batch
+        auto it = c->batch_tune.find(njobs);   // repeated runs of one workload reuse the choice
+        if (it == c->batch_tune.end()) {
+            // autotune: time each candidate launch shape on this batch; lanes:
+            // the automatic choice (0) and the two widest units
             double best = 1e300;
+            std::pair<int, int> choice{2, 0};
             const int policies[2] = {1, 2};
-            const int lanes[3] = {8, 16, 32};
+            const int lanes[3] = {0, 32, 64};
             for (int p : policies)
                 for (int l : lanes) {
-                    if (saved_lanes && l != saved_lanes) continue;
-                    c->lanes = l;
+                    if (saved_lanes && l != 0) continue;   // a width set by the caller is kept
+                    c->lanes = saved_lanes ? saved_lanes : l;
                     sge_status st = run_instances(c, specs, out, mp, ms, true, p);
-                    if (st != SGE_OK) { c->lanes = saved_lanes; return st; }
-                    if (ms < best) { best = ms; tc.policy = p; tc.lanes = l; }
+                    c->lanes = saved_lanes;
+                    if (st != SGE_OK) return st;
+                    if (ms < best) { best = ms; choice = {p, l}; }
                 }
-            tc.valid = true;
-            tc.njobs = njobs;
-            std::lock_guard<std::mutex> g(tune_mu);
-            tune_cache[{c, njobs}] = tc;
+            it = c->batch_tune.emplace(njobs, choice).first;
         }
-        policy = tc.policy;
-        c->lanes = saved_lanes ? saved_lanes : tc.lanes;
+        policy = it->second.first;
+        c->lanes = saved_lanes ? saved_lanes : it->second.second;
     }
     sge_status st = run_instances(c, specs, out, mp, ms, true, policy);
     c->lanes = saved_lanes;
@@ -90,6 +71,7 @@ sge_status sge_batch_run(sge_ctx *c, uint32_t njobs, const sge_job *jobs, sge_re
         results[i].states = out[i].states;
         results[i].candidates = out[i].candidates;
         results[i].steals = out[i].steals;
+        results[i].steps = out[i].steps;
         results[i].ms_prep = mp;
         results[i].ms_search = ms;
         aborted |= out[i].status == SGE_E_ABORTED;

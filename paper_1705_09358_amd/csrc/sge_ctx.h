@@ -40,7 +40,7 @@ struct InstanceSpec {
 struct InstanceOut {
     sge_status status = SGE_OK;
     bool timed_out = false;
-    uint64_t matches = 0, states = 0, candidates = 0, steals = 0;
+    uint64_t matches = 0, states = 0, candidates = 0, steals = 0, steps = 0;
 };
 
 // Buffers of one launch stream.
@@ -70,6 +70,8 @@ struct sge_ctx {
     int lanes = 0, dense = -1, donate = 1;
     uint32_t root_chunk = 0;
     int batch_policy = 0;
+    // batch autotuner's choice by batch size: (policy, lanes); cleared when tuning changes
+    std::map<uint32_t, std::pair<int, int>> batch_tune;
     int num_cus = 0;
     size_t lds_per_cu = 0;
     std::map<uint32_t, std::unique_ptr<sge::Target>> targets;
@@ -77,6 +79,7 @@ struct sge_ctx {
     uint32_t next_handle = 1;
     sge::LaunchBufs bufs;
     sge::DevBuf d_rows;
+    double last_ms[3] = {0, 0, 0};   // last launch: kernel, until the last task finished, until done was set
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::unique_ptr<sge::Server, sge::ServerDeleter> server;
     std::mutex serve_mu;
@@ -105,6 +108,8 @@ bool plan_instance(const sge_ctx *c, const InstanceSpec &s, bool dense, Plan &pl
 struct Pack {
     LaunchCfg cfg;
     uint32_t m = 0;
+    double ms_work = 0, ms_done = 0;   // filled by read_pack
+    bool bad_task = false;             // filled by read_pack: the work queue delivered an invalid task
     size_t blob = 0, ctr_bytes = 0;
     uint32_t total_chunks = 0;
 };
@@ -117,7 +122,7 @@ sge_status pack_instances(sge_ctx *c, const std::vector<const InstanceSpec *> &s
 // Upload, reset, search and read back on `s` (asynchronous).
 hipError_t enqueue_pack(sge_ctx *c, const Pack &pk, LaunchBufs &bufs, hipStream_t s);
 // After the stream has drained: per-instance results and the kernel time.
-void read_pack(const sge_ctx *c, const Pack &pk, const LaunchBufs &bufs, const std::vector<const InstanceSpec *> &specs,
+void read_pack(const sge_ctx *c, Pack &pk, const LaunchBufs &bufs, const std::vector<const InstanceSpec *> &specs,
                std::vector<InstanceOut *> &out, double &ms_search);
 
 // Device memory for a target's resident data.

@@ -109,44 +109,62 @@ struct InstDesc {
 
 // Per-instance device counters.
 struct InstCounters {
-    unsigned long long matches, states, candidates, steals, row_next, pad0, pad1, pad2;
+    unsigned long long matches, states, candidates, steals, row_next, pad0, steps, pad2;
 };
 
-// Global scheduling words of one launch.  Each word that many waves touch
-// sits on its own 128-byte line.
+constexpr uint32_t QUEUE_GROUPS = 8;                          // work-queue groups
+constexpr uint32_t QUEUE_GROUP_SLOTS = QUEUE_SLOTS / QUEUE_GROUPS;
+constexpr uint32_t TASK_ENTRIES = 16;                        // accepted candidates one task can carry
+constexpr uint32_t DEFAULT_DONATE_PERIOD = 32;               // steps between a unit's donations
+
+// Counters of one work-queue group, each on its own 128-byte line.
+struct QGroup {
+    unsigned int tail;         // producer tickets
+    unsigned int p0[31];
+    unsigned int head;         // consumer tickets
+    unsigned int p1[31];
+    unsigned int avail;        // published, not yet taken
+    unsigned int p2[31];
+    unsigned int free;         // free slots
+    unsigned int p3[31];
+    unsigned int created;      // tasks given away into the queues (monotonic)
+    unsigned int p4[31];
+    unsigned int finished;     // tasks finished, root chunks included (monotonic)
+    unsigned int p5[31];
+};
+
+// Global scheduling words of one launch.
 struct Sched {
     unsigned int chunk_next;   // next root chunk (flattened over instances)
     unsigned int p0[31];
-    unsigned int work;         // outstanding tasks: queued plus in progress
-    unsigned int p1[31];
-    unsigned int q_tail;       // producer tickets of the work queue
-    unsigned int p2[31];
-    unsigned int q_head;       // consumer tickets
-    unsigned int p3[31];
-    unsigned int q_avail;      // published, not yet taken
-    unsigned int p4[31];
-    unsigned int q_free;       // free slots
-    unsigned int p5[31];
-    unsigned int done;         // set once no task is queued, running or unclaimed
+    unsigned int done;         // set once every task is finished
     unsigned int abort;        // set when the launch's time limit is reached
-    unsigned int p6[30];
+    unsigned int bad;          // set when a dequeued task fails validation (never expected)
+    unsigned int p1[29];
     unsigned long long t_start;  // earliest block start (s_memrealtime, 100 MHz)
     unsigned long long t_end;    // latest wave exit
-    unsigned long long p7[14];
+    unsigned long long t_work;   // latest task finish
+    unsigned long long t_done;   // when `done` was set
+    unsigned long long p2[12];
+    QGroup grp[QUEUE_GROUPS];
 };
 
-// One queued task: instance, prefix length L, prefix mapping M[0..L-1] and the
-// candidate range [lo, hi) of position L (hi = 0xFFFFFFFF: the whole list).
+// One queued task: instance, prefix length L and prefix mapping M[0..L-1],
+// and what of position L it covers -- by `kind`: a range [lo, hi) of its
+// candidate list (hi = 0xFFFFFFFF: the whole list); `ne` accepted candidates
+// in `ent` (already counted); or, dense, the words [lo, hi) of its candidate
+// set (already counted).
 struct QTask {
     unsigned int seq;
-    unsigned int inst, L, lo, hi, pad[3];
+    unsigned int inst, L, lo, hi, kind, ne, pad;
     unsigned int M[KMAX];
+    unsigned int ent[TASK_ENTRIES];
 };
 
 struct LaunchCfg {
     int lanes = 16;           // lanes per search unit
     int dense = 0;            // dense-bitset kernel
-    int donate = 1;
+    int donate = 1;            // 0 off, 1 default period, N > 1: period of N steps
     uint32_t kmax = 0, nmax = 0, wmax = 0;
     int blocks = 0;           // 0 = fill the device
     int used_bitset = 1;

@@ -57,8 +57,10 @@ static int auto_lanes(const std::vector<const InstanceSpec *> &specs) {
         deg += (double)s->t->g.col.size();
         cnt += s->t->g.n;
     }
+    // a step evaluates one candidate per lane: wide units pay off once
+    // neighbour lists are longer than a few entries
     double avg = cnt ? deg / (double)cnt : 0;
-    if (avg <= 12) return 32;
+    if (avg <= 6) return 32;
     return 64;
 }
 
@@ -192,20 +194,27 @@ hipError_t enqueue_pack(sge_ctx *c, const Pack &pk, LaunchBufs &bufs, hipStream_
                           s);
 }
 
-void read_pack(const sge_ctx *c, const Pack &pk, const LaunchBufs &bufs, const std::vector<const InstanceSpec *> &specs,
+void read_pack(const sge_ctx *c, Pack &pk, const LaunchBufs &bufs, const std::vector<const InstanceSpec *> &specs,
                std::vector<InstanceOut *> &out, double &ms_search) {
     const InstCounters *hc = (const InstCounters *)bufs.h_ctr.p;
     const Sched *hs = (const Sched *)((const char *)bufs.h_ctr.p + pk.ctr_bytes);
     // kernel time from the device clock (100 MHz): first block start to last wave exit
-    ms_search = hs->t_end > hs->t_start ? (double)(hs->t_end - hs->t_start) / 1e5 : 0.0;
+    auto since = [&](unsigned long long t) { return t > hs->t_start ? (double)(t - hs->t_start) / 1e5 : 0.0; };
+    ms_search = since(hs->t_end);
+    pk.ms_work = since(hs->t_work);
+    pk.ms_done = since(hs->t_done);
+    pk.bad_task = hs->bad != 0;
     for (uint32_t j = 0; j < pk.m; j++) {
         InstanceOut &o = *out[j];
         o.matches = hc[j].matches;
         o.states = hc[j].states;
         o.candidates = hc[j].candidates;
         o.steals = hc[j].steals;
+        o.steps = hc[j].steps;
         o.status = SGE_OK;
-        if (hs->abort) {
+        if (pk.bad_task) {
+            o.status = SGE_E_DEVICE;
+        } else if (hs->abort) {
             o.status = SGE_E_ABORTED;
             o.timed_out = true;
         } else if (c->cap && o.states > c->cap) {
@@ -286,6 +295,10 @@ sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "search");
     }
     read_pack(c, pk, c->bufs, sp, op, ms_search);
+    c->last_ms[0] = ms_search;
+    c->last_ms[1] = pk.ms_work;
+    c->last_ms[2] = pk.ms_done;
+    if (pk.bad_task) return fail(c, SGE_E_DEVICE, "the work queue delivered an invalid task; counters are unreliable");
     if (op[0]->timed_out) c->err = "search stopped at the time limit; counters are partial";
     return SGE_OK;
 }

@@ -3,33 +3,45 @@
 //
 // Search unit.  A unit is a group of G lanes of a 64-lane wavefront (G = 8,
 // 16, 32 or 64); a wave holds 64/G units that advance in lock-step through
-// one loop, each on its own subtree.  A unit owns, in LDS, the mapping M of
-// the current prefix (by order position), one frame per position and a small
-// stack of accepted-but-unexplored candidates.  This is the state space of
-// Section 2.2.1 traversed depth-first, with RI's candidate generation (the
-// target neighbours of the mapped parent; all nodes, or the domain, for a
-// node without a parent) and pruning rules in the paper's order (unused,
-// label, degree, edges to mapped nodes), plus the RI-DS domain test first
-// (Section 4.1).
+// one loop, each on its own subtree.  The traversal is the state space of
+// Section 2.2.1, depth-first, with RI's candidate generation (the target
+// neighbours of the mapped parent; all nodes, or the domain, for a node
+// without a parent) and pruning rules in the paper's order (unused, label,
+// degree, edges to mapped nodes), plus the RI-DS domain test first
+// (Section 4.1).  Two variants share the scheduling loop:
 //
-// One step of a unit: pop exhausted frames; if the current frame has an
-// accepted candidate left, map it and open the next position's frame; then
-// evaluate the next G candidates of the current frame, one per lane, and push
-// the accepted ones (at the last position, count and emit them instead).
-// States are counted when a candidate is pushed (or, at the last position,
-// accepted), so a candidate that did not fit in the stack is evaluated again
-// later without being counted twice.
+//  * CSR (DENSE = false).  A unit owns, in LDS, the mapping M of the current
+//    prefix (by order position), one frame per position and a small stack of
+//    accepted-but-unexplored candidates.  One step: pop exhausted frames; map
+//    the top stacked candidate and open the next position's frame; evaluate
+//    the next G candidates of the current frame, one per lane, and push the
+//    accepted ones (at the last position, count and emit them instead).
+//    States are counted when pushed, so a candidate that did not fit in the
+//    stack is evaluated again later without being counted twice.
+//  * Dense bitsets (DENSE = true).  Each frame holds the accepted candidates
+//    of a position as a bitset over the target nodes; mapping the lowest
+//    member and expanding the next position ANDs the parent's adjacency row,
+//    the position's domain (or label and degree) row, the complement of the
+//    used set and every back-edge row, one 64-bit word per lane, and counts
+//    the result with popcounts.
 //
 // Load balance.  Root candidates (position 0) are handed out in chunks from
 // an atomic counter (the paper's initial distribution, Section 3.3; chunks
-// play the role of task groups, Section 3.4).  Busy units donate work to a
-// global queue when units are idle: the untried remainder of their shallowest
-// open frame, or one accepted candidate of it -- near the root, as in the
-// paper's stealing from the back of a deque (Section 3.2).  A queued task
-// carries its prefix mapping, so only stolen work copies a mapping.
-// Termination: `work` counts queued plus running tasks; it reaches zero only
-// when no unit holds or can create work (replacing the token ring of
-// Section 3.5).
+// play the role of task groups, Section 3.4).  Busy units give work away to
+// work-queue groups when their group runs low, near the root as in the
+// paper's stealing from the back of a deque (Section 3.2), and in bulk: half
+// of the untried candidates of their shallowest open frame, up to 16 of its
+// accepted candidates, or (dense) half of its remaining candidate words.  A
+// queued task carries its prefix mapping, so only moved work copies a
+// mapping (Section 3.1).  A block's home group is blockIdx mod 8; idle units
+// look at their home group first and then at the others.
+//
+// Termination (in place of the token ring of Section 3.5).  Each group counts,
+// monotonically, the tasks given away into it and the tasks finished (root
+// chunks included).  A task is created only by a unit that holds an
+// unfinished task, and every creation precedes its own finish, so once all
+// root chunks are claimed, reading the finished counts and then the created
+// counts and finding finished = chunks + created means no task is left.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -49,18 +61,21 @@ struct SearchArgs {
     unsigned ninst;
     unsigned kmax, E, UW, W, unit_words;
     int donate;
+    unsigned donate_period;           // a unit gives work away at most once per this many of its steps
     unsigned long long state_cap;
     unsigned long long limit_ticks;   // time limit in s_memrealtime ticks (100 MHz); 0 = none
 };
 
 constexpr unsigned FULL_RANGE = 0xFFFFFFFFu;
 constexpr unsigned NO_TASK = 0xFFFFFFFFu;
+constexpr unsigned NO_GROUP = 0xFFFFFFFFu;
+// task kinds (QTask::kind)
+constexpr unsigned TK_RANGE = 0;     // CSR: candidates [lo, hi) of position L; dense: expand position L
+constexpr unsigned TK_ENTRIES = 1;   // CSR: `ne` accepted candidates of position L
+constexpr unsigned TK_WINDOW = 2;    // dense: words [lo, hi) of position L's candidate set
 
 __device__ __forceinline__ unsigned ld_rlx(const unsigned *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned ld_acq(const unsigned *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_rlx(unsigned *p, unsigned v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -70,9 +85,6 @@ __device__ __forceinline__ void st_rel(unsigned *p, unsigned v) {
 }
 __device__ __forceinline__ unsigned fadd(unsigned *p, unsigned v) {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned fadd_ar(unsigned *p, unsigned v) {
-    return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ unsigned long long fadd64(unsigned long long *p, unsigned long long v) {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -86,18 +98,17 @@ __device__ __forceinline__ bool cas_dec_if_pos(unsigned *p) {
     }
     return false;
 }
-__device__ __forceinline__ void fence_acq() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
-__device__ __forceinline__ void fence_rel() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
-
-// Termination.  `work` counts queued plus running tasks; a root chunk is
-// counted before it is claimed.  The unit whose decrement empties `work`
-// checks, in this order, that every root chunk has been claimed and that
-// `work` is still zero: a claim seen by the first load had already counted
-// itself, so a zero after it means no task is left anywhere.
-__device__ __forceinline__ void release_task(Sched *S, unsigned nchunks) {
-    if (fadd(&S->work, (unsigned)-1) == 1) {
-        if (ld_acq(&S->chunk_next) >= nchunks && ld_acq(&S->work) == 0) st_rel(&S->done, 1u);
-    }
+// Waits until every memory operation this wave has issued is complete.
+// Queue payloads and scheduler counters are read and written only with
+// agent-scope atomics, which are coherent across the XCDs' L2 caches, so a
+// completed store is visible to every later agent-scope load.  Ordering them
+// with this wait instead of agent-scope fences keeps the L2 of the XCD intact:
+// an acquire fence invalidates it and a release fence writes it back, and at
+// the rate tasks move that costs the searching waves their cached graph.
+__device__ __forceinline__ void vm_drain() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 // Orders LDS accesses between lanes of one wavefront (no instruction is
@@ -117,17 +128,22 @@ __device__ __forceinline__ unsigned long long group_mask(unsigned long long ball
     else return (ballot >> gbase) & ((1ull << G) - 1);
 }
 
-// Per-unit LDS arrays.
+template <int G>
+__device__ __forceinline__ unsigned group_sum(unsigned x) {
+    for (int o = G / 2; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+// Per-unit LDS arrays of the CSR variant.
 struct UnitLds {
     unsigned *M, *MB, *MD;        // mapping by position, row start and degree of M[i]
     unsigned *cur, *end, *lb;     // frame: next candidate index, list length, list start
     unsigned *eb, *dn;            // frame: first stack entry, entries given away from the bottom
     unsigned *ev, *ebg, *edg;     // stack of accepted candidates: node, row start, degree
     unsigned *used;               // bitset of mapped target nodes
-    unsigned *misc;               // group broadcast scratch
 };
 
-__device__ __forceinline__ UnitLds carve(unsigned *base, unsigned kmax, unsigned E, unsigned UW) {
+__device__ __forceinline__ UnitLds carve(unsigned *base, unsigned kmax, unsigned E) {
     UnitLds u;
     u.M = base;
     u.MB = u.M + kmax;
@@ -141,14 +157,14 @@ __device__ __forceinline__ UnitLds carve(unsigned *base, unsigned kmax, unsigned
     u.ebg = u.ev + E;
     u.edg = u.ebg + E;
     u.used = u.edg + E;
-    u.misc = u.used + UW;
     return u;
 }
 
-// Per-unit LDS arrays of the dense kernel.
+// Per-unit LDS arrays of the dense variant.
 struct DenseLds {
     unsigned *M;                  // mapping by position
     unsigned *fc;                 // frame: number of candidates left
+    unsigned *hw;                 // frame: words at or above this index were given away
     unsigned long long *cand;     // frame: candidate set, kmax rows of W words
     unsigned long long *used;     // bitset of mapped target nodes (W words)
 };
@@ -159,7 +175,8 @@ __device__ __forceinline__ DenseLds carve_dense(unsigned *base, unsigned kmax, u
     DenseLds u;
     u.M = base;
     u.fc = u.M + even(kmax);
-    u.cand = reinterpret_cast<unsigned long long *>(u.fc + even(kmax));
+    u.hw = u.fc + even(kmax);
+    u.cand = reinterpret_cast<unsigned long long *>(u.hw + even(kmax));
     u.used = u.cand + (size_t)kmax * W;
     return u;
 }
@@ -180,12 +197,6 @@ __device__ __forceinline__ bool adjacent(const InstDesc &d, unsigned W, unsigned
     return lo < b + deg && d.col[lo] == v;
 }
 
-// DENSE = false: candidate lists (CSR rows) evaluated G at a time, accepted
-// candidates kept on a per-unit stack.  DENSE = true: each frame holds the set
-// of accepted candidates as a bitset over the target nodes; expanding a mapped
-// node ANDs the parent's adjacency row, the position's domain (or label and
-// degree) row, the complement of the used set and every back-edge row, one
-// 64-bit word per lane, and counts the result with popcounts.
 template <int G, bool DENSE>
 __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
     extern __shared__ unsigned lds[];
@@ -200,7 +211,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
         for (unsigned i = gl; i < a.W; i += G) D.used[i] = 0;
         L.M = D.M;
     } else {
-        L = carve(lds + (size_t)unit * a.unit_words, a.kmax, a.E, a.UW);
+        L = carve(lds + (size_t)unit * a.unit_words, a.kmax, a.E);
         for (unsigned i = gl; i < a.UW; i += G) L.used[i] = 0;
     }
     const unsigned WS = a.W;   // LDS row stride of the dense frames
@@ -212,16 +223,20 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
         if (lane == 0) atomicMax(&S->t_end, now_ticks());
         return;
     }
+    const unsigned home = blockIdx.x % QUEUE_GROUPS;
+    QGroup *HG = &S->grp[home];
+    const bool checker = blockIdx.x == 0 && threadIdx.x < 64;   // the wave that detects termination
 
     // unit state (identical in the G lanes of a unit)
     unsigned inst = NO_TASK, cinst = NO_TASK, lvl = 0, base = 0, etop = 0, k = 0, W = 0;
     InstDesc d{};
     const DevPlan *P = nullptr;
-    unsigned long long c_states = 0, c_matches = 0, c_cands = 0, c_steals = 0;
+    unsigned long long c_states = 0, c_matches = 0, c_cands = 0, c_steals = 0, c_steps = 0;
     bool roots_done = false;
     unsigned since_donate = 0;     // steps since this unit's task began or it last gave work away
-    unsigned iter = 0, backoff = 0;
+    unsigned iter = 0, backoff = 0, polls = 0;
     bool donate_hint = false;
+    unsigned long long last_finish = 0;   // device clock of this wave's last task finish
     // every wave ends by the deadline, whatever the state of the search
     const unsigned long long deadline = a.limit_ticks ? now_ticks() + a.limit_ticks : ~0ull;
 
@@ -231,13 +246,14 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
             if (c_matches) fadd64(&c->matches, c_matches);
             if (c_cands) fadd64(&c->candidates, c_cands);
             if (c_steals) fadd64(&c->steals, c_steals);
+            if (c_steps) fadd64(&c->steps, c_steps);
             if (c_states) {
                 unsigned long long before = fadd64(&c->states, c_states);
                 if (a.state_cap && before + c_states > a.state_cap)
                     __hip_atomic_store(&c->pad0, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        c_states = c_matches = c_cands = c_steals = 0;
+        c_states = c_matches = c_cands = c_steals = c_steps = 0;
     };
     auto inst_aborted = [&](unsigned i) -> bool {
         unsigned long long f = 0;
@@ -257,7 +273,6 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
         L.eb[pos] = etop;
         L.dn[pos] = 0;
     };
-    // give up the current task (used bits of the mapped prefix are cleared)
     auto mark = [&](unsigned v) {
         if constexpr (DENSE) atomicOr(&D.used[v >> 6], 1ull << (v & 63));
         else atomicOr(&L.used[v >> 5], 1u << (v & 31));
@@ -287,8 +302,9 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
         return v == 0xFFFFFFFFu ? 0u : v;
     };
     // dense: candidates of position `pos` given M[0..pos-1]; at the last position
-    // they are counted (and emitted) as matches, otherwise they become frame pos
-    auto expand = [&](unsigned pos) {
+    // they are counted (and emitted) as matches, otherwise they become frame pos.
+    // `count` = false for a set that was counted by the unit that gave it away.
+    auto expand = [&](unsigned pos, bool count) {
         const int p = P->parent[pos];
         const unsigned mp = p >= 0 ? D.M[p] : 0u;
         const unsigned long long bmask = P->back[pos];
@@ -317,7 +333,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
                 }
                 if (!last) D.cand[(size_t)pos * WS + w] = x;
                 cnt += (unsigned)__popcll(x);
-                if (last && d.rows) {
+                if (last && count && d.rows) {
                     for (unsigned long long y = x; y; y &= y - 1) {
                         const unsigned v = w * 64 + (unsigned)__builtin_ctzll(y);
                         unsigned long long slot = atomicAdd(&a.ctr[inst].row_next, 1ull);
@@ -330,15 +346,22 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
                 }
             }
         }
-        for (int o = G / 2; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-        c_states += cnt;
-        if (last) c_matches += cnt;
+        cnt = group_sum<G>(cnt);
+        if (count) {
+            c_states += cnt;
+            if (last) c_matches += cnt;
+        }
         D.fc[pos] = last ? 0u : cnt;
+        D.hw[pos] = W;
     };
+    // finish the current task (used bits of the mapped prefix are cleared)
     auto drop_task = [&](unsigned mapped) {
         WAVE_SYNC();
         for (unsigned i = gl; i < mapped; i += G) unmark(L.M[i]);
-        if (gl == 0) release_task(S, nchunks);
+        // a unit that gave work away during the task has already waited for
+        // that task's `created` count to complete
+        if (gl == 0) fadd(&HG->finished, 1);
+        last_finish = now_ticks();
         inst = NO_TASK;
         etop = 0;
     };
@@ -350,51 +373,74 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
         // ------------------------------------------------ poll the scheduler (one lane per wave)
         const bool poll = idle_b != 0 && (wave_idle || (iter & 31) == 0);
         if (poll || (iter & 63) == 0) {
-            unsigned flags = 0, av = 0, cn = 0, fr = 0;
+            unsigned flags = 0, src = NO_GROUP, cn = 0;
             if (lane == 0) {
+                polls++;
                 if (now_ticks() > deadline) {
                     st_rlx(&S->abort, 1u);
                     flags |= 1;
                 }
                 if (ld_rlx(&S->abort)) flags |= 1;
                 if (ld_rlx(&S->done)) flags |= 2;
-                av = ld_rlx(&S->q_avail);
                 cn = ld_rlx(&S->chunk_next);
-                fr = ld_rlx(&S->q_free);
+                const unsigned av = ld_rlx(&HG->avail);
+                const unsigned fr = ld_rlx(&HG->free);
+                if (av) src = home;
+                // give work away only once the roots are all claimed and the home group runs low
+                if (cn >= nchunks && av < 4 && fr > 32) flags |= 4;
+                if (poll && !av && cn >= nchunks) {
+                    for (unsigned g = 1; g < QUEUE_GROUPS && src == NO_GROUP; g++) {
+                        const unsigned gg = (home + g) % QUEUE_GROUPS;
+                        if (ld_rlx(&S->grp[gg].avail)) src = gg;
+                    }
+                    if (checker && src == NO_GROUP && wave_idle && (polls & 3) == 0) {
+                        // termination check (one wave of the grid): finished counts
+                        // first, then created counts.  A giver's `created` increment
+                        // completes before its task is published, hence before any
+                        // finish it precedes; the created counts are read only
+                        // after the finished counts have arrived.
+                        unsigned fin = 0, cre = 0;
+                        for (unsigned g = 0; g < QUEUE_GROUPS; g++) fin += ld_rlx(&S->grp[g].finished);
+                        vm_drain();
+                        for (unsigned g = 0; g < QUEUE_GROUPS; g++) cre += ld_rlx(&S->grp[g].created);
+                        if (fin == nchunks + cre) {
+                            st_rel(&S->done, 1u);
+                            atomicMax(&S->t_done, now_ticks());
+                            flags |= 2;
+                        }
+                    }
+                }
             }
             flags = __shfl(flags, 0);
-            av = __shfl(av, 0);
+            src = __shfl(src, 0);
             cn = __shfl(cn, 0);
-            fr = __shfl(fr, 0);
             if (flags & 1) break;                    // time limit: every wave stops
             if ((flags & 2) && wave_idle) break;     // the search is complete
-            // give work away only once the roots are all claimed and the queue runs low
-            donate_hint = a.donate && cn >= nchunks && av < 64 && fr > 256;
-            if (poll && (av > 0 || cn < nchunks)) {
+            donate_hint = a.donate && (flags & 4);
+            if (poll && (src != NO_GROUP || cn < nchunks)) {
                 // ---------------------------------------- task acquisition, one unit at a time
                 for (int g = 0; g < 64 / G; g++) {
                     if (!(inst == NO_TASK && (lane / G) == g)) continue;
                     unsigned kind = 0, val = 0;
                     if (gl == 0) {
-                        if (av > 0 && cas_dec_if_pos(&S->q_avail)) {
-                            unsigned t = fadd(&S->q_head, 1);
-                            unsigned slot = t % QUEUE_SLOTS;
+                        if (src != NO_GROUP && cas_dec_if_pos(&S->grp[src].avail)) {
+                            unsigned t = fadd(&S->grp[src].head, 1);
+                            QTask *q = a.queue + src * QUEUE_GROUP_SLOTS + t % QUEUE_GROUP_SLOTS;
                             kind = 1;
-                            while (ld_rlx(&a.queue[slot].seq) != 2 * t + 1) {
+                            // the payload loads below are issued after this load has
+                            // returned the published sequence number
+                            while (ld_rlx(&q->seq) != 2 * t + 1) {
                                 __builtin_amdgcn_s_sleep(1);
                                 if (now_ticks() > deadline) { kind = 0; break; }
                             }
-                            fence_acq();
                             val = t;
                         } else if (!roots_done && cn < nchunks) {
-                            fadd(&S->work, 1);
-                            unsigned c = fadd_ar(&S->chunk_next, 1);
+                            unsigned c = fadd(&S->chunk_next, 1);
                             if (c < nchunks) {
                                 kind = 2;
                                 val = c;
                             } else {
                                 roots_done = true;
-                                release_task(S, nchunks);
                             }
                         }
                     }
@@ -402,18 +448,54 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
                     val = __shfl(val, gbase);
                     roots_done = __shfl((int)roots_done, gbase) != 0;
                     if (kind == 0) continue;
-                    unsigned ti = 0, tL = 0, tlo = 0, thi = 0;
+                    unsigned ti = 0, tL = 0, tlo = 0, thi = 0, tkind = TK_RANGE, tne = 0;
                     if (kind == 1) {
-                        QTask *q = a.queue + (val % QUEUE_SLOTS);
-                        ti = q->inst;
-                        tL = q->L;
-                        tlo = q->lo;
-                        thi = q->hi;
-                        for (unsigned i = gl; i < tL; i += G) L.M[i] = q->M[i];
-                        fence_rel();
+                        QTask *q = a.queue + src * QUEUE_GROUP_SLOTS + val % QUEUE_GROUP_SLOTS;
+                        ti = ld_rlx(&q->inst);
+                        tL = ld_rlx(&q->L);
+                        tlo = ld_rlx(&q->lo);
+                        thi = ld_rlx(&q->hi);
+                        tkind = ld_rlx(&q->kind);
+                        tne = ld_rlx(&q->ne);
+                        // a task is checked before any of it is used: instance, prefix
+                        // length and every node it names must be in range
+                        bool bad = ti >= a.ninst || tkind > TK_WINDOW || tne > TASK_ENTRIES;
+                        unsigned tn = 0;
+                        if (!bad) {
+                            const DevPlan *tp = a.inst[ti].plan;
+                            tn = tp->n;
+                            bad = tL >= tp->k || (tkind == TK_WINDOW && (tlo > thi || thi > tp->W));
+                        }
+                        if (!bad) {
+                            bool bl = false;
+                            for (unsigned i = gl; i < tL; i += G) {
+                                const unsigned v = ld_rlx(&q->M[i]);
+                                bl |= v >= tn;
+                                L.M[i] = v;
+                            }
+                            if constexpr (!DENSE) {
+                                for (unsigned i = gl; i < tne; i += G) {
+                                    const unsigned v = ld_rlx(&q->ent[i]);
+                                    bl |= v >= tn;
+                                    L.ev[i] = v;
+                                }
+                            }
+                            bad = group_mask<G>(__ballot(bl), gbase) != 0;
+                        }
+                        // the payload loads have completed (their values are in
+                        // registers and LDS) before the slot is handed back
+                        vm_drain();
+                        WAVE_SYNC();
                         if (gl == 0) {
-                            st_rlx(&q->seq, 2 * (val + QUEUE_SLOTS));
-                            fadd(&S->q_free, 1);
+                            st_rlx(&q->seq, 2 * (val + QUEUE_GROUP_SLOTS));
+                            fadd(&S->grp[src].free, 1);
+                        }
+                        if (bad) {   // reported to the host; the task counts as finished
+                            if (gl == 0) {
+                                st_rlx(&S->bad, 1u);
+                                fadd(&HG->finished, 1);
+                            }
+                            continue;
                         }
                     } else {
                         unsigned lo = 0, hi = a.ninst;   // largest i with prefix[i] <= val
@@ -443,7 +525,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
                     if (kind == 1) c_steals++;
                     etop = 0;
                     if (a.state_cap && inst_aborted(inst)) {   // capped instance: drop the task
-                        if (gl == 0) release_task(S, nchunks);
+                        if (gl == 0) fadd(&HG->finished, 1);
                         inst = NO_TASK;
                         continue;
                     }
@@ -451,7 +533,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
                         for (unsigned i = gl; i < tL; i += G) mark(D.M[i]);
                         WAVE_SYNC();
                         base = lvl = tL;
-                        if (tL == 0) {
+                        if (kind == 2) {
                             // a root chunk: its list entries are the accepted candidates of position 0
                             for (unsigned w = gl; w < W; w += G) D.cand[w] = 0ull;
                             WAVE_SYNC();
@@ -468,8 +550,24 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
                             c_states += cnt;
                             if (k == 1) c_matches += cnt;
                             D.fc[0] = k == 1 ? 0u : cnt;
+                            D.hw[0] = W;
+                        } else if (tkind == TK_WINDOW) {
+                            // words [tlo, thi) of position tL's candidate set, counted by the giver
+                            expand(tL, false);
+                            unsigned cnt = 0;
+                            for (unsigned r = 0; r * G < W; r++) {
+                                const unsigned w = r * G + gl;
+                                if (w < W) {
+                                    unsigned long long x = D.cand[(size_t)tL * WS + w];
+                                    if (w < tlo || w >= thi) x = 0ull;
+                                    D.cand[(size_t)tL * WS + w] = x;
+                                    cnt += (unsigned)__popcll(x);
+                                }
+                            }
+                            D.fc[tL] = group_sum<G>(cnt);
+                            D.hw[tL] = thi;
                         } else {
-                            expand(tL);
+                            expand(tL, true);
                         }
                         WAVE_SYNC();
                     } else {
@@ -482,7 +580,19 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
                         }
                         WAVE_SYNC();
                         base = lvl = tL;
-                        open_frame(tL, tlo, thi);
+                        if (kind == 1 && tkind == TK_ENTRIES) {
+                            // accepted candidates of position tL, counted by the giver
+                            open_frame(tL, 0, 0);
+                            for (unsigned i = gl; i < tne; i += G) {
+                                const unsigned v = L.ev[i];
+                                const NodeRec r = d.node[v];
+                                L.ebg[i] = r.begin;
+                                L.edg[i] = r.deg;
+                            }
+                            etop = tne;
+                        } else {
+                            open_frame(tL, tlo, thi);
+                        }
                     }
                 }
             }
@@ -499,6 +609,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
         // ------------------------------------------------ one search step
         WAVE_SYNC();
         since_donate++;
+        c_steps++;
         if constexpr (DENSE) {
             // pop exhausted frames
             bool task_done = false;
@@ -519,7 +630,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
             D.M[lvl] = v;
             if (gl == 0) mark(v);
             WAVE_SYNC();
-            expand(lvl + 1);
+            expand(lvl + 1, true);
             if (lvl + 2 == k) {
                 if (gl == 0) unmark(v);   // the last position was counted; stay on this frame
             } else {
@@ -554,65 +665,63 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
                 open_frame(lvl, 0, FULL_RANGE);
             }
             // evaluate up to G candidates of the current frame
-            {
-                const unsigned c0 = L.cur[lvl], e = L.end[lvl], lb = L.lb[lvl];
-                const unsigned idx = c0 + gl;
-                bool ok = idx < e;
-                const bool has_parent = P->parent[lvl] >= 0;
-                unsigned v = 0;
-                NodeRec r{0, 0, 0, 0};
-                if (ok) {
-                    v = has_parent ? d.col[lb + idx] : d.lists[lb + idx];
-                    r = d.node[v];
-                }
-                if (ok && d.bits) ok = (d.bits[(size_t)lvl * W + (v >> 6)] >> (v & 63)) & 1ull;
-                if (ok) ok = !used_test(L.used, v);
-                const unsigned pl = P->plabel[lvl];
-                if (ok && pl != LABEL_ANY) ok = r.label == pl;
-                if (ok) ok = r.deg >= P->pdeg[lvl];
-                unsigned long long bm = P->back[lvl];
-                while (bm) {
-                    unsigned j = (unsigned)__builtin_ctzll(bm);
-                    bm &= bm - 1;
-                    if (ok) ok = adjacent(d, W, L.M[j], L.MB[j], L.MD[j], v);
-                }
-                c_cands += min((unsigned)G, e - c0);
-                unsigned long long acc = group_mask<G>(__ballot(ok), gbase);
-                unsigned cnt = (unsigned)__popcll(acc);
-                if (lvl + 1 == k) {
-                    c_states += cnt;
-                    c_matches += cnt;
-                    if (d.rows && ok) {
-                        unsigned long long slot = atomicAdd(&a.ctr[inst].row_next, 1ull);
-                        if (slot < d.cap_rows) {
-                            uint32_t *row = d.rows + slot * k;
-                            for (unsigned i = 0; i + 1 < k; i++) row[P->order[i]] = L.M[i];
-                            row[P->order[k - 1]] = v;
-                        }
+            const unsigned c0 = L.cur[lvl], e = L.end[lvl], lb = L.lb[lvl];
+            const unsigned idx = c0 + gl;
+            bool ok = idx < e;
+            const bool has_parent = P->parent[lvl] >= 0;
+            unsigned v = 0;
+            NodeRec r{0, 0, 0, 0};
+            if (ok) {
+                v = has_parent ? d.col[lb + idx] : d.lists[lb + idx];
+                r = d.node[v];
+            }
+            if (ok && d.bits) ok = (d.bits[(size_t)lvl * W + (v >> 6)] >> (v & 63)) & 1ull;
+            if (ok) ok = !used_test(L.used, v);
+            const unsigned pl = P->plabel[lvl];
+            if (ok && pl != LABEL_ANY) ok = r.label == pl;
+            if (ok) ok = r.deg >= P->pdeg[lvl];
+            unsigned long long bm = P->back[lvl];
+            while (bm) {
+                unsigned j = (unsigned)__builtin_ctzll(bm);
+                bm &= bm - 1;
+                if (ok) ok = adjacent(d, W, L.M[j], L.MB[j], L.MD[j], v);
+            }
+            c_cands += min((unsigned)G, e - c0);
+            unsigned long long acc = group_mask<G>(__ballot(ok), gbase);
+            unsigned cnt = (unsigned)__popcll(acc);
+            if (lvl + 1 == k) {
+                c_states += cnt;
+                c_matches += cnt;
+                if (d.rows && ok) {
+                    unsigned long long slot = atomicAdd(&a.ctr[inst].row_next, 1ull);
+                    if (slot < d.cap_rows) {
+                        uint32_t *row = d.rows + slot * k;
+                        for (unsigned i = 0; i + 1 < k; i++) row[P->order[i]] = L.M[i];
+                        row[P->order[k - 1]] = v;
                     }
-                    L.cur[lvl] = c0 + G;
-                } else {
-                    int room = (int)a.E - (int)etop - (int)(k - 2 - lvl);
-                    unsigned take = cnt;
-                    unsigned long long keep = acc;
-                    unsigned ncur = c0 + G;
-                    if ((int)take > room) {
-                        take = (unsigned)room;
-                        unsigned long long m = acc;
-                        for (unsigned i = 0; i < take; i++) m &= m - 1;
-                        keep = acc & ~m;                       // the first `take` accepted lanes
-                        ncur = c0 + (63u - (unsigned)__clzll(keep)) + 1;
-                    }
-                    if ((keep >> gl) & 1ull) {
-                        unsigned rank = (unsigned)__popcll(keep & ((1ull << gl) - 1));
-                        L.ev[etop + rank] = v;
-                        L.ebg[etop + rank] = r.begin;
-                        L.edg[etop + rank] = r.deg;
-                    }
-                    etop += take;
-                    c_states += take;
-                    L.cur[lvl] = ncur;
                 }
+                L.cur[lvl] = c0 + G;
+            } else {
+                int room = (int)a.E - (int)etop - (int)(k - 2 - lvl);
+                unsigned take = cnt;
+                unsigned long long keep = acc;
+                unsigned ncur = c0 + G;
+                if ((int)take > room) {
+                    take = (unsigned)room;
+                    unsigned long long m = acc;
+                    for (unsigned i = 0; i < take; i++) m &= m - 1;
+                    keep = acc & ~m;                       // the first `take` accepted lanes
+                    ncur = c0 + (63u - (unsigned)__clzll(keep)) + 1;
+                }
+                if ((keep >> gl) & 1ull) {
+                    unsigned rank = (unsigned)__popcll(keep & ((1ull << gl) - 1));
+                    L.ev[etop + rank] = v;
+                    L.ebg[etop + rank] = r.begin;
+                    L.edg[etop + rank] = r.deg;
+                }
+                etop += take;
+                c_states += take;
+                L.cur[lvl] = ncur;
             }
         }
 
@@ -625,15 +734,15 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
             }
         }
 
-        // ------------------------------------------------ donation (one unit at a time)
-        if (donate_hint && (iter & 15) == 0 && __ballot(since_donate >= 256) != 0) {
+        // ------------------------------------------------ giving work away (one unit at a time)
+        if (donate_hint && (iter & 7) == 0 && __ballot(since_donate >= a.donate_period) != 0) {
             for (int g = 0; g < 64 / G; g++) {
-                if (!((lane / G) == g && inst != NO_TASK && since_donate >= 256)) continue;
-                // shallowest frame with untried candidates or a spare accepted one
+                if (!((lane / G) == g && inst != NO_TASK && since_donate >= a.donate_period)) continue;
+                // the shallowest frame with something to spare
                 unsigned f = base, kind = 0;
                 for (; f <= lvl; f++) {
                     if constexpr (DENSE) {
-                        if (D.fc[f] > (f == lvl ? 1u : 0u)) { kind = 2; break; }
+                        if (D.fc[f] > (f == lvl ? 1u : 0u)) { kind = 1; break; }
                     } else {
                         if (L.cur[f] < L.end[f]) { kind = 1; break; }
                         unsigned top = f < lvl ? L.eb[f + 1] : etop;
@@ -642,64 +751,121 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
                     }
                 }
                 if (!kind) continue;
+                since_donate = 0;
                 unsigned t = 0, okr = 0;
                 if (gl == 0) {
-                    if (cas_dec_if_pos(&S->q_free)) {
-                        fadd(&S->work, 1);
-                        t = fadd(&S->q_tail, 1);
+                    if (cas_dec_if_pos(&HG->free)) {
+                        fadd(&HG->created, 1);
+                        t = fadd(&HG->tail, 1);
                         okr = 1;
-                        while (ld_rlx(&a.queue[t % QUEUE_SLOTS].seq) != 2 * t) {
+                        QTask *qq = a.queue + home * QUEUE_GROUP_SLOTS + t % QUEUE_GROUP_SLOTS;
+                        // the slot is free once its previous payload was read; the
+                        // new payload is written only after that is observed
+                        while (ld_rlx(&qq->seq) != 2 * t) {
                             __builtin_amdgcn_s_sleep(1);
                             if (now_ticks() > deadline) { okr = 0; break; }
                         }
-                        fence_acq();
                     }
                 }
                 if (!__shfl(okr, gbase)) continue;
                 t = __shfl(t, gbase);
                 WAVE_SYNC();
-                since_donate = 0;
-                QTask *q = a.queue + (t % QUEUE_SLOTS);
-                unsigned tL, tlo, thi, extra = 0;
+                QTask *q = a.queue + home * QUEUE_GROUP_SLOTS + t % QUEUE_GROUP_SLOTS;
+                unsigned tL = f, tlo = 0, thi = FULL_RANGE, tkind = TK_RANGE, tne = 0, extra = 0;
                 if constexpr (DENSE) {
-                    extra = pick_lowest(f);
-                    D.fc[f] = D.fc[f] - 1;
-                    tL = f + 1;
-                    tlo = 0;
-                    thi = FULL_RANGE;
+                    // half of the frame's remaining words above its lowest nonzero
+                    // word (within the words it still owns), else its lowest candidate
+                    const unsigned hw = D.hw[f];
+                    unsigned w0 = hw, nz_hi = 0;
+                    for (unsigned r = 0; r * G < hw; r++) {
+                        const unsigned w = r * G + gl;
+                        const bool nz = w < hw && D.cand[(size_t)f * WS + w] != 0ull;
+                        const unsigned long long b = group_mask<G>(__ballot(nz), gbase);
+                        if (b && w0 == hw) w0 = r * G + (unsigned)__builtin_ctzll(b);
+                    }
+                    for (unsigned r = 0; r * G < hw; r++) {
+                        const unsigned w = r * G + gl;
+                        if (w < hw && w > w0 && D.cand[(size_t)f * WS + w] != 0ull) nz_hi++;
+                    }
+                    nz_hi = group_sum<G>(nz_hi);
+                    if (nz_hi) {
+                        unsigned wmid = w0 + 1 + (hw - w0 - 1) / 2;
+                        unsigned moved = 0;
+                        for (unsigned r = 0; r * G < hw; r++) {
+                            const unsigned w = r * G + gl;
+                            if (w < hw && w >= wmid) moved += (unsigned)__popcll(D.cand[(size_t)f * WS + w]);
+                        }
+                        moved = group_sum<G>(moved);
+                        if (!moved) {
+                            wmid = w0 + 1;
+                            for (unsigned r = 0; r * G < hw; r++) {
+                                const unsigned w = r * G + gl;
+                                if (w < hw && w >= wmid) moved += (unsigned)__popcll(D.cand[(size_t)f * WS + w]);
+                            }
+                            moved = group_sum<G>(moved);
+                        }
+                        WAVE_SYNC();
+                        for (unsigned r = 0; r * G < hw; r++) {
+                            const unsigned w = r * G + gl;
+                            if (w < hw && w >= wmid) D.cand[(size_t)f * WS + w] = 0ull;
+                        }
+                        D.fc[f] = D.fc[f] - moved;
+                        D.hw[f] = wmid;
+                        tkind = TK_WINDOW;
+                        tlo = wmid;
+                        thi = hw;
+                    } else {
+                        extra = pick_lowest(f);
+                        D.fc[f] = D.fc[f] - 1;
+                        tL = f + 1;
+                    }
                 } else if (kind == 1) {
+                    // the untried upper half of the frame's candidate range
                     unsigned c = L.cur[f], e = L.end[f];
                     unsigned mid = c + (e - c) / 2;
-                    tL = f;
                     tlo = mid;
                     thi = e;
                     L.end[f] = mid;
                 } else {
-                    unsigned idx = L.eb[f] + L.dn[f];
-                    L.dn[f] = L.dn[f] + 1;
-                    extra = L.ev[idx];
-                    tL = f + 1;
-                    tlo = 0;
-                    thi = FULL_RANGE;
+                    // up to TASK_ENTRIES accepted candidates from the bottom of the frame
+                    unsigned top = f < lvl ? L.eb[f + 1] : etop;
+                    unsigned live = top - (L.eb[f] + L.dn[f]);
+                    tne = f < lvl ? (live + 1) / 2 : live / 2;
+                    // the receiver holds them on its stack and still needs a slot
+                    // for each deeper position: at most E - k + f + 3 of them
+                    tne = min(min(tne, TASK_ENTRIES), a.E + f + 3 - k);
+                    const unsigned b0 = L.eb[f] + L.dn[f];
+                    for (unsigned i = gl; i < tne; i += G) st_rlx(&q->ent[i], L.ev[b0 + i]);
+                    L.dn[f] = L.dn[f] + tne;
+                    tkind = TK_ENTRIES;
                 }
-                for (unsigned i = gl; i < f; i += G) q->M[i] = L.M[i];
-                if (kind == 2 && gl == 0) q->M[f] = extra;
+                // prefix positions taken from M (a single dense candidate carries M[f] in `extra`)
+                const unsigned pre = (DENSE && tkind == TK_RANGE) ? f : tL;
+                for (unsigned i = gl; i < pre; i += G) st_rlx(&q->M[i], L.M[i]);
+                if (DENSE && tkind == TK_RANGE && gl == 0) st_rlx(&q->M[f], extra);
                 if (gl == 0) {
-                    q->inst = inst;
-                    q->L = tL;
-                    q->lo = tlo;
-                    q->hi = thi;
+                    st_rlx(&q->inst, inst);
+                    st_rlx(&q->L, tL);
+                    st_rlx(&q->lo, tlo);
+                    st_rlx(&q->hi, thi);
+                    st_rlx(&q->kind, tkind);
+                    st_rlx(&q->ne, tne);
                 }
-                fence_rel();
+                // the payload (and the `created` count taken with the ticket)
+                // is complete before the task is published
+                vm_drain();
                 if (gl == 0) {
                     st_rlx(&q->seq, 2 * t + 1);
-                    fadd(&S->q_avail, 1);
+                    fadd(&HG->avail, 1);
                 }
             }
         }
     }
     flush();
-    if (lane == 0) atomicMax(&S->t_end, now_ticks());
+    if (lane == 0) {
+        if (last_finish) atomicMax(&S->t_work, last_finish);
+        atomicMax(&S->t_end, now_ticks());
+    }
 }
 
 __global__ void reset_kernel(Sched *s, InstCounters *c, unsigned ninst, QTask *q) {
@@ -709,13 +875,11 @@ __global__ void reset_kernel(Sched *s, InstCounters *c, unsigned ninst, QTask *q
         unsigned *w = reinterpret_cast<unsigned *>(s);
         for (unsigned j = threadIdx.x; j < sizeof(Sched) / 4; j += blockDim.x) w[j] = 0;
         __syncthreads();
-        if (threadIdx.x == 0) {
-            s->q_free = QUEUE_SLOTS;
-            s->t_start = ~0ull;
-        }
+        if (threadIdx.x < QUEUE_GROUPS) s->grp[threadIdx.x].free = QUEUE_GROUP_SLOTS;
+        if (threadIdx.x == 0) s->t_start = ~0ull;
     }
     for (unsigned j = i; j < ninst; j += stride) c[j] = InstCounters{0, 0, 0, 0, 0, 0, 0, 0};
-    for (unsigned j = i; j < QUEUE_SLOTS; j += stride) q[j].seq = 2 * j;
+    for (unsigned j = i; j < QUEUE_SLOTS; j += stride) q[j].seq = 2 * (j % QUEUE_GROUP_SLOTS);
 }
 
 template <int G, bool DENSE>
@@ -738,10 +902,10 @@ hipError_t launch_g(const SearchArgs &args, int blocks, int threads, size_t lds,
 }
 
 unsigned unit_words(const LaunchCfg &cfg) {
-    if (cfg.dense) return 2 * even(cfg.kmax) + 2 * cfg.kmax * cfg.wmax + 2 * cfg.wmax;
+    if (cfg.dense) return 3 * even(cfg.kmax) + 2 * cfg.kmax * cfg.wmax + 2 * cfg.wmax;
     unsigned E = cfg.kmax + cfg.lanes;
     unsigned UW = (cfg.nmax + 31) / 32;
-    return 8 * cfg.kmax + 3 * E + UW + 8;
+    return 8 * cfg.kmax + 3 * E + UW;
 }
 
 // Largest block (256, 128 or 64 threads) whose units fit in 64 KiB of LDS.
@@ -778,7 +942,8 @@ hipError_t launch_search(const LaunchCfg &cfg, DevWork &w, uint32_t ninst, uint3
     a.UW = (cfg.nmax + 31) / 32;
     a.W = cfg.dense ? cfg.wmax : 0;
     a.unit_words = unit_words(cfg);
-    a.donate = cfg.donate;
+    a.donate = cfg.donate != 0;
+    a.donate_period = cfg.donate > 1 ? (unsigned)cfg.donate : DEFAULT_DONATE_PERIOD;
     a.state_cap = state_cap;
     a.limit_ticks = time_limit_ms * 100000ull;   // s_memrealtime runs at 100 MHz
     const int threads = block_threads(cfg);

@@ -277,6 +277,7 @@ sge_status sge_serve_poll(sge_ctx *c, uint64_t ticket, sge_result *res) {
     res->states = q->out.states;
     res->candidates = q->out.candidates;
     res->steals = q->out.steals;
+    res->steps = q->out.steps;
     res->ms_prep = q->ms_prep;
     res->ms_search = q->ms_search;
     sge_status st = q->out.status;

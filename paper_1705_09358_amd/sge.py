@@ -25,13 +25,14 @@ EXPORTS = [
     "sge_create", "sge_destroy", "sge_last_error", "sge_load_target", "sge_unload_target", "sge_load_pattern",
     "sge_unload_pattern", "sge_set_labelled", "sge_set_mode", "sge_set_state_cap", "sge_set_root_range",
     "sge_count", "sge_enumerate", "sge_batch_run", "sge_set_batch_policy", "sge_serve_start", "sge_serve_submit",
-    "sge_serve_poll", "sge_serve_stop", "sge_plan_host", "sge_set_tuning", "sge_set_time_limit",
+    "sge_serve_poll", "sge_serve_stop", "sge_plan_host", "sge_set_tuning", "sge_set_time_limit", "sge_last_launch_timing",
 ]
 
 
 class c_result(ctypes.Structure):
     _fields_ = [("matches", ctypes.c_uint64), ("states", ctypes.c_uint64), ("candidates", ctypes.c_uint64),
-                ("steals", ctypes.c_uint64), ("ms_prep", ctypes.c_double), ("ms_search", ctypes.c_double)]
+                ("steals", ctypes.c_uint64), ("steps", ctypes.c_uint64), ("ms_prep", ctypes.c_double),
+                ("ms_search", ctypes.c_double)]
 
 
 class c_job(ctypes.Structure):
@@ -46,12 +47,13 @@ class Result:
     states: int
     candidates: int
     steals: int
+    steps: int
     ms_prep: float
     ms_search: float
 
     @staticmethod
     def of(st: int, r: c_result) -> "Result":
-        return Result(st, r.matches, r.states, r.candidates, r.steals, r.ms_prep, r.ms_search)
+        return Result(st, r.matches, r.states, r.candidates, r.steals, r.steps, r.ms_prep, r.ms_search)
 
 
 class SgeError(RuntimeError):
@@ -94,6 +96,7 @@ def lib() -> ctypes.CDLL:
             "sge_plan_host": (I32, [U32, P, P, P, U32, P, P, P, I32, I32, P, P, P, ctypes.POINTER(I32)]),
             "sge_set_tuning": (I32, [P, I32, U32, I32, I32]),
             "sge_set_time_limit": (I32, [P, U64]),
+            "sge_last_launch_timing": (I32, [P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -168,6 +171,12 @@ class Context:
             raise SgeError(st, f"{what}: {msg.decode() if msg else ''}")
         return st
 
+    def last_launch_timing(self):
+        """(kernel ms, ms until the last task finished, ms until termination was detected)."""
+        out = (ctypes.c_double * 3)()
+        self._check(self._L.sge_last_launch_timing(self._h, ctypes.addressof(out)), "sge_last_launch_timing")
+        return tuple(out)
+
     def last_error(self) -> str:
         m = self._L.sge_last_error(self._h)
         return m.decode() if m else ""
@@ -207,8 +216,9 @@ class Context:
     def set_root_range(self, lo: int = 0, hi: int = 0xFFFFFFFF):
         self._check(self._L.sge_set_root_range(self._h, int(lo), int(hi)), "sge_set_root_range")
 
-    def set_tuning(self, lanes: int = 0, root_chunk: int = 0, donate: bool = True, dense: int = -1):
-        self._check(self._L.sge_set_tuning(self._h, lanes, root_chunk, int(bool(donate)), dense), "sge_set_tuning")
+    def set_tuning(self, lanes: int = 0, root_chunk: int = 0, donate: int = 1, dense: int = -1):
+        """donate: 0 off, 1 default period, N > 1 at most one donation per N steps of a unit."""
+        self._check(self._L.sge_set_tuning(self._h, lanes, root_chunk, int(donate), dense), "sge_set_tuning")
 
     def set_batch_policy(self, policy: int):
         self._check(self._L.sge_set_batch_policy(self._h, policy), "sge_set_batch_policy")

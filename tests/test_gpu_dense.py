@@ -31,7 +31,7 @@ def _sorted(rows):
 def ctx():
     c = sge.Context(0)
     c.set_time_limit(60000)
-    c.set_tuning(0, 0, True, 1)     # force the dense kernel
+    c.set_tuning(0, 0, 1, 1)     # force the dense kernel
     yield c
     c.close()
 

@@ -163,7 +163,7 @@ def test_schedule_independence(run, ctx, lanes, chunk, donate):
         inst = synth.c1_instance(3)
         check(run, inst.pattern, inst.target, 3, True, f"c1/3/lanes{lanes}")
     finally:
-        ctx.set_tuning(0, 0, True)
+        ctx.set_tuning(0, 0, 1)
 
 
 def test_empty_pattern(run):
