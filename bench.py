@@ -23,6 +23,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 REPO = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, REPO)
 
@@ -47,6 +49,7 @@ def instances(cfg, man):
 
 def run_batch_workload(ctx, torch, stream, insts, man, steps, warmup, label):
     """Load all targets/patterns, then time `steps` batched launches."""
+    from paper_1705_09358_amd import sge
     tgt = {}
     jobs = []
     for inst in insts:
@@ -54,26 +57,27 @@ def run_batch_workload(ctx, torch, stream, insts, man, steps, warmup, label):
         if key not in tgt:
             tgt[key] = ctx.load_target(inst.target)
         jobs.append((tgt[key], ctx.load_pattern(inst.pattern), inst.mode, inst.labelled))
-    want_states = [r["states"] for r in man["instances"]]
-    want_matches = [r["matches"] for r in man["instances"]]
+    want_states = np.array([r["states"] for r in man["instances"]], dtype=np.uint64)
+    want_matches = np.array([r["matches"] for r in man["instances"]], dtype=np.uint64)
+    job_arr = sge.job_array(jobs)
     log(f"{label}: {len(jobs)} jobs loaded; warmup {warmup}")
     for _ in range(warmup):
-        st, res = ctx.batch_run(jobs)
+        st, res = ctx.batch_run(job_arr)
     torch.cuda.synchronize()
     kernel_ms = []
     log(f"{label}: timing {steps} steps")
     t0 = time.perf_counter()
     for _ in range(steps):
-        st, res = ctx.batch_run(jobs)
-        kernel_ms.append(res[0].ms_search)
-        if [r.states for r in res] != want_states or [r.matches for r in res] != want_matches:
+        st, res = ctx.batch_run(job_arr)
+        kernel_ms.append(float(res.ms_search[0]))
+        if not (np.array_equal(res.states, want_states) and np.array_equal(res.matches, want_matches)):
             raise SystemExit(f"{label}: counts differ from the oracle's stored values")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    tot_states = sum(want_states) * steps
-    tot_matches = sum(want_matches) * steps
+    tot_states = int(want_states.sum()) * steps
+    tot_matches = int(want_matches.sum()) * steps
     return dict(ms_per_step=1000 * el / steps, states_per_s=tot_states / el, matches_per_s=tot_matches / el,
-                kernel_ms=sum(kernel_ms) / len(kernel_ms), prep_ms=res[0].ms_prep, jobs=jobs, tgt=tgt)
+                kernel_ms=sum(kernel_ms) / len(kernel_ms), prep_ms=float(res.ms_prep[0]), jobs=jobs, tgt=tgt)
 
 
 def run_plain(ctx, torch, jobs, want_states, reps=1):

@@ -71,6 +71,24 @@ void index_target(Target &t) {
     t.W = (g.n + 63) / 64;
     t.max_deg = 0;
     for (uint32_t v = 0; v < g.n; v++) t.max_deg = std::max(t.max_deg, g.rp[v + 1] - g.rp[v]);
+    // the first arc-consistency round reads, for a candidate v and a pattern
+    // neighbour of label L and degree d, whether v has a neighbour of label L
+    // and degree >= d (pattern degrees are below 64, so 255 saturates safely)
+    t.nbr_deg.clear();
+    t.nbr_cols = (uint32_t)t.label_keys.size() + 1;
+    if ((uint64_t)g.n * t.nbr_cols <= NBR_DEG_MAX_BYTES) {
+        const uint32_t C = t.nbr_cols;
+        t.nbr_deg.assign((size_t)g.n * C, 0);
+        for (uint32_t v = 0; v < g.n; v++) {
+            uint8_t *row = &t.nbr_deg[(size_t)v * C];
+            for (uint32_t e = g.rp[v]; e < g.rp[v + 1]; e++) {
+                const uint32_t x = g.col[e];
+                const uint8_t dx = (uint8_t)std::min<uint32_t>(g.rp[x + 1] - g.rp[x], 255);
+                row[t.dlab[x]] = std::max(row[t.dlab[x]], dx);
+                row[C - 1] = std::max(row[C - 1], dx);
+            }
+        }
+    }
 }
 
 }  // namespace sge

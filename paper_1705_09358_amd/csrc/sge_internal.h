@@ -42,6 +42,11 @@ struct Target {
     std::vector<std::vector<uint32_t>> by_label; // dense id -> nodes
     uint32_t W = 0;                              // 64-bit words per bitset row
     uint32_t max_deg = 0;
+    // nbr_deg[v * nbr_cols + L]: largest degree (saturated at 255) among the
+    // neighbours of v with dense label L; column nbr_cols - 1 ignores labels.
+    // Empty when n * nbr_cols would exceed NBR_DEG_MAX_BYTES.
+    std::vector<uint8_t> nbr_deg;
+    uint32_t nbr_cols = 0;
     // device
     uint32_t *d_col = nullptr;
     NodeRec *d_node = nullptr;
@@ -75,7 +80,10 @@ struct Plan {
 void build_plan(const Target &t, const HostGraph &p, int mode, bool labelled, uint32_t root_lo, uint32_t root_hi,
                 Plan &plan, bool want_pos_bitsets, std::vector<uint64_t> &pos_bits);
 
-// Dense label ids of a target (fills dlab, label_keys, by_label, W, max_deg).
+constexpr uint64_t NBR_DEG_MAX_BYTES = 256ull << 20;
+
+// Dense label ids of a target (fills dlab, label_keys, by_label, W, max_deg)
+// and its neighbour-degree table.
 void index_target(Target &t);
 
 // ------------------------------------------------------------ device structs

@@ -3,12 +3,10 @@
 // tie-break (Section "RI" ordering; Section 4.2.1), parents and back-edges.
 //
 // Pattern neighbourhoods are 64-bit masks (k <= 64); domains are bitsets of
-// ceil(n/64) words.  Arc-consistency is evaluated in its support form: v stays
-// in D(u) iff for every pattern neighbour w of u, v is a target neighbour of
-// some member of D(w) (the graph is undirected), i.e. v lies in the union of
-// the target rows of D(w).  Rounds recompute every support set from the
-// current domains until nothing changes, which reaches the same greatest
-// arc-consistent domains as revising one value at a time.
+// ceil(n/64) words.  Arc-consistency keeps v in D(u) iff for every pattern
+// neighbour w of u some target neighbour of v lies in D(w) (the graphs are
+// undirected).  Values are removed until nothing changes; every order of
+// removals reaches the same greatest arc-consistent domains.
 #include <algorithm>
 #include <cstring>
 
@@ -71,35 +69,66 @@ void build_plan(const Target &t, const HostGraph &p, int mode, bool labelled, ui
     if (use_dom) {
         D.assign((size_t)k * W, 0);
         for (uint32_t u = 0; u < k; u++) compat_nodes(u, [&](uint32_t v) { D[(size_t)u * W + (v >> 6)] |= 1ull << (v & 63); });
-        // arc-consistency, support form, to the fixpoint
-        std::vector<uint64_t> S((size_t)k * W);
-        for (bool changed = true; changed;) {
-            changed = false;
-            std::fill(S.begin(), S.end(), 0);
-            for (uint32_t w = 0; w < k; w++) {
-                if (!nb[w]) continue;  // no pattern node has w as a neighbour
-                uint64_t *s = &S[(size_t)w * W];
-                const uint64_t *d = &D[(size_t)w * W];
+        // arc-consistency to the fixpoint.  A round revises D(u) against the
+        // pattern neighbours w whose domains changed since D(u) was last
+        // revised against them (for the others every member of D(u) still has
+        // its support, as D(w) is unchanged): v leaves D(u) when no target
+        // neighbour of v lies in D(w).
+        bool any_empty = false;
+        for (uint32_t u = 0; u < k; u++) any_empty |= popcount_row(&D[(size_t)u * W], W) == 0;
+        uint64_t dirty = 0;   // nodes whose domain changed since their neighbours were revised against it
+        if (!any_empty && !t.nbr_deg.empty()) {
+            // first round against the label-and-degree domains: a target node
+            // has a neighbour in D(w) iff it has a neighbour of w's label whose
+            // degree is at least w's, which the target's table answers
+            const uint32_t C = t.nbr_cols;
+            uint32_t col[KMAX];
+            for (uint32_t w = 0; w < k; w++) col[w] = lab[w] == LABEL_ANY ? C - 1 : lab[w];
+            for (uint32_t u = 0; u < k; u++) {
+                if (!nb[u]) continue;
+                uint64_t *d = &D[(size_t)u * W];
                 for (uint32_t i = 0; i < W; i++) {
                     for (uint64_t bits = d[i]; bits; bits &= bits - 1) {
-                        uint32_t x = i * 64 + (uint32_t)__builtin_ctzll(bits);
-                        for (uint32_t e = tg.rp[x]; e < tg.rp[x + 1]; e++) {
-                            uint32_t y = tg.col[e];
-                            s[y >> 6] |= 1ull << (y & 63);
+                        const uint32_t v = i * 64 + (uint32_t)__builtin_ctzll(bits);
+                        const uint8_t *row = &t.nbr_deg[(size_t)v * C];
+                        for (uint64_t m = nb[u]; m; m &= m - 1) {
+                            const uint32_t w = (uint32_t)__builtin_ctzll(m);
+                            if (row[col[w]] < deg[w]) {
+                                d[i] &= ~(1ull << (v & 63));
+                                dirty |= 1ull << u;
+                                break;
+                            }
                         }
                     }
                 }
             }
+        } else if (!any_empty) {
+            for (uint32_t u = 0; u < k; u++)
+                if (nb[u]) dirty |= 1ull << u;
+        }
+        while (dirty) {
+            uint64_t next = 0;
             for (uint32_t u = 0; u < k; u++) {
+                const uint64_t ws = nb[u] & dirty;
+                if (!ws) continue;
                 uint64_t *d = &D[(size_t)u * W];
-                for (uint64_t m = nb[u]; m; m &= m - 1) {
-                    const uint64_t *s = &S[(size_t)__builtin_ctzll(m) * W];
-                    for (uint32_t i = 0; i < W; i++) {
-                        uint64_t x = d[i] & s[i];
-                        if (x != d[i]) { d[i] = x; changed = true; }
+                for (uint32_t i = 0; i < W; i++) {
+                    for (uint64_t bits = d[i]; bits; bits &= bits - 1) {
+                        const uint32_t v = i * 64 + (uint32_t)__builtin_ctzll(bits);
+                        for (uint64_t m = ws; m; m &= m - 1) {
+                            const uint64_t *dw = &D[(size_t)__builtin_ctzll(m) * W];
+                            bool sup = false;
+                            for (uint32_t e = tg.rp[v]; e < tg.rp[v + 1] && !sup; e++) sup = test_bit(dw, tg.col[e]);
+                            if (!sup) {
+                                d[i] &= ~(1ull << (v & 63));
+                                next |= 1ull << u;
+                                break;
+                            }
+                        }
                     }
                 }
             }
+            dirty = next;
         }
         for (uint32_t u = 0; u < k; u++) {
             dsize[u] = popcount_row(&D[(size_t)u * W], W);

@@ -56,6 +56,46 @@ class Result:
         return Result(st, r.matches, r.states, r.candidates, r.steals, r.steps, r.ms_prep, r.ms_search)
 
 
+# numpy layouts of sge_job and sge_result, for batches marshalled without
+# per-job Python objects
+JOB_DTYPE = np.dtype([("target", "<u4"), ("pattern", "<u4"), ("mode", "<i4"), ("labelled", "<i4")])
+RESULT_DTYPE = np.dtype([("matches", "<u8"), ("states", "<u8"), ("candidates", "<u8"), ("steals", "<u8"),
+                         ("steps", "<u8"), ("ms_prep", "<f8"), ("ms_search", "<f8")])
+assert JOB_DTYPE.itemsize == ctypes.sizeof(c_job) and RESULT_DTYPE.itemsize == ctypes.sizeof(c_result)
+
+
+def job_array(jobs) -> np.ndarray:
+    """(target, pattern, mode, labelled) tuples -> a contiguous sge_job array (reusable across runs)."""
+    if isinstance(jobs, np.ndarray) and jobs.dtype == JOB_DTYPE:
+        return np.ascontiguousarray(jobs)
+    return np.array([(int(t), int(p), int(m), int(bool(l))) for t, p, m, l in jobs], dtype=JOB_DTYPE)
+
+
+class BatchResults:
+    """Per-job counters of one batch: columns as numpy arrays (``.states``,
+    ``.matches``, ...), or one Result per job by index or iteration."""
+
+    def __init__(self, status: int, array: np.ndarray):
+        self.status = status
+        self.array = array
+
+    def __len__(self) -> int:
+        return len(self.array)
+
+    def __getitem__(self, i: int) -> "Result":
+        r = self.array[i]
+        return Result(self.status, int(r["matches"]), int(r["states"]), int(r["candidates"]), int(r["steals"]),
+                      int(r["steps"]), float(r["ms_prep"]), float(r["ms_search"]))
+
+    def __iter__(self):
+        return (self[i] for i in range(len(self)))
+
+    def __getattr__(self, name):
+        if name in RESULT_DTYPE.names:
+            return self.array[name]
+        raise AttributeError(name)
+
+
 class SgeError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
@@ -250,16 +290,14 @@ class Context:
         return res, buf
 
     def batch_run(self, jobs, allow=(OK,)):
-        """jobs: iterable of (target, pattern, mode, labelled).  Returns (status, [Result])."""
-        jobs = list(jobs)
-        arr = (c_job * max(len(jobs), 1))()
-        for i, (t, p, m, l) in enumerate(jobs):
-            arr[i] = c_job(t, p, m, int(bool(l)))
-        res = (c_result * max(len(jobs), 1))()
-        st = self._L.sge_batch_run(self._h, len(jobs), ctypes.addressof(arr), ctypes.addressof(res))
+        """jobs: iterable of (target, pattern, mode, labelled), or an array from
+        ``job_array``.  Returns (status, BatchResults)."""
+        arr = job_array(jobs)
+        res = np.zeros(max(len(arr), 1), dtype=RESULT_DTYPE)
+        st = self._L.sge_batch_run(self._h, len(arr), arr.ctypes.data if len(arr) else None, res.ctypes.data)
         if st not in allow:
             self._check(st, "sge_batch_run")
-        return st, [Result.of(st, res[i]) for i in range(len(jobs))]
+        return st, BatchResults(st, res[:len(arr)])
 
     def serve_start(self, slots: int, arena_bytes: int):
         self._check(self._L.sge_serve_start(self._h, slots, arena_bytes), "sge_serve_start")

@@ -78,6 +78,21 @@ def test_plan_matches_oracle_c4(orc, j):
         _cmp_plan(inst.pattern, inst.target, mode, True, orc)
 
 
+@pytest.mark.parametrize("j", [0, 7])
+def test_plan_matches_oracle_c3(orc, j):
+    # dense target: node degrees near 300 pass the 255 saturation of the
+    # library's neighbour-degree table
+    inst = synth.c3_instance(j)
+    for mode in (1, 3):
+        _cmp_plan(inst.pattern, inst.target, mode, True, orc)
+
+
+def test_plan_matches_oracle_unlabelled_contact(orc):
+    inst = synth.c2_instance(5)
+    for mode in (1, 2, 3):
+        _cmp_plan(inst.pattern, inst.target, mode, False, orc)
+
+
 def test_plan_paper_orderings(orc):
     # the hand-checked orderings of the oracle tests, through the library
     P = G.from_edges(5, [(0, 1), (0, 2), (0, 4), (2, 4), (1, 3)])
