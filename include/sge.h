@@ -176,6 +176,19 @@ sge_status sge_plan_host(uint32_t k, const uint32_t *p_row_ptr, const uint32_t *
                          uint32_t n, const uint32_t *t_row_ptr, const uint32_t *t_col, const uint32_t *t_labels,
                          int mode, int labelled, uint32_t *order, int32_t *parent, uint64_t *dom, int *empty);
 
+/* The plan the device computes for one instance, as every search launch
+ * computes it before searching (domains of Section 4.1 with arc-consistency,
+ * forward checking of Section 4.2.2, the order of Section "RI" with the
+ * tie-break of Section 4.2.1), copied back for checking against an
+ * independent reference.  Host output arrays: order[k] and parent[k] as in
+ * sge_plan_host; dom (may be NULL; ignored in SGE_RI): k * ceil(n/64) uint64
+ * words of the final domains by pattern node; *nroot: candidates of position
+ * 0 within the context's root range.  *empty = 1 when a domain became empty
+ * (order, parent and dom are then not written).  Ordered on the context's
+ * stream; returns when the copy is complete. */
+sge_status sge_plan_device(sge_ctx *ctx, uint32_t target, uint32_t pattern, int mode, int labelled, uint32_t *order,
+                           int32_t *parent, uint64_t *dom, uint32_t *nroot, int *empty);
+
 /* Tuning knobs (for measurement): lanes per search unit (8, 16, 32 or 64;
  * 0 = automatic), root chunk size (0 = automatic), work donation (0 = off,
  * 1 = on with the default period, N > 1 = a unit gives work away at most

@@ -81,6 +81,13 @@ sge_status upload_target(sge_ctx *c, Target &t) {
             return hip_fail(c, e, "upload adjacency bitsets");
         t.dev_bytes += adj.size() * 8;
     }
+    const size_t nk = std::max<size_t>(t.label_keys.size(), 1);
+    if ((e = hipMalloc(&t.d_label_keys, nk * 4)) != hipSuccess) return hip_fail(c, e, "hipMalloc(label keys)");
+    if (!t.label_keys.empty() &&
+        (e = hipMemcpy(t.d_label_keys, t.label_keys.data(), t.label_keys.size() * 4, hipMemcpyHostToDevice)) !=
+            hipSuccess)
+        return hip_fail(c, e, "upload label keys");
+    t.dev_bytes += nk * 4;
     return SGE_OK;
 }
 
@@ -88,9 +95,50 @@ void free_target(Target &t) {
     if (t.d_col) (void)hipFree(t.d_col);
     if (t.d_node) (void)hipFree(t.d_node);
     if (t.d_adj) (void)hipFree(t.d_adj);
+    if (t.d_label_keys) (void)hipFree(t.d_label_keys);
     t.d_col = nullptr;
     t.d_node = nullptr;
     t.d_adj = nullptr;
+    t.d_label_keys = nullptr;
+}
+
+sge_status upload_pattern(sge_ctx *c, Pattern &p) {
+    const HostGraph &g = p.g;
+    DevPattern dp{};
+    dp.k = g.n;
+    // connected components: each begins one parentless position of the order
+    std::vector<uint32_t> comp(g.n, 0xFFFFFFFFu), stack;
+    for (uint32_t s = 0; s < g.n; s++) {
+        if (comp[s] != 0xFFFFFFFFu) continue;
+        comp[s] = dp.ncomp;
+        stack.assign(1, s);
+        while (!stack.empty()) {
+            const uint32_t u = stack.back();
+            stack.pop_back();
+            for (uint32_t e = g.rp[u]; e < g.rp[u + 1]; e++)
+                if (comp[g.col[e]] == 0xFFFFFFFFu) {
+                    comp[g.col[e]] = dp.ncomp;
+                    stack.push_back(g.col[e]);
+                }
+        }
+        dp.ncomp++;
+    }
+    for (uint32_t u = 0; u < g.n; u++) {
+        for (uint32_t e = g.rp[u]; e < g.rp[u + 1]; e++) dp.nb[u] |= 1ull << g.col[e];
+        dp.deg[u] = g.rp[u + 1] - g.rp[u];
+        dp.label[u] = g.lab[u];
+    }
+    p.ncomp = dp.ncomp;
+    hipError_t e;
+    if ((e = hipMalloc(&p.d_pat, sizeof(DevPattern))) != hipSuccess) return hip_fail(c, e, "hipMalloc(pattern)");
+    if ((e = hipMemcpy(p.d_pat, &dp, sizeof(DevPattern), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(c, e, "upload pattern");
+    return SGE_OK;
+}
+
+void free_pattern(Pattern &p) {
+    if (p.d_pat) (void)hipFree(p.d_pat);
+    p.d_pat = nullptr;
 }
 
 }  // namespace sge
@@ -133,6 +181,7 @@ void sge_destroy(sge_ctx *c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     for (auto &kv : c->targets) free_target(*kv.second);
+    for (auto &kv : c->patterns) free_pattern(*kv.second);
     c->bufs.release();
     c->d_rows.release();
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -184,6 +233,12 @@ sge_status sge_load_pattern(sge_ctx *c, uint32_t k, const uint32_t *row_ptr, con
     auto p = std::make_unique<Pattern>();
     std::string why = normalise_graph(k, row_ptr, col, labels, p->g);
     if (!why.empty()) return fail(c, SGE_E_INVAL, "pattern: " + why);
+    (void)hipSetDevice(c->device);
+    sge_status st = upload_pattern(c, *p);
+    if (st != SGE_OK) {
+        free_pattern(*p);
+        return st;
+    }
     uint32_t h = c->next_handle++;
     c->patterns[h] = std::move(p);
     *handle = h;
@@ -192,7 +247,11 @@ sge_status sge_load_pattern(sge_ctx *c, uint32_t k, const uint32_t *row_ptr, con
 
 sge_status sge_unload_pattern(sge_ctx *c, uint32_t handle) {
     if (!c) return SGE_E_INVAL;
-    if (!c->patterns.erase(handle)) return fail(c, SGE_E_HANDLE, "unknown pattern handle");
+    auto it = c->patterns.find(handle);
+    if (it == c->patterns.end()) return fail(c, SGE_E_HANDLE, "unknown pattern handle");
+    (void)hipStreamSynchronize(c->stream);
+    free_pattern(*it->second);
+    c->patterns.erase(it);
     return SGE_OK;
 }
 
@@ -302,6 +361,48 @@ sge_status sge_enumerate(sge_ctx *c, uint32_t target, uint32_t pattern, uint32_t
                          sge_result *res) {
     if (!rows && cap_rows) return fail(c, SGE_E_INVAL, "rows is NULL");
     return single(c, target, pattern, rows, cap_rows, res);
+}
+
+sge_status sge_plan_device(sge_ctx *c, uint32_t target, uint32_t pattern, int mode, int labelled, uint32_t *order,
+                           int32_t *parent, uint64_t *dom, uint32_t *nroot, int *empty) {
+    if (!c || !order || !parent || !nroot || !empty) return SGE_E_INVAL;
+    if (mode < SGE_RI || mode > SGE_RIDS_SI_FC) return fail(c, SGE_E_INVAL, "unknown mode");
+    auto it = c->targets.find(target);
+    if (it == c->targets.end()) return fail(c, SGE_E_HANDLE, "unknown target handle");
+    auto ip = c->patterns.find(pattern);
+    if (ip == c->patterns.end()) return fail(c, SGE_E_HANDLE, "unknown pattern handle");
+    const uint32_t k = ip->second->g.n;
+    *empty = 0;
+    *nroot = 0;
+    if (k == 0) return SGE_OK;
+    (void)hipSetDevice(c->device);
+    InstanceSpec s;
+    s.t = it->second.get();
+    s.p = ip->second.get();
+    s.mode = mode;
+    s.labelled = labelled != 0;
+    std::vector<const InstanceSpec *> sp{&s};
+    Pack pk;
+    sge_status st = pack_instances(c, sp, false, 2, c->bufs, pk);
+    if (st != SGE_OK) return st;
+    hipError_t e = enqueue_plan_only(pk, c->bufs, c->root_chunk, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "device plan");
+    DevPlan dp;
+    if ((e = hipMemcpy(&dp, c->bufs.d_arena.p, sizeof(DevPlan), hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(c, e, "read device plan");
+    *empty = dp.empty ? 1 : 0;
+    if (dp.empty) return SGE_OK;
+    std::memcpy(order, dp.order, k * 4);
+    std::memcpy(parent, dp.parent, k * 4);
+    *nroot = dp.list_len[0];
+    if (dom && mode != SGE_RI) {
+        const size_t words = (size_t)k * s.t->W;
+        if ((e = hipMemcpy(dom, (char *)c->bufs.d_arena.p + pk.dom_at[0], words * 8, hipMemcpyDeviceToHost)) !=
+            hipSuccess)
+            return hip_fail(c, e, "read device domains");
+    }
+    return SGE_OK;
 }
 
 sge_status sge_plan_host(uint32_t k, const uint32_t *p_rp, const uint32_t *p_col, const uint32_t *p_lab, uint32_t n,

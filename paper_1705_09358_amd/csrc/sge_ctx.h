@@ -46,7 +46,8 @@ struct InstanceOut {
 // Buffers of one launch stream.
 struct LaunchBufs {
     DevWork work;
-    DevBuf d_blob;
+    DevBuf d_blob;    // uploaded: search descriptors and plan requests (+ chunk prefix, device-written)
+    DevBuf d_arena;   // device-written: plans, domains, per-position bitsets, candidate lists
     HostBuf h_blob, h_ctr;
     void release();
 };
@@ -90,43 +91,50 @@ namespace sge {
 sge_status fail(sge_ctx *c, sge_status code, const std::string &msg);
 sge_status hip_fail(sge_ctx *c, hipError_t e, const char *what);
 
-// Plan, upload and search `specs` in one persistent launch.  With `graph`
-// the uploads, the launch and the read-back are captured in a HIP graph and
-// replayed.  Fills `out` and the prep / search times (ms).
+// Upload the job descriptors of `specs`, plan every instance on the device
+// and search them all in one persistent launch.  With `graph` the upload, the
+// kernels and the read-back are captured in a HIP graph and replayed.  Fills
+// `out` and the host-preparation / search times (ms).
 sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std::vector<InstanceOut> &out,
                          double &ms_prep, double &ms_search, bool graph, int policy);
 
 // The pieces of run_instances, also used by the server.
 // Whether these instances are searched by the dense-bitset kernel.
 bool choose_dense(const sge_ctx *c, const std::vector<InstanceSpec> &specs);
-// Plan one instance (k = 0 and empty domains are answered in `out`).
-// Returns whether the instance needs a search.
-bool plan_instance(const sge_ctx *c, const InstanceSpec &s, bool dense, Plan &plan, std::vector<uint64_t> &bits,
-                   InstanceOut &out);
+// Device bytes one instance holds during a launch (descriptors, plan, domains,
+// per-position bitsets, candidate lists).
+uint64_t instance_device_bytes(const InstanceSpec &s);
 
-// The host layout of one launch: which plans, where in the blob.
+// The layout of one launch: descriptors and plan requests in the uploaded
+// blob, the device-written plan data in the arena.
 struct Pack {
     LaunchCfg cfg;
     uint32_t m = 0;
+    int policy = 2;
+    uint64_t units = 1;                // approximate search units (root chunk sizing)
     double ms_work = 0, ms_done = 0;   // filled by read_pack
     bool bad_task = false;             // filled by read_pack: the work queue delivered an invalid task
-    size_t blob = 0, ctr_bytes = 0;
-    uint32_t total_chunks = 0;
+    size_t blob = 0, upload = 0, arena = 0, ctr_bytes = 0;
+    size_t off_req = 0, off_pref = 0;  // in the blob
+    std::vector<size_t> dom_at;        // in the arena: instance j's domains by pattern node
 };
 
-// Lay the plans out in the pinned blob (device addresses from bufs.d_blob);
-// `plans[j]`/`bits[j]` belong to `specs[j]`, all of which need a search.
-sge_status pack_instances(sge_ctx *c, const std::vector<const InstanceSpec *> &specs,
-                          const std::vector<const Plan *> &plans, const std::vector<const std::vector<uint64_t> *> &bits,
-                          bool dense, int policy, LaunchBufs &bufs, Pack &pk);
-// Upload, reset, search and read back on `s` (asynchronous).
+// Lay out the descriptors and plan requests of `specs` (every one with k > 0)
+// in the pinned blob, with device addresses in bufs.d_blob / bufs.d_arena.
+sge_status pack_instances(sge_ctx *c, const std::vector<const InstanceSpec *> &specs, bool dense, int policy,
+                          LaunchBufs &bufs, Pack &pk);
+// Upload, plan, reset, search and read back on `s` (asynchronous).
 hipError_t enqueue_pack(sge_ctx *c, const Pack &pk, LaunchBufs &bufs, hipStream_t s);
+// Upload and plan only (the plan of instance 0 is then read back by the caller).
+hipError_t enqueue_plan_only(const Pack &pk, LaunchBufs &bufs, uint32_t root_chunk, hipStream_t s);
 // After the stream has drained: per-instance results and the kernel time.
 void read_pack(const sge_ctx *c, Pack &pk, const LaunchBufs &bufs, const std::vector<const InstanceSpec *> &specs,
                std::vector<InstanceOut *> &out, double &ms_search);
 
-// Device memory for a target's resident data.
+// Device memory for a target's / pattern's resident data.
 sge_status upload_target(sge_ctx *c, Target &t);
 void free_target(Target &t);
+sge_status upload_pattern(sge_ctx *c, Pattern &p);
+void free_pattern(Pattern &p);
 
 }  // namespace sge

@@ -50,21 +50,16 @@ std::string normalise_graph(uint32_t n, const uint32_t *row_ptr, const uint32_t 
 
 void index_target(Target &t) {
     const HostGraph &g = t.g;
-    std::unordered_map<uint32_t, uint32_t> ids;
+    // dense label ids in increasing order of the raw labels, so that a raw
+    // label's id is its rank among label_keys (found by binary search)
+    t.label_keys.assign(g.lab.begin(), g.lab.end());
+    std::sort(t.label_keys.begin(), t.label_keys.end());
+    t.label_keys.erase(std::unique(t.label_keys.begin(), t.label_keys.end()), t.label_keys.end());
     t.dlab.resize(g.n);
-    t.label_keys.clear();
-    t.by_label.clear();
+    t.by_label.assign(t.label_keys.size(), {});
     for (uint32_t v = 0; v < g.n; v++) {
-        auto it = ids.find(g.lab[v]);
-        uint32_t id;
-        if (it == ids.end()) {
-            id = (uint32_t)t.label_keys.size();
-            ids.emplace(g.lab[v], id);
-            t.label_keys.push_back(g.lab[v]);
-            t.by_label.emplace_back();
-        } else {
-            id = it->second;
-        }
+        const uint32_t id =
+            (uint32_t)(std::lower_bound(t.label_keys.begin(), t.label_keys.end(), g.lab[v]) - t.label_keys.begin());
         t.dlab[v] = id;
         t.by_label[id].push_back(v);
     }

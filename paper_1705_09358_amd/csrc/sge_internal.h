@@ -38,7 +38,7 @@ struct NodeRec {
 struct Target {
     HostGraph g;
     std::vector<uint32_t> dlab;                  // dense label id per node
-    std::vector<uint32_t> label_keys;            // dense id -> raw label
+    std::vector<uint32_t> label_keys;            // dense id -> raw label (increasing)
     std::vector<std::vector<uint32_t>> by_label; // dense id -> nodes
     uint32_t W = 0;                              // 64-bit words per bitset row
     uint32_t max_deg = 0;
@@ -51,11 +51,23 @@ struct Target {
     uint32_t *d_col = nullptr;
     NodeRec *d_node = nullptr;
     uint64_t *d_adj = nullptr;                   // n * W, or null when too large
+    uint32_t *d_label_keys = nullptr;            // label_keys on the device
     uint64_t dev_bytes = 0;
+};
+
+// A pattern as the plan kernel reads it (resident on the device).
+struct DevPattern {
+    uint32_t k, ncomp;            // nodes, connected components
+    uint32_t pad[2];
+    uint64_t nb[KMAX];            // bit w of nb[u]: {u, w} is a pattern edge
+    uint32_t label[KMAX];         // raw labels
+    uint32_t deg[KMAX];
 };
 
 struct Pattern {
     HostGraph g;
+    uint32_t ncomp = 0;
+    DevPattern *d_pat = nullptr;
 };
 
 // Search plan of one (pattern, target, mode, labelled) instance.
@@ -90,7 +102,7 @@ void index_target(Target &t);
 // Everything one instance of the search needs, as the kernels read it.
 struct DevPlan {
     uint32_t k, W, n, use_dom;
-    uint32_t labelled, pad0, pad1, pad2;
+    uint32_t labelled, empty, pad1, pad2;   // empty: a domain became empty (nothing to search)
     int32_t parent[KMAX];
     uint64_t back[KMAX];
     uint32_t plabel[KMAX];
@@ -113,6 +125,25 @@ struct InstDesc {
     uint32_t chunk;           // root candidates per chunk
     uint32_t nroot;           // candidates of position 0
     uint32_t pad;
+};
+
+// One instance's plan request: the plan kernel turns the resident pattern
+// and target into the DevPlan, the per-position bitsets and the candidate
+// lists of the instance (Sections "RI" and 4), and the finalize kernel sets
+// the root chunking of every instance.
+struct PlanIn {
+    const DevPattern *pat;
+    const uint32_t *label_keys;   // the target's raw labels by dense id (increasing)
+    uint32_t nlabels;
+    uint32_t mode, labelled, n, W;
+    uint32_t root_lo, root_hi;
+    uint32_t list_cap;            // entries `lists` holds: ncomp*n + k (a singleton domain adds one)
+    InstDesc *desc;               // the instance's search descriptor (col, node read; nroot written)
+    DevPlan *plan;                // written
+    uint64_t *dom;                // k*W words: domains by pattern node (written)
+    uint64_t *pos_bits;           // k*W words by position (written), or null
+    uint32_t *lists;              // room for list_cap candidates (written)
+    uint64_t *support;            // W words of scratch when W exceeds the plan kernel's LDS
 };
 
 // Per-instance device counters.
@@ -190,10 +221,19 @@ struct DevWork {
     size_t ctr_cap = 0;
 };
 
-// Launch one persistent search over `ninst` instances (already on the device).
-// Returns a HIP error code.
-hipError_t launch_search(const LaunchCfg &cfg, DevWork &w, uint32_t ninst, uint32_t total_chunks,
-                         uint64_t state_cap, uint64_t time_limit_ms, hipStream_t s, int num_cus);
+// Plan `m` instances (one workgroup each), then set every instance's root
+// chunks and the chunk prefix: `policy` 1 = one chunk per instance, else
+// `root_chunk` candidates per chunk, or (0) the total roots over 4 * `units`.
+hipError_t launch_plan(const PlanIn *reqs, uint32_t m, uint32_t wmax, InstDesc *desc, unsigned *chunk_prefix,
+                       int policy, uint32_t root_chunk, uint64_t units, hipStream_t s);
+// LDS words of the plan kernel's support buffer (larger W uses PlanIn::support).
+constexpr uint32_t PLAN_LDS_WORDS = 4096;
+
+// Launch one persistent search over `ninst` planned instances.  The grid is
+// the resident maximum (or cfg.blocks); blocks beyond what the root chunks
+// can keep busy leave at once.  Returns a HIP error code.
+hipError_t launch_search(const LaunchCfg &cfg, DevWork &w, uint32_t ninst, uint64_t state_cap,
+                         uint64_t time_limit_ms, hipStream_t s, int num_cus);
 // Shared memory a block of the search kernel needs.
 size_t search_lds_bytes(const LaunchCfg &cfg);
 // Clear the scheduling words of a launch (a fill kernel; usable in a captured graph).

@@ -1,7 +1,9 @@
-// One persistent search launch over a set of instances: plan on the host,
-// lay the plans out in one blob, upload, reset the scheduler, search, read
-// the counters back.  Used by the single-instance calls, by batches (in a HIP
-// graph) and by the server (asynchronously, one stream per launch lane).
+// One persistent search launch over a set of instances: the host lays out a
+// descriptor and a plan request per instance (pattern and target are
+// resident on the device), uploads them, and the device plans every instance,
+// sets the root chunking, resets the scheduler and searches; the counters are
+// read back.  Used by the single-instance calls, by batches (in a HIP graph)
+// and by the server (asynchronously, one stream per launch lane).
 #include <algorithm>
 #include <cstring>
 #include <thread>
@@ -16,6 +18,7 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 void LaunchBufs::release() {
     d_blob.release();
+    d_arena.release();
     h_blob.release();
     h_ctr.release();
     if (work.sched) (void)hipFree(work.sched);
@@ -39,15 +42,17 @@ bool choose_dense(const sge_ctx *c, const std::vector<InstanceSpec> &specs) {
     return c->dense == 1 || deg >= 2.0 * words;
 }
 
-bool plan_instance(const sge_ctx *c, const InstanceSpec &s, bool dense, Plan &plan, std::vector<uint64_t> &bits,
-                   InstanceOut &out) {
-    if (s.p->g.n == 0) {   // the empty pattern has one (empty) match
-        out.matches = 1;
-        return false;
-    }
-    bool want_bits = dense || s.mode != SGE_RI;
-    build_plan(*s.t, s.p->g, s.mode, s.labelled, c->root_lo, c->root_hi, plan, want_bits, bits);
-    return !plan.empty;
+// Candidate-list entries of one instance: a parentless position either
+// starts a pattern component (at most n candidates) or, in the RI-DS modes,
+// holds a singleton domain placed first (one candidate).
+static uint64_t list_entries(const InstanceSpec &s) {
+    return (uint64_t)std::max<uint32_t>(s.p->ncomp, 1) * s.t->g.n + s.p->g.n;
+}
+
+uint64_t instance_device_bytes(const InstanceSpec &s) {
+    const uint64_t k = s.p->g.n, W = s.t->W;
+    return sizeof(DevPlan) + sizeof(InstDesc) + sizeof(PlanIn) + sizeof(InstCounters) + 2 * k * W * 8 +
+           list_entries(s) * 4 + (W > PLAN_LDS_WORDS ? W * 8 : 0);
 }
 
 static int auto_lanes(const std::vector<const InstanceSpec *> &specs) {
@@ -80,17 +85,17 @@ static hipError_t ensure_work(DevWork &w, uint32_t m) {
     return hipSuccess;
 }
 
-sge_status pack_instances(sge_ctx *c, const std::vector<const InstanceSpec *> &specs,
-                          const std::vector<const Plan *> &plans, const std::vector<const std::vector<uint64_t> *> &bits,
-                          bool dense, int policy, LaunchBufs &bufs, Pack &pk) {
+sge_status pack_instances(sge_ctx *c, const std::vector<const InstanceSpec *> &specs, bool dense, int policy,
+                          LaunchBufs &bufs, Pack &pk) {
     const uint32_t m = (uint32_t)specs.size();
     pk = Pack{};
     pk.m = m;
+    pk.policy = policy;
     LaunchCfg &cfg = pk.cfg;
-    for (uint32_t j = 0; j < m; j++) {
-        cfg.kmax = std::max(cfg.kmax, plans[j]->k);
-        cfg.nmax = std::max(cfg.nmax, plans[j]->n);
-        cfg.wmax = std::max(cfg.wmax, plans[j]->W);
+    for (const InstanceSpec *sp : specs) {
+        cfg.kmax = std::max(cfg.kmax, sp->p->g.n);
+        cfg.nmax = std::max(cfg.nmax, sp->t->g.n);
+        cfg.wmax = std::max(cfg.wmax, sp->t->W);
     }
     cfg.dense = dense ? 1 : 0;
     if (c->lanes) {
@@ -103,89 +108,94 @@ sge_status pack_instances(sge_ctx *c, const std::vector<const InstanceSpec *> &s
     }
     cfg.donate = c->donate;
     // approximate number of search units (for the root chunk size)
-    const uint64_t units = (uint64_t)c->num_cus * 4 * 8 * (64 / cfg.lanes) / 2;
+    pk.units = (uint64_t)c->num_cus * 4 * 8 * (64 / cfg.lanes) / 2;
 
-    // blob layout: plans | descs | chunk prefix | lists | bits
-    const size_t off_plan = 0;
-    const size_t off_desc = align_up(off_plan + m * sizeof(DevPlan), 256);
-    const size_t off_pref = align_up(off_desc + m * sizeof(InstDesc), 256);
-    const size_t off_list = align_up(off_pref + (m + 1) * sizeof(unsigned), 256);
-    std::vector<size_t> list_at(m), bits_at(m);
-    size_t cur = off_list;
+    // blob (uploaded): descriptors | plan requests | chunk prefix (device-written)
+    const size_t off_desc = 0;
+    pk.off_req = align_up(off_desc + m * sizeof(InstDesc), 256);
+    pk.off_pref = align_up(pk.off_req + m * sizeof(PlanIn), 256);
+    pk.upload = pk.off_pref;
+    pk.blob = std::max<size_t>(align_up(pk.off_pref + (m + 1) * sizeof(unsigned), 256), 256);
+    // arena (device-written): plans | per instance: domains, bitsets, lists, support scratch
+    const size_t off_plans = 0;
+    size_t cur = align_up(off_plans + m * sizeof(DevPlan), 256);
+    pk.dom_at.resize(m);
+    std::vector<size_t> pos_at(m), list_at(m), sup_at(m);
     for (uint32_t j = 0; j < m; j++) {
+        const InstanceSpec &sp = *specs[j];
+        const size_t kw = (size_t)sp.p->g.n * sp.t->W;
+        pk.dom_at[j] = cur;
+        cur = align_up(cur + kw * 8, 64);
+        pos_at[j] = cur;
+        if (dense || sp.mode != SGE_RI) cur = align_up(cur + kw * 8, 64);
         list_at[j] = cur;
-        cur = align_up(cur + plans[j]->lists.size() * 4, 16);
+        cur = align_up(cur + list_entries(sp) * 4, 64);
+        sup_at[j] = cur;
+        if (sp.t->W > PLAN_LDS_WORDS) cur = align_up(cur + (size_t)sp.t->W * 8, 64);
     }
-    cur = align_up(cur, 256);
-    for (uint32_t j = 0; j < m; j++) {
-        bits_at[j] = cur;
-        cur = align_up(cur + bits[j]->size() * 8, 16);
-    }
-    pk.blob = std::max<size_t>(cur, 256);
+    pk.arena = std::max<size_t>(cur, 256);
     pk.ctr_bytes = align_up(m * sizeof(InstCounters), 64);
     hipError_t e;
-    if ((e = bufs.d_blob.reserve(pk.blob)) != hipSuccess) return hip_fail(c, e, "device plan buffer");
-    if ((e = bufs.h_blob.reserve(pk.blob)) != hipSuccess) return hip_fail(c, e, "pinned plan buffer");
+    if ((e = bufs.d_blob.reserve(pk.blob)) != hipSuccess) return hip_fail(c, e, "device descriptor buffer");
+    if ((e = bufs.d_arena.reserve(pk.arena)) != hipSuccess) return hip_fail(c, e, "device plan arena");
+    if ((e = bufs.h_blob.reserve(pk.blob)) != hipSuccess) return hip_fail(c, e, "pinned descriptor buffer");
     if ((e = bufs.h_ctr.reserve(pk.ctr_bytes + sizeof(Sched))) != hipSuccess) return hip_fail(c, e, "pinned counters");
     if ((e = ensure_work(bufs.work, m)) != hipSuccess) return hip_fail(c, e, "scheduler buffers");
     char *hb = (char *)bufs.h_blob.p;
     char *db = (char *)bufs.d_blob.p;
-
-    uint64_t total_roots = 0;
-    for (uint32_t j = 0; j < m; j++) total_roots += plans[j]->list_len[0];
-    unsigned *pref = (unsigned *)(hb + off_pref);
-    pref[0] = 0;
+    char *da = (char *)bufs.d_arena.p;
+    InstDesc *hdesc = (InstDesc *)(hb + off_desc);
+    PlanIn *hreq = (PlanIn *)(hb + pk.off_req);
     for (uint32_t j = 0; j < m; j++) {
-        const Plan &pl = *plans[j];
-        const InstanceSpec &s = *specs[j];
-        DevPlan &dp = ((DevPlan *)(hb + off_plan))[j];
-        std::memset(&dp, 0, sizeof(dp));
-        dp.k = pl.k;
-        dp.W = pl.W;
-        dp.n = pl.n;
-        dp.use_dom = pl.mode != SGE_RI;
-        dp.labelled = pl.labelled;
-        for (uint32_t i = 0; i < pl.k; i++) {
-            dp.parent[i] = pl.parent[i];
-            dp.back[i] = pl.back[i];
-            dp.plabel[i] = pl.plabel[i];
-            dp.pdeg[i] = pl.pdeg[i];
-            dp.order[i] = pl.order[i];
-            dp.list_off[i] = pl.list_off[i];
-            dp.list_len[i] = pl.list_len[i];
-        }
-        std::memcpy(hb + list_at[j], pl.lists.data(), pl.lists.size() * 4);
-        std::memcpy(hb + bits_at[j], bits[j]->data(), bits[j]->size() * 8);
-        InstDesc &d = ((InstDesc *)(hb + off_desc))[j];
-        d.col = s.t->d_col;
-        d.node = s.t->d_node;
-        d.adj = s.t->d_adj;
-        d.plan = (const DevPlan *)(db + off_plan) + j;
-        d.bits = bits[j]->empty() ? nullptr : (const uint64_t *)(db + bits_at[j]);
-        d.lists = (const uint32_t *)(db + list_at[j]);
-        d.rows = s.rows;
-        d.cap_rows = s.rows ? s.cap_rows : 0;
-        d.nroot = pl.list_len[0];
-        uint32_t chunk;
-        if (policy == 1) chunk = std::max<uint32_t>(1, d.nroot);
-        else if (c->root_chunk) chunk = c->root_chunk;
-        else chunk = (uint32_t)std::max<uint64_t>(1, total_roots / (4 * units));
-        d.chunk = chunk;
-        d.nchunks = d.nroot ? (d.nroot + chunk - 1) / chunk : 0;
-        pref[j + 1] = pref[j] + d.nchunks;
+        const InstanceSpec &sp = *specs[j];
+        const bool with_bits = dense || sp.mode != SGE_RI;
+        InstDesc &d = hdesc[j];
+        d = InstDesc{};
+        d.col = sp.t->d_col;
+        d.node = sp.t->d_node;
+        d.adj = sp.t->d_adj;
+        d.plan = (const DevPlan *)(da + off_plans) + j;
+        d.bits = with_bits ? (const uint64_t *)(da + pos_at[j]) : nullptr;
+        d.lists = (const uint32_t *)(da + list_at[j]);
+        d.rows = sp.rows;
+        d.cap_rows = sp.rows ? sp.cap_rows : 0;
+        PlanIn &r = hreq[j];
+        r = PlanIn{};
+        r.pat = sp.p->d_pat;
+        r.label_keys = sp.t->d_label_keys;
+        r.nlabels = (uint32_t)sp.t->label_keys.size();
+        r.mode = (uint32_t)sp.mode;
+        r.labelled = sp.labelled ? 1u : 0u;
+        r.n = sp.t->g.n;
+        r.W = sp.t->W;
+        r.root_lo = c->root_lo;
+        r.root_hi = c->root_hi;
+        r.desc = (InstDesc *)(db + off_desc) + j;
+        r.plan = (DevPlan *)(da + off_plans) + j;
+        r.dom = (uint64_t *)(da + pk.dom_at[j]);
+        r.pos_bits = with_bits ? (uint64_t *)(da + pos_at[j]) : nullptr;
+        r.lists = (uint32_t *)(da + list_at[j]);
+        r.list_cap = (uint32_t)std::min<uint64_t>(list_entries(sp), 0xFFFFFFFFull);
+        r.support = sp.t->W > PLAN_LDS_WORDS ? (uint64_t *)(da + sup_at[j]) : nullptr;
     }
-    pk.total_chunks = pref[m];
     bufs.work.inst = (InstDesc *)(db + off_desc);
-    bufs.work.chunk_prefix = (unsigned *)(db + off_pref);
+    bufs.work.chunk_prefix = (unsigned *)(db + pk.off_pref);
     return SGE_OK;
+}
+
+hipError_t enqueue_plan_only(const Pack &pk, LaunchBufs &bufs, uint32_t root_chunk, hipStream_t s) {
+    hipError_t r;
+    if ((r = hipMemcpyAsync(bufs.d_blob.p, bufs.h_blob.p, pk.upload, hipMemcpyHostToDevice, s)) != hipSuccess)
+        return r;
+    return launch_plan((const PlanIn *)((char *)bufs.d_blob.p + pk.off_req), pk.m, pk.cfg.wmax, bufs.work.inst,
+                       bufs.work.chunk_prefix, pk.policy, root_chunk, pk.units, s);
 }
 
 hipError_t enqueue_pack(sge_ctx *c, const Pack &pk, LaunchBufs &bufs, hipStream_t s) {
     hipError_t r;
-    if ((r = hipMemcpyAsync(bufs.d_blob.p, bufs.h_blob.p, pk.blob, hipMemcpyHostToDevice, s)) != hipSuccess) return r;
+    if ((r = enqueue_plan_only(pk, bufs, c->root_chunk, s)) != hipSuccess) return r;
     if ((r = launch_reset(bufs.work, pk.m, s)) != hipSuccess) return r;
-    if ((r = launch_search(pk.cfg, bufs.work, pk.m, pk.total_chunks, c->cap, c->time_limit_ms, s, c->num_cus)) !=
-        hipSuccess)
+    if ((r = launch_search(pk.cfg, bufs.work, pk.m, c->cap, c->time_limit_ms, s, c->num_cus)) != hipSuccess)
         return r;
     if ((r = hipMemcpyAsync(bufs.h_ctr.p, bufs.work.ctr, pk.m * sizeof(InstCounters), hipMemcpyDeviceToHost, s)) !=
         hipSuccess)
@@ -230,40 +240,24 @@ sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std
     auto t0 = clk::now();
     const size_t N = specs.size();
     out.assign(N, InstanceOut{});
-    std::vector<Plan> plans(N);
-    std::vector<std::vector<uint64_t>> bits(N);
-    std::vector<char> active(N, 0);
-    const bool dense = choose_dense(c, specs);
-    auto plan_one = [&](size_t i) { active[i] = plan_instance(c, specs[i], dense, plans[i], bits[i], out[i]); };
-    if (N >= 64) {
-        unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-        std::vector<std::thread> th;
-        for (unsigned w = 0; w < nt; w++)
-            th.emplace_back([&, w]() {
-                for (size_t i = w; i < N; i += nt) plan_one(i);
-            });
-        for (auto &x : th) x.join();
-    } else {
-        for (size_t i = 0; i < N; i++) plan_one(i);
-    }
     std::vector<const InstanceSpec *> sp;
-    std::vector<const Plan *> pp;
-    std::vector<const std::vector<uint64_t> *> bp;
     std::vector<InstanceOut *> op;
-    for (size_t i = 0; i < N; i++)
-        if (active[i]) {
-            sp.push_back(&specs[i]);
-            pp.push_back(&plans[i]);
-            bp.push_back(&bits[i]);
-            op.push_back(&out[i]);
+    for (size_t i = 0; i < N; i++) {
+        if (specs[i].p->g.n == 0) {   // the empty pattern has one (empty) match
+            out[i].matches = 1;
+            continue;
         }
+        sp.push_back(&specs[i]);
+        op.push_back(&out[i]);
+    }
     ms_search = 0;
     if (sp.empty()) {
         ms_prep = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
         return SGE_OK;
     }
+    const bool dense = choose_dense(c, specs);
     Pack pk;
-    sge_status st = pack_instances(c, sp, pp, bp, dense, policy, c->bufs, pk);
+    sge_status st = pack_instances(c, sp, dense, policy, c->bufs, pk);
     if (st != SGE_OK) return st;
     hipStream_t s = c->stream;
     ms_prep = std::chrono::duration<double, std::milli>(clk::now() - t0).count();

@@ -1,0 +1,397 @@
+// Device preparation of a batch of searches: one workgroup plans one
+// instance from the resident pattern and target, then one block sets the root
+// chunking of every instance.  The plan is the one the host planner
+// (sge_plan.cpp) builds, step for step:
+//
+//  * Domains (Section 4.1): D(u) starts as the target nodes passing the label
+//    and degree rules for pattern node u, built a word (64 nodes) at a time
+//    with one ballot per pattern node.
+//  * Arc-consistency (Section 4.1) to the greatest fixpoint, in support form:
+//    v stays in D(u) iff for each pattern neighbour w of u some target
+//    neighbour of v lies in D(w), i.e. v lies in the support set S(w), the
+//    union of the target rows of D(w).  S(w) is scattered into LDS with atomic
+//    ORs, one lane per member of D(w); the pattern neighbours of w are then
+//    intersected with it.  A round recomputes S(w) only for the w whose domain
+//    changed in the previous round.
+//  * Forward checking (Section 4.2.2): while a domain is a singleton {t} that
+//    has not been used, t leaves every other domain.
+//  * The constraint-first order (Section "RI"; singletons first and the
+//    domain-size tie-break of Section 4.2.1): lane u of one wave scores
+//    pattern node u, and a wave-wide maximum of the packed key
+//    (w_m, w_n, degree, [-|D(u)|], -u) picks the next node.
+//  * Parents and back-edges, the per-position bitsets the search reads, and
+//    the candidate lists of parentless positions (compacted by a wave scan;
+//    position 0 limited to the root range).
+#include <hip/hip_runtime.h>
+
+#include "sge_internal.h"
+
+namespace sge {
+
+namespace {
+
+constexpr int PLAN_THREADS = 256;
+constexpr int PLAN_WAVES = PLAN_THREADS / 64;
+
+// dense id of a raw label among the target's increasing label keys
+__device__ uint32_t label_id(const uint32_t *keys, uint32_t nl, uint32_t raw) {
+    uint32_t lo = 0, hi = nl;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (keys[mid] < raw) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < nl && keys[lo] == raw) ? lo : LABEL_NONE;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+__device__ __forceinline__ unsigned long long wave_max(unsigned long long x) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(x, o);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+// bits of word t (nodes 64t .. 64t+63) that lie in [lo, hi)
+__device__ __forceinline__ unsigned long long range_mask(uint32_t t, uint32_t lo, uint32_t hi) {
+    const unsigned long long base = (unsigned long long)t * 64;
+    const unsigned long long a = lo > base ? lo - base : 0, b = hi < base + 64 ? (hi > base ? hi - base : 0) : 64;
+    if (a >= b) return 0ull;
+    const unsigned long long upto_b = b == 64 ? ~0ull : ((1ull << b) - 1);
+    return upto_b & ~((1ull << a) - 1);
+}
+
+__global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs) {
+    extern __shared__ unsigned long long s_support[];
+    __shared__ unsigned long long s_nb[KMAX];
+    __shared__ uint32_t s_lab[KMAX], s_deg[KMAX], s_dsize[KMAX], s_order[KMAX], s_pos[KMAX];
+    __shared__ int32_t s_par[KMAX];
+    __shared__ unsigned long long s_next;
+    __shared__ int s_empty;
+
+    const PlanIn R = reqs[blockIdx.x];
+    const DevPattern *pat = R.pat;
+    const uint32_t k = pat->k, n = R.n, W = R.W;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool use_dom = R.mode != SGE_RI;
+    const bool use_si = R.mode == SGE_RIDS_SI || R.mode == SGE_RIDS_SI_FC;
+    const NodeRec *node = R.desc->node;
+    const uint32_t *col = R.desc->col;
+    uint64_t *D = R.dom;
+    unsigned long long *S = W <= PLAN_LDS_WORDS ? s_support : reinterpret_cast<unsigned long long *>(R.support);
+    DevPlan *pl = R.plan;
+
+    if ((uint32_t)tid < k) {
+        s_nb[tid] = pat->nb[tid];
+        s_deg[tid] = pat->deg[tid];
+        s_lab[tid] = R.labelled ? label_id(R.label_keys, R.nlabels, pat->label[tid]) : LABEL_ANY;
+    }
+    if (tid == 0) s_empty = 0;
+    __syncthreads();
+
+    // label and degree domains; lane l of a wave decides node 64 i + l
+    for (uint32_t i = wave; i < W; i += PLAN_WAVES) {
+        const uint32_t v = i * 64 + lane;
+        const bool valid = v < n;
+        uint32_t vl = LABEL_NONE, vd = 0;
+        if (valid) {
+            const NodeRec r = node[v];
+            vl = r.label;
+            vd = r.deg;
+        }
+        unsigned long long mine = 0;
+        for (uint32_t u = 0; u < k; u++) {
+            const uint32_t lu = s_lab[u];
+            const bool p = valid && (lu == LABEL_ANY || vl == lu) && vd >= s_deg[u];
+            const unsigned long long b = __ballot(p);
+            if ((uint32_t)lane == u) mine = b;
+        }
+        if ((uint32_t)lane < k) D[(size_t)lane * W + i] = mine;
+    }
+    __syncthreads();
+
+    // arc-consistency to the fixpoint
+    if (use_dom) {
+        unsigned long long dirty = 0;
+        for (uint32_t u = 0; u < k; u++)
+            if (s_nb[u]) dirty |= 1ull << u;
+        while (dirty) {
+            if (tid == 0) s_next = 0;
+            for (unsigned long long dm = dirty; dm; dm &= dm - 1) {
+                const uint32_t w = (uint32_t)__builtin_ctzll(dm);
+                for (uint32_t i = tid; i < W; i += PLAN_THREADS) S[i] = 0;
+                __syncthreads();
+                // S(w): every target neighbour of a member of D(w)
+                for (uint32_t i = wave; i < W; i += PLAN_WAVES) {
+                    const uint64_t word = D[(size_t)w * W + i];
+                    if ((word >> lane) & 1ull) {
+                        const NodeRec r = node[i * 64 + lane];
+                        for (uint32_t e = r.begin; e < r.begin + r.deg; e++) {
+                            const uint32_t y = col[e];
+                            atomicOr(&S[y >> 6], 1ull << (y & 63));
+                        }
+                    }
+                }
+                __syncthreads();
+                // revise the pattern neighbours of w against S(w)
+                for (unsigned long long um = s_nb[w]; um; um &= um - 1) {
+                    const uint32_t u = (uint32_t)__builtin_ctzll(um);
+                    bool ch = false;
+                    for (uint32_t i = tid; i < W; i += PLAN_THREADS) {
+                        const uint64_t old = D[(size_t)u * W + i], nw = old & S[i];
+                        if (nw != old) {
+                            D[(size_t)u * W + i] = nw;
+                            ch = true;
+                        }
+                    }
+                    if (ch) atomicOr(&s_next, 1ull << u);
+                }
+                __syncthreads();
+            }
+            dirty = s_next;
+            __syncthreads();
+        }
+    }
+
+    // domain sizes; an empty domain leaves nothing to search
+    for (uint32_t u = wave; u < k; u += PLAN_WAVES) {
+        uint32_t c = 0;
+        for (uint32_t i = lane; i < W; i += 64) c += (uint32_t)__popcll(D[(size_t)u * W + i]);
+        c = wave_sum(c);
+        if (lane == 0) s_dsize[u] = c;
+    }
+    __syncthreads();
+    if (use_dom && tid == 0)
+        for (uint32_t u = 0; u < k; u++)
+            if (s_dsize[u] == 0) s_empty = 1;
+    __syncthreads();
+
+    // forward checking (one wave; lane u holds |D(u)|)
+    if (R.mode == SGE_RIDS_SI_FC && !s_empty) {
+        if (wave == 0) {
+            unsigned long long done = 0;
+            uint32_t mysize = (uint32_t)lane < k ? s_dsize[lane] : 0;
+            bool emp = false;
+            while (!emp) {
+                const unsigned long long cand = __ballot((uint32_t)lane < k && !((done >> lane) & 1ull) && mysize == 1);
+                if (!cand) break;
+                const uint32_t u = (uint32_t)__builtin_ctzll(cand);
+                done |= 1ull << u;
+                uint32_t t = 0xFFFFFFFFu;   // the member of D(u)
+                for (uint32_t i0 = 0; i0 < W; i0 += 64) {
+                    const uint32_t i = i0 + lane;
+                    const unsigned long long x = i < W ? D[(size_t)u * W + i] : 0ull;
+                    const unsigned long long b = __ballot(x != 0ull);
+                    if (b) {
+                        const uint32_t j = (uint32_t)__builtin_ctzll(b);
+                        const unsigned long long xw = __shfl(x, (int)j);
+                        t = (i0 + j) * 64 + (uint32_t)__builtin_ctzll(xw);
+                        break;
+                    }
+                }
+                if (t != 0xFFFFFFFFu && (uint32_t)lane < k && (uint32_t)lane != u) {
+                    uint64_t *pw = &D[(size_t)lane * W + (t >> 6)];
+                    const uint64_t bit = 1ull << (t & 63);
+                    const uint64_t x = *pw;
+                    if (x & bit) {
+                        *pw = x & ~bit;
+                        mysize--;
+                    }
+                }
+                emp = __ballot((uint32_t)lane < k && mysize == 0) != 0ull;
+            }
+            if ((uint32_t)lane < k) s_dsize[lane] = mysize;
+            if (emp && lane == 0) s_empty = 1;
+        }
+        __syncthreads();
+    }
+    const bool empty = s_empty != 0;
+
+    // the constraint-first order (one wave; lane u scores pattern node u)
+    if (!empty && wave == 0) {
+        const bool mine = (uint32_t)lane < k;
+        const unsigned long long mynb = mine ? s_nb[lane] : 0ull;
+        const uint32_t mydeg = mine ? s_deg[lane] : 0u, mysz = mine ? s_dsize[lane] : 0u;
+        unsigned long long placed = 0;
+        uint32_t len = 0;
+        if (use_dom) {
+            for (unsigned long long single = __ballot(mine && mysz == 1); single; single &= single - 1) {
+                const uint32_t u = (uint32_t)__builtin_ctzll(single);
+                if (lane == 0) s_order[len] = u;
+                len++;
+                placed |= 1ull << u;
+            }
+        }
+        while (len < k) {
+            unsigned long long key = 0;
+            if (mine && !((placed >> lane) & 1ull)) {
+                const uint32_t wm = (uint32_t)__popcll(mynb & placed);
+                uint32_t wn = 0;
+                for (unsigned long long m = placed; m; m &= m - 1)
+                    if (mynb & s_nb[__builtin_ctzll(m)] & ~placed) wn++;
+                // w_m, w_n and degree are below 64; the smaller domain and then
+                // the lower id win the remaining ties
+                key = (1ull << 62) | ((unsigned long long)wm << 50) | ((unsigned long long)wn << 44) |
+                      ((unsigned long long)mydeg << 38) | ((unsigned long long)(use_si ? ~mysz : 0u) << 6) |
+                      (unsigned long long)(63 - lane);
+            }
+            key = wave_max(key);
+            const uint32_t u = 63u - (uint32_t)(key & 63ull);
+            if (lane == 0) s_order[len] = u;
+            len++;
+            placed |= 1ull << u;
+        }
+    }
+    __syncthreads();
+
+    if (tid == 0) {
+        pl->k = k;
+        pl->W = W;
+        pl->n = n;
+        pl->use_dom = use_dom ? 1u : 0u;
+        pl->labelled = R.labelled;
+        pl->empty = empty ? 1u : 0u;
+        if (empty) {
+            pl->list_len[0] = 0;
+            R.desc->nroot = 0;
+        }
+    }
+    if (empty) return;
+
+    // parents and back-edges (lane i: position i)
+    if ((uint32_t)tid < k) s_pos[s_order[tid]] = (uint32_t)tid;
+    __syncthreads();
+    if ((uint32_t)tid < k) {
+        const uint32_t u = s_order[tid];
+        unsigned long long earlier = 0;
+        for (unsigned long long m = s_nb[u]; m; m &= m - 1) {
+            const uint32_t j = s_pos[__builtin_ctzll(m)];
+            if (j < (uint32_t)tid) earlier |= 1ull << j;
+        }
+        const int32_t par = earlier ? (int32_t)__builtin_ctzll(earlier) : -1;
+        s_par[tid] = par;
+        pl->parent[tid] = par;
+        pl->back[tid] = earlier ? (earlier & (earlier - 1)) : 0ull;
+        pl->plabel[tid] = s_lab[u];
+        pl->pdeg[tid] = s_deg[u];
+        pl->order[tid] = u;
+        pl->list_off[tid] = 0;
+        pl->list_len[tid] = 0;
+    }
+    __syncthreads();
+
+    // per-position bitsets: the domain (RI-DS) or the label/degree set (RI)
+    if (R.pos_bits) {
+        const uint32_t kw = k * W;
+        for (uint32_t idx = tid; idx < kw; idx += PLAN_THREADS) {
+            const uint32_t i = idx / W, t = idx - i * W;
+            uint64_t x = D[(size_t)s_order[i] * W + t];
+            if (i == 0) x &= range_mask(t, R.root_lo, R.root_hi);
+            R.pos_bits[idx] = x;
+        }
+    }
+    // candidate lists of the parentless positions, in increasing node order
+    if (wave == 0) {
+        uint32_t off = 0;
+        for (uint32_t i = 0; i < k; i++) {
+            if (s_par[i] >= 0) continue;
+            const uint64_t *row = &D[(size_t)s_order[i] * W];
+            const uint32_t start = off;
+            for (uint32_t i0 = 0; i0 < W; i0 += 64) {
+                const uint32_t t = i0 + lane;
+                unsigned long long x = t < W ? row[t] : 0ull;
+                if (i == 0) x &= range_mask(t, R.root_lo, R.root_hi);
+                const uint32_t c = (uint32_t)__popcll(x);
+                uint32_t s = c;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const uint32_t y = __shfl_up(s, o);
+                    if (lane >= o) s += y;
+                }
+                uint32_t o = off + s - c;
+                for (unsigned long long y = x; y; y &= y - 1, o++)
+                    if (o < R.list_cap) R.lists[o] = t * 64 + (uint32_t)__builtin_ctzll(y);
+                off += __shfl(s, 63);
+            }
+            // lists fit by construction (list_cap); should they not, keep
+            // every list inside the buffer
+            const uint32_t len = off > R.list_cap ? (start < R.list_cap ? R.list_cap - start : 0u) : off - start;
+            if (lane == 0) {
+                pl->list_off[i] = start;
+                pl->list_len[i] = len;
+                if (i == 0) R.desc->nroot = len;
+            }
+        }
+    }
+}
+
+// Root chunks of every instance and their exclusive prefix (one block).
+constexpr int FIN_THREADS = 1024;
+
+__global__ void __launch_bounds__(FIN_THREADS)
+    finalize_kernel(InstDesc *desc, unsigned *prefix, uint32_t m, int policy, uint32_t root_chunk,
+                    unsigned long long units) {
+    __shared__ unsigned long long s_red[FIN_THREADS];
+    __shared__ unsigned s_scan[FIN_THREADS];
+    const int tid = threadIdx.x;
+    unsigned long long t = 0;
+    for (uint32_t j = tid; j < m; j += FIN_THREADS) t += desc[j].nroot;
+    s_red[tid] = t;
+    __syncthreads();
+    for (int o = FIN_THREADS / 2; o > 0; o >>= 1) {
+        if (tid < o) s_red[tid] += s_red[tid + o];
+        __syncthreads();
+    }
+    const unsigned long long total = s_red[0];
+    const unsigned long long q = total / (4ull * (units ? units : 1ull));
+    const uint32_t chunk_default = q < 1 ? 1u : (q > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)q);
+    // thread tid owns instances [lo, hi)
+    const uint32_t per = (m + FIN_THREADS - 1) / FIN_THREADS;
+    const uint32_t lo = min(m, (uint32_t)tid * per), hi = min(m, lo + per);
+    unsigned local = 0;
+    for (uint32_t j = lo; j < hi; j++) {
+        const uint32_t nr = desc[j].nroot;
+        uint32_t chunk;
+        if (policy == 1) chunk = nr ? nr : 1u;
+        else if (root_chunk) chunk = root_chunk;
+        else chunk = chunk_default;
+        const uint32_t nch = nr ? (uint32_t)(((unsigned long long)nr + chunk - 1) / chunk) : 0u;
+        desc[j].chunk = chunk;
+        desc[j].nchunks = nch;
+        local += nch;
+    }
+    s_scan[tid] = local;
+    __syncthreads();
+    for (int o = 1; o < FIN_THREADS; o <<= 1) {   // inclusive scan
+        const unsigned y = tid >= o ? s_scan[tid - o] : 0u;
+        __syncthreads();
+        s_scan[tid] += y;
+        __syncthreads();
+    }
+    unsigned base = s_scan[tid] - local;
+    for (uint32_t j = lo; j < hi; j++) {
+        prefix[j] = base;
+        base += desc[j].nchunks;
+    }
+    if (tid == FIN_THREADS - 1) prefix[m] = s_scan[tid];
+}
+
+}  // namespace
+
+hipError_t launch_plan(const PlanIn *reqs, uint32_t m, uint32_t wmax, InstDesc *desc, unsigned *chunk_prefix,
+                       int policy, uint32_t root_chunk, uint64_t units, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    const size_t lds = (size_t)std::min<uint32_t>(std::max<uint32_t>(wmax, 1), PLAN_LDS_WORDS) * 8;
+    hipLaunchKernelGGL(plan_kernel, dim3(m), dim3(PLAN_THREADS), lds, s, reqs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(FIN_THREADS), 0, s, desc, chunk_prefix, m, policy, root_chunk,
+                       (unsigned long long)units);
+    return hipGetLastError();
+}
+
+}  // namespace sge

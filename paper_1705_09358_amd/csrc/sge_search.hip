@@ -64,6 +64,8 @@ struct SearchArgs {
     unsigned donate_period;           // a unit gives work away at most once per this many of its steps
     unsigned long long state_cap;
     unsigned long long limit_ticks;   // time limit in s_memrealtime ticks (100 MHz); 0 = none
+    unsigned min_blocks;              // blocks kept whatever the number of root chunks
+    unsigned units_per_block;
 };
 
 constexpr unsigned FULL_RANGE = 0xFFFFFFFFu;
@@ -218,6 +220,9 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
 
     Sched *S = a.sched;
     const unsigned nchunks = a.chunk_prefix[a.ninst];
+    // blocks beyond four units per root chunk (and the minimum) have nothing to start with
+    const unsigned long long want = (4ull * nchunks + a.units_per_block - 1) / a.units_per_block;
+    if (blockIdx.x >= max((unsigned long long)min(gridDim.x, a.min_blocks), want)) return;
     if (threadIdx.x == 0) atomicMin(&S->t_start, now_ticks());
     if (nchunks == 0) {   // no root candidate anywhere: nothing to search
         if (lane == 0) atomicMax(&S->t_end, now_ticks());
@@ -883,20 +888,18 @@ __global__ void reset_kernel(Sched *s, InstCounters *c, unsigned ninst, QTask *q
 }
 
 template <int G, bool DENSE>
-hipError_t launch_g(const SearchArgs &args, int blocks, int threads, size_t lds, hipStream_t s, int num_cus,
-                    uint32_t total_chunks) {
+hipError_t launch_g(SearchArgs args, int blocks, int threads, size_t lds, hipStream_t s, int num_cus) {
     if (blocks <= 0) {
-        // resident blocks only (a persistent grid), and no more than the root
-        // chunks can keep busy before work is handed around
+        // resident blocks only (a persistent grid); the kernel trims it to
+        // what the root chunks can keep busy before work is handed around
         int per_cu = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel<G, DENSE>, threads, lds);
         if (e != hipSuccess) return e;
         if (per_cu < 1) per_cu = 1;
-        int units_per_block = threads / G;
-        long want = (4L * total_chunks + units_per_block - 1) / units_per_block;
-        if (want < 2L * num_cus) want = 2L * num_cus;
-        blocks = (int)std::min<long>((long)per_cu * num_cus, want);
+        blocks = per_cu * num_cus;
     }
+    args.min_blocks = (unsigned)std::max(1, 2 * num_cus);
+    args.units_per_block = (unsigned)(threads / G);
     hipLaunchKernelGGL((search_kernel<G, DENSE>), dim3(blocks), dim3(threads), lds, s, args);
     return hipGetLastError();
 }
@@ -928,8 +931,8 @@ hipError_t launch_reset(DevWork &w, uint32_t ninst, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_search(const LaunchCfg &cfg, DevWork &w, uint32_t ninst, uint32_t total_chunks,
-                         uint64_t state_cap, uint64_t time_limit_ms, hipStream_t s, int num_cus) {
+hipError_t launch_search(const LaunchCfg &cfg, DevWork &w, uint32_t ninst, uint64_t state_cap,
+                         uint64_t time_limit_ms, hipStream_t s, int num_cus) {
     SearchArgs a{};
     a.inst = w.inst;
     a.chunk_prefix = w.chunk_prefix;
@@ -952,18 +955,18 @@ hipError_t launch_search(const LaunchCfg &cfg, DevWork &w, uint32_t ninst, uint3
     int blocks = cfg.blocks;
     if (cfg.dense) {
         switch (cfg.lanes) {
-            case 8: return launch_g<8, true>(a, blocks, threads, lds, s, num_cus, total_chunks);
-            case 16: return launch_g<16, true>(a, blocks, threads, lds, s, num_cus, total_chunks);
-            case 32: return launch_g<32, true>(a, blocks, threads, lds, s, num_cus, total_chunks);
-            case 64: return launch_g<64, true>(a, blocks, threads, lds, s, num_cus, total_chunks);
+            case 8: return launch_g<8, true>(a, blocks, threads, lds, s, num_cus);
+            case 16: return launch_g<16, true>(a, blocks, threads, lds, s, num_cus);
+            case 32: return launch_g<32, true>(a, blocks, threads, lds, s, num_cus);
+            case 64: return launch_g<64, true>(a, blocks, threads, lds, s, num_cus);
             default: return hipErrorInvalidValue;
         }
     }
     switch (cfg.lanes) {
-        case 8: return launch_g<8, false>(a, blocks, threads, lds, s, num_cus, total_chunks);
-        case 16: return launch_g<16, false>(a, blocks, threads, lds, s, num_cus, total_chunks);
-        case 32: return launch_g<32, false>(a, blocks, threads, lds, s, num_cus, total_chunks);
-        case 64: return launch_g<64, false>(a, blocks, threads, lds, s, num_cus, total_chunks);
+        case 8: return launch_g<8, false>(a, blocks, threads, lds, s, num_cus);
+        case 16: return launch_g<16, false>(a, blocks, threads, lds, s, num_cus);
+        case 32: return launch_g<32, false>(a, blocks, threads, lds, s, num_cus);
+        case 64: return launch_g<64, false>(a, blocks, threads, lds, s, num_cus);
         default: return hipErrorInvalidValue;
     }
 }

@@ -1,16 +1,16 @@
 // Serving: continuous batching of pattern queries on resident targets.
 //
-// Targets (CSR, node records, adjacency rows) stay resident on the device.
-// A query is admitted when a slot is free and its device bytes (plan,
-// domains, candidate lists) fit in the arena budget; otherwise submit says
-// SGE_E_BUSY and the caller retries.  Admitted queries are prepared (order,
-// RI-DS domains with arc-consistency and forward checking) by a pool of host
-// threads.  A dispatcher thread packs whatever is ready into one persistent
-// search launch on the first idle launch lane (one HIP stream each, with its
-// own scheduler state and buffers), so queries that arrive while earlier ones
-// are on the GPU start at once on another lane and run beside them.  When a
-// lane's launch completes its queries' results become visible to poll and
-// their slots and bytes are released.
+// Targets (CSR, node records, adjacency rows, label keys) and patterns stay
+// resident on the device.  A query is admitted when a slot is free and its
+// device bytes (plan, domains, candidate lists) fit in the arena budget;
+// otherwise submit says SGE_E_BUSY and the caller retries.  A dispatcher
+// thread packs every admitted query into one launch on the first idle launch
+// lane (one HIP stream each, with its own scheduler state and buffers): the
+// launch plans each query on the device (order, RI-DS domains with
+// arc-consistency and forward checking) and searches them all, so queries
+// that arrive while earlier ones are on the GPU start at once on another lane
+// and run beside them.  When a lane's launch completes its queries' results
+// become visible to poll and their slots and bytes are released.
 #include <algorithm>
 #include <condition_variable>
 #include <deque>
@@ -26,8 +26,6 @@ namespace sge {
 struct Query {
     uint64_t ticket = 0;
     InstanceSpec spec;
-    Plan plan;
-    std::vector<uint64_t> bits;
     InstanceOut out;
     uint64_t bytes = 0;
     bool done = false;
@@ -48,13 +46,12 @@ struct Server {
     uint32_t slots = 0;
     uint64_t arena = 0;
     std::mutex mu;
-    std::condition_variable cv_prep, cv_disp;
+    std::condition_variable cv_disp;
     std::map<uint64_t, std::unique_ptr<Query>> queries;
     uint64_t next_ticket = 1;
     uint64_t bytes_in_use = 0;
     uint32_t in_flight = 0;
-    std::deque<Query *> prep_q, ready_q;
-    std::vector<std::thread> preppers;
+    std::deque<Query *> ready_q;
     std::thread dispatcher;
     std::vector<LaunchLane> lanes;
     bool stopping = false;
@@ -65,43 +62,9 @@ struct Server {
         bytes_in_use -= q->bytes;
         in_flight--;
     }
-    void prep_loop();
     void dispatch_loop();
 };
 void ServerDeleter::operator()(Server *s) const { delete s; }
-
-// Device bytes a query holds while admitted: its plan record and descriptor,
-// the domain (or label/degree) rows by position, and candidate lists.
-static uint64_t query_bytes(const Target &t, const Pattern &p) {
-    uint64_t k = p.g.n;
-    return sizeof(DevPlan) + sizeof(InstDesc) + sizeof(InstCounters) + k * t.W * 8 + (uint64_t)t.g.n * 4;
-}
-
-void Server::prep_loop() {
-    (void)hipSetDevice(c->device);
-    for (;;) {
-        Query *q;
-        {
-            std::unique_lock<std::mutex> lk(mu);
-            cv_prep.wait(lk, [&] { return stopping || !prep_q.empty(); });
-            if (prep_q.empty()) return;
-            q = prep_q.front();
-            prep_q.pop_front();
-        }
-        auto t0 = clk::now();
-        std::vector<InstanceSpec> one{q->spec};
-        bool dense = choose_dense(c, one);
-        bool need = plan_instance(c, q->spec, dense, q->plan, q->bits, q->out);
-        q->ms_prep = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
-        std::lock_guard<std::mutex> lk(mu);
-        if (need) {
-            ready_q.push_back(q);
-            cv_disp.notify_one();
-        } else {
-            release(q);
-        }
-    }
-}
 
 void Server::dispatch_loop() {
     (void)hipSetDevice(c->device);
@@ -136,7 +99,7 @@ void Server::dispatch_loop() {
             std::unique_lock<std::mutex> lk(mu);
             bool any_busy = false;
             for (LaunchLane &ln : lanes) any_busy |= ln.busy;
-            if (stopping && ready_q.empty() && prep_q.empty() && !any_busy) return;
+            if (stopping && ready_q.empty() && !any_busy) return;
             for (LaunchLane &ln : lanes)
                 if (!ln.busy) { lane = &ln; break; }
             if (lane && !ready_q.empty() && fatal.empty()) {
@@ -150,18 +113,17 @@ void Server::dispatch_loop() {
                 continue;
             }
         }
+        auto t0 = clk::now();
         std::vector<const InstanceSpec *> sp;
-        std::vector<const Plan *> pp;
-        std::vector<const std::vector<uint64_t> *> bp;
         std::vector<InstanceSpec> specs;
         for (Query *q : take) {
             sp.push_back(&q->spec);
-            pp.push_back(&q->plan);
-            bp.push_back(&q->bits);
             specs.push_back(q->spec);
         }
         bool dense = choose_dense(c, specs);
-        sge_status st = pack_instances(c, sp, pp, bp, dense, 2, lane->bufs, lane->pk);
+        sge_status st = pack_instances(c, sp, dense, 2, lane->bufs, lane->pk);
+        const double ms_pack = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+        for (Query *q : take) q->ms_prep = ms_pack;
         hipError_t e = hipSuccess;
         if (st == SGE_OK) {
             // a share of the device per lane, so launches of several lanes run side by side
@@ -194,9 +156,7 @@ __attribute__((visibility("hidden"))) void sge_serve_shutdown_internal(sge_ctx *
         std::lock_guard<std::mutex> lk(sv->mu);
         sv->stopping = true;
     }
-    sv->cv_prep.notify_all();
     sv->cv_disp.notify_all();
-    for (auto &t : sv->preppers) t.join();
     if (sv->dispatcher.joinable()) sv->dispatcher.join();
     for (LaunchLane &ln : sv->lanes) {
         if (ln.s) (void)hipStreamSynchronize(ln.s);
@@ -227,8 +187,6 @@ sge_status sge_serve_start(sge_ctx *c, uint32_t slots, uint64_t arena_bytes) {
             return hip_fail(c, e, "server streams");
         }
     }
-    unsigned np = std::max(2u, std::min(8u, std::thread::hardware_concurrency() / 2));
-    for (unsigned i = 0; i < np; i++) sv->preppers.emplace_back([sv] { sv->prep_loop(); });
     sv->dispatcher = std::thread([sv] { sv->dispatch_loop(); });
     return SGE_OK;
 }
@@ -247,7 +205,7 @@ sge_status sge_serve_submit(sge_ctx *c, const sge_job *job, uint64_t *ticket) {
     q->spec.p = ip->second.get();
     q->spec.mode = job->mode;
     q->spec.labelled = job->labelled != 0;
-    q->bytes = query_bytes(*q->spec.t, *q->spec.p);
+    q->bytes = instance_device_bytes(q->spec);
     std::lock_guard<std::mutex> lk(sv->mu);
     if (!sv->fatal.empty()) return fail(c, SGE_E_DEVICE, sv->fatal);
     if (sv->stopping) return fail(c, SGE_E_INVAL, "server is stopping");
@@ -258,9 +216,14 @@ sge_status sge_serve_submit(sge_ctx *c, const sge_job *job, uint64_t *ticket) {
     *ticket = q->ticket;
     sv->in_flight++;
     sv->bytes_in_use += q->bytes;
-    sv->prep_q.push_back(q.get());
+    if (q->spec.p->g.n == 0) {   // the empty pattern has one (empty) match
+        q->out.matches = 1;
+        sv->release(q.get());
+    } else {
+        sv->ready_q.push_back(q.get());
+        sv->cv_disp.notify_one();
+    }
     sv->queries[q->ticket] = std::move(q);
-    sv->cv_prep.notify_one();
     return SGE_OK;
 }
 

@@ -1,7 +1,8 @@
 """Thin ctypes binding of the C ABI in ``include/sge.h`` (argument marshalling only).
 
-Every step of the search runs in the native library ``_lib/libsge.so`` (host
-preparation in C++, the search in HIP kernels for gfx950).  If the library is
+Every step of the search runs in the native library ``_lib/libsge.so``: input
+validation in C++ when graphs are loaded, the plan and the search in HIP
+kernels for gfx950.  If the library is
 missing it is built in-tree; if it cannot be loaded an error is raised -- there
 is no fallback path.
 """
@@ -25,7 +26,8 @@ EXPORTS = [
     "sge_create", "sge_destroy", "sge_last_error", "sge_load_target", "sge_unload_target", "sge_load_pattern",
     "sge_unload_pattern", "sge_set_labelled", "sge_set_mode", "sge_set_state_cap", "sge_set_root_range",
     "sge_count", "sge_enumerate", "sge_batch_run", "sge_set_batch_policy", "sge_serve_start", "sge_serve_submit",
-    "sge_serve_poll", "sge_serve_stop", "sge_plan_host", "sge_set_tuning", "sge_set_time_limit", "sge_last_launch_timing",
+    "sge_serve_poll", "sge_serve_stop", "sge_plan_host", "sge_plan_device", "sge_set_tuning", "sge_set_time_limit",
+    "sge_last_launch_timing",
 ]
 
 
@@ -134,6 +136,7 @@ def lib() -> ctypes.CDLL:
             "sge_serve_poll": (I32, [P, U64, ctypes.POINTER(c_result)]),
             "sge_serve_stop": (I32, [P]),
             "sge_plan_host": (I32, [U32, P, P, P, U32, P, P, P, I32, I32, P, P, P, ctypes.POINTER(I32)]),
+            "sge_plan_device": (I32, [P, U32, U32, I32, I32, P, P, P, ctypes.POINTER(U32), ctypes.POINTER(I32)]),
             "sge_set_tuning": (I32, [P, I32, U32, I32, I32]),
             "sge_set_time_limit": (I32, [P, U64]),
             "sge_last_launch_timing": (I32, [P, P]),
@@ -216,6 +219,25 @@ class Context:
         out = (ctypes.c_double * 3)()
         self._check(self._L.sge_last_launch_timing(self._h, ctypes.addressof(out)), "sge_last_launch_timing")
         return tuple(out)
+
+    def plan_device(self, target: int, pattern: int, k: int, n: int, mode: int, labelled: bool) -> dict:
+        """The plan the device computes before a search: order, parents, the
+        number of root candidates and (RI-DS modes) domains as bool [k, n]."""
+        W = (n + 63) // 64
+        order = np.zeros(max(k, 1), np.uint32)
+        parent = np.zeros(max(k, 1), np.int32)
+        dom = np.zeros(max(k * W, 1), np.uint64)
+        nroot = ctypes.c_uint32(0)
+        empty = ctypes.c_int(0)
+        self._check(self._L.sge_plan_device(self._h, target, pattern, mode, int(bool(labelled)), order.ctypes.data,
+                                            parent.ctypes.data, dom.ctypes.data, ctypes.byref(nroot),
+                                            ctypes.byref(empty)), "sge_plan_device")
+        domains = None
+        if mode != RI and k and not empty.value:
+            bits = np.unpackbits(dom[:k * W].view(np.uint8).reshape(k, W * 8), axis=1, bitorder="little")
+            domains = bits[:, :n].astype(bool)
+        return dict(order=order[:k].copy(), parent=parent[:k].copy(), nroot=int(nroot.value),
+                    empty=bool(empty.value), domains=domains)
 
     def last_error(self) -> str:
         m = self._L.sge_last_error(self._h)
