@@ -189,6 +189,12 @@ sge_status sge_plan_host(uint32_t k, const uint32_t *p_row_ptr, const uint32_t *
 sge_status sge_plan_device(sge_ctx *ctx, uint32_t target, uint32_t pattern, int mode, int labelled, uint32_t *order,
                            int32_t *parent, uint64_t *dom, uint32_t *nroot, int *empty);
 
+/* Where launches are planned: -1 = automatic (on the device for launches of
+ * 64 or more instances, on the host otherwise), 0 = always on the host
+ * (C++ on the calling thread, or the server's preparation threads), 1 = always
+ * on the device (the plan kernel).  Both give the same plan. */
+sge_status sge_set_plan_location(sge_ctx *ctx, int where);
+
 /* Tuning knobs (for measurement): lanes per search unit (8, 16, 32 or 64;
  * 0 = automatic), root chunk size (0 = automatic), work donation (0 = off,
  * 1 = on with the default period, N > 1 = a unit gives work away at most

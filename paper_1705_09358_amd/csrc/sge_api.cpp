@@ -288,6 +288,13 @@ sge_status sge_set_root_range(sge_ctx *c, uint32_t lo, uint32_t hi) {
     return SGE_OK;
 }
 
+sge_status sge_set_plan_location(sge_ctx *c, int where) {
+    if (!c) return SGE_E_INVAL;
+    if (where < -1 || where > 1) return fail(c, SGE_E_INVAL, "plan location must be -1, 0 or 1");
+    c->plan_where = where;
+    return SGE_OK;
+}
+
 sge_status sge_set_tuning(sge_ctx *c, int lanes, uint32_t root_chunk, int donate, int dense) {
     if (!c) return SGE_E_INVAL;
     if (lanes != 0 && lanes != 8 && lanes != 16 && lanes != 32 && lanes != 64)

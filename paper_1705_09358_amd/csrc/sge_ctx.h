@@ -71,6 +71,7 @@ struct sge_ctx {
     int lanes = 0, dense = -1, donate = 1;
     uint32_t root_chunk = 0;
     int batch_policy = 0;
+    int plan_where = -1;   // -1 automatic, 0 host, 1 device
     // batch autotuner's choice by batch size: (policy, lanes); cleared when tuning changes
     std::map<uint32_t, std::pair<int, int>> batch_tune;
     int num_cus = 0;
@@ -111,6 +112,7 @@ struct Pack {
     LaunchCfg cfg;
     uint32_t m = 0;
     int policy = 2;
+    bool device_plan = true;           // planned by the plan kernel (else uploaded host plans)
     uint64_t units = 1;                // approximate search units (root chunk sizing)
     double ms_work = 0, ms_done = 0;   // filled by read_pack
     bool bad_task = false;             // filled by read_pack: the work queue delivered an invalid task
@@ -123,6 +125,18 @@ struct Pack {
 // in the pinned blob, with device addresses in bufs.d_blob / bufs.d_arena.
 sge_status pack_instances(sge_ctx *c, const std::vector<const InstanceSpec *> &specs, bool dense, int policy,
                           LaunchBufs &bufs, Pack &pk);
+// The same launch with plans built on the host (plans[j] / bits[j] belong to
+// specs[j]; none of them empty): plans, lists and bitsets are uploaded.
+sge_status pack_host_planned(sge_ctx *c, const std::vector<const InstanceSpec *> &specs,
+                             const std::vector<const Plan *> &plans,
+                             const std::vector<const std::vector<uint64_t> *> &bits, bool dense, int policy,
+                             LaunchBufs &bufs, Pack &pk);
+// Whether a launch of `ninst` instances is planned on the device: batches
+// are (the plan kernel runs one workgroup per instance side by side); single
+// searches and small launches are planned on the host, where the short serial
+// work of one plan finishes sooner.
+constexpr size_t PLAN_DEVICE_MIN_INSTANCES = 64;
+bool plan_on_device(const sge_ctx *c, size_t ninst);
 // Upload, plan, reset, search and read back on `s` (asynchronous).
 hipError_t enqueue_pack(sge_ctx *c, const Pack &pk, LaunchBufs &bufs, hipStream_t s);
 // Upload and plan only (the plan of instance 0 is then read back by the caller).

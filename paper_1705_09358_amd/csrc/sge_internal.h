@@ -138,6 +138,7 @@ struct PlanIn {
     uint32_t mode, labelled, n, W;
     uint32_t root_lo, root_hi;
     uint32_t list_cap;            // entries `lists` holds: ncomp*n + k (a singleton domain adds one)
+    uint32_t rows;                // build support sets from adjacency rows (dense targets), not lists
     InstDesc *desc;               // the instance's search descriptor (col, node read; nroot written)
     DevPlan *plan;                // written
     uint64_t *dom;                // k*W words: domains by pattern node (written)
@@ -224,7 +225,7 @@ struct DevWork {
 // Plan `m` instances (one workgroup each), then set every instance's root
 // chunks and the chunk prefix: `policy` 1 = one chunk per instance, else
 // `root_chunk` candidates per chunk, or (0) the total roots over 4 * `units`.
-hipError_t launch_plan(const PlanIn *reqs, uint32_t m, uint32_t wmax, InstDesc *desc, unsigned *chunk_prefix,
+hipError_t launch_plan(const PlanIn *reqs, uint32_t m, uint32_t wmax, uint32_t kmax, InstDesc *desc, unsigned *chunk_prefix,
                        int policy, uint32_t root_chunk, uint64_t units, hipStream_t s);
 // LDS words of the plan kernel's support buffer (larger W uses PlanIn::support).
 constexpr uint32_t PLAN_LDS_WORDS = 4096;

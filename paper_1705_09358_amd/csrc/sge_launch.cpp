@@ -49,6 +49,11 @@ static uint64_t list_entries(const InstanceSpec &s) {
     return (uint64_t)std::max<uint32_t>(s.p->ncomp, 1) * s.t->g.n + s.p->g.n;
 }
 
+bool plan_on_device(const sge_ctx *c, size_t ninst) {
+    if (c->plan_where >= 0) return c->plan_where == 1;
+    return ninst >= PLAN_DEVICE_MIN_INSTANCES;
+}
+
 uint64_t instance_device_bytes(const InstanceSpec &s) {
     const uint64_t k = s.p->g.n, W = s.t->W;
     return sizeof(DevPlan) + sizeof(InstDesc) + sizeof(PlanIn) + sizeof(InstCounters) + 2 * k * W * 8 +
@@ -85,11 +90,11 @@ static hipError_t ensure_work(DevWork &w, uint32_t m) {
     return hipSuccess;
 }
 
-sge_status pack_instances(sge_ctx *c, const std::vector<const InstanceSpec *> &specs, bool dense, int policy,
-                          LaunchBufs &bufs, Pack &pk) {
-    const uint32_t m = (uint32_t)specs.size();
+// Launch shape shared by both packings: sizes, kernel variant, unit width.
+static void launch_config(const sge_ctx *c, const std::vector<const InstanceSpec *> &specs, bool dense, int policy,
+                          Pack &pk) {
     pk = Pack{};
-    pk.m = m;
+    pk.m = (uint32_t)specs.size();
     pk.policy = policy;
     LaunchCfg &cfg = pk.cfg;
     for (const InstanceSpec *sp : specs) {
@@ -109,7 +114,13 @@ sge_status pack_instances(sge_ctx *c, const std::vector<const InstanceSpec *> &s
     cfg.donate = c->donate;
     // approximate number of search units (for the root chunk size)
     pk.units = (uint64_t)c->num_cus * 4 * 8 * (64 / cfg.lanes) / 2;
+}
 
+sge_status pack_instances(sge_ctx *c, const std::vector<const InstanceSpec *> &specs, bool dense, int policy,
+                          LaunchBufs &bufs, Pack &pk) {
+    const uint32_t m = (uint32_t)specs.size();
+    launch_config(c, specs, dense, policy, pk);
+    pk.device_plan = true;
     // blob (uploaded): descriptors | plan requests | chunk prefix (device-written)
     const size_t off_desc = 0;
     pk.off_req = align_up(off_desc + m * sizeof(InstDesc), 256);
@@ -177,6 +188,89 @@ sge_status pack_instances(sge_ctx *c, const std::vector<const InstanceSpec *> &s
         r.lists = (uint32_t *)(da + list_at[j]);
         r.list_cap = (uint32_t)std::min<uint64_t>(list_entries(sp), 0xFFFFFFFFull);
         r.support = sp.t->W > PLAN_LDS_WORDS ? (uint64_t *)(da + sup_at[j]) : nullptr;
+        // an adjacency row (W words) is cheaper than a neighbour list once the
+        // mean degree reaches W
+        r.rows = sp.t->d_adj && sp.t->g.n && sp.t->g.col.size() >= (uint64_t)sp.t->g.n * sp.t->W ? 1u : 0u;
+    }
+    bufs.work.inst = (InstDesc *)(db + off_desc);
+    bufs.work.chunk_prefix = (unsigned *)(db + pk.off_pref);
+    return SGE_OK;
+}
+
+sge_status pack_host_planned(sge_ctx *c, const std::vector<const InstanceSpec *> &specs,
+                             const std::vector<const Plan *> &plans,
+                             const std::vector<const std::vector<uint64_t> *> &bits, bool dense, int policy,
+                             LaunchBufs &bufs, Pack &pk) {
+    const uint32_t m = (uint32_t)specs.size();
+    launch_config(c, specs, dense, policy, pk);
+    pk.device_plan = false;
+    // blob (uploaded whole): descriptors | chunk prefix | plans | lists | bits
+    const size_t off_desc = 0;
+    pk.off_pref = align_up(off_desc + m * sizeof(InstDesc), 256);
+    const size_t off_plan = align_up(pk.off_pref + (m + 1) * sizeof(unsigned), 256);
+    size_t cur = align_up(off_plan + m * sizeof(DevPlan), 256);
+    std::vector<size_t> list_at(m), bits_at(m);
+    for (uint32_t j = 0; j < m; j++) {
+        list_at[j] = cur;
+        cur = align_up(cur + plans[j]->lists.size() * 4, 16);
+    }
+    cur = align_up(cur, 256);
+    for (uint32_t j = 0; j < m; j++) {
+        bits_at[j] = cur;
+        cur = align_up(cur + bits[j]->size() * 8, 16);
+    }
+    pk.blob = pk.upload = std::max<size_t>(cur, 256);
+    pk.ctr_bytes = align_up(m * sizeof(InstCounters), 64);
+    hipError_t e;
+    if ((e = bufs.d_blob.reserve(pk.blob)) != hipSuccess) return hip_fail(c, e, "device plan buffer");
+    if ((e = bufs.h_blob.reserve(pk.blob)) != hipSuccess) return hip_fail(c, e, "pinned plan buffer");
+    if ((e = bufs.h_ctr.reserve(pk.ctr_bytes + sizeof(Sched))) != hipSuccess) return hip_fail(c, e, "pinned counters");
+    if ((e = ensure_work(bufs.work, m)) != hipSuccess) return hip_fail(c, e, "scheduler buffers");
+    char *hb = (char *)bufs.h_blob.p;
+    char *db = (char *)bufs.d_blob.p;
+    uint64_t total_roots = 0;
+    for (uint32_t j = 0; j < m; j++) total_roots += plans[j]->list_len[0];
+    unsigned *pref = (unsigned *)(hb + pk.off_pref);
+    pref[0] = 0;
+    for (uint32_t j = 0; j < m; j++) {
+        const Plan &pl = *plans[j];
+        const InstanceSpec &sp = *specs[j];
+        DevPlan &dp = ((DevPlan *)(hb + off_plan))[j];
+        std::memset(&dp, 0, sizeof(dp));
+        dp.k = pl.k;
+        dp.W = pl.W;
+        dp.n = pl.n;
+        dp.use_dom = pl.mode != SGE_RI;
+        dp.labelled = pl.labelled;
+        for (uint32_t i = 0; i < pl.k; i++) {
+            dp.parent[i] = pl.parent[i];
+            dp.back[i] = pl.back[i];
+            dp.plabel[i] = pl.plabel[i];
+            dp.pdeg[i] = pl.pdeg[i];
+            dp.order[i] = pl.order[i];
+            dp.list_off[i] = pl.list_off[i];
+            dp.list_len[i] = pl.list_len[i];
+        }
+        std::memcpy(hb + list_at[j], pl.lists.data(), pl.lists.size() * 4);
+        std::memcpy(hb + bits_at[j], bits[j]->data(), bits[j]->size() * 8);
+        InstDesc &d = ((InstDesc *)(hb + off_desc))[j];
+        d = InstDesc{};
+        d.col = sp.t->d_col;
+        d.node = sp.t->d_node;
+        d.adj = sp.t->d_adj;
+        d.plan = (const DevPlan *)(db + off_plan) + j;
+        d.bits = bits[j]->empty() ? nullptr : (const uint64_t *)(db + bits_at[j]);
+        d.lists = (const uint32_t *)(db + list_at[j]);
+        d.rows = sp.rows;
+        d.cap_rows = sp.rows ? sp.cap_rows : 0;
+        d.nroot = pl.list_len[0];
+        uint32_t chunk;
+        if (policy == 1) chunk = std::max<uint32_t>(1, d.nroot);
+        else if (c->root_chunk) chunk = c->root_chunk;
+        else chunk = (uint32_t)std::max<uint64_t>(1, total_roots / (4 * pk.units));
+        d.chunk = chunk;
+        d.nchunks = d.nroot ? (d.nroot + chunk - 1) / chunk : 0;
+        pref[j + 1] = pref[j] + d.nchunks;
     }
     bufs.work.inst = (InstDesc *)(db + off_desc);
     bufs.work.chunk_prefix = (unsigned *)(db + pk.off_pref);
@@ -187,13 +281,15 @@ hipError_t enqueue_plan_only(const Pack &pk, LaunchBufs &bufs, uint32_t root_chu
     hipError_t r;
     if ((r = hipMemcpyAsync(bufs.d_blob.p, bufs.h_blob.p, pk.upload, hipMemcpyHostToDevice, s)) != hipSuccess)
         return r;
-    return launch_plan((const PlanIn *)((char *)bufs.d_blob.p + pk.off_req), pk.m, pk.cfg.wmax, bufs.work.inst,
-                       bufs.work.chunk_prefix, pk.policy, root_chunk, pk.units, s);
+    return launch_plan((const PlanIn *)((char *)bufs.d_blob.p + pk.off_req), pk.m, pk.cfg.wmax, pk.cfg.kmax,
+                       bufs.work.inst, bufs.work.chunk_prefix, pk.policy, root_chunk, pk.units, s);
 }
 
 hipError_t enqueue_pack(sge_ctx *c, const Pack &pk, LaunchBufs &bufs, hipStream_t s) {
     hipError_t r;
-    if ((r = enqueue_plan_only(pk, bufs, c->root_chunk, s)) != hipSuccess) return r;
+    if (pk.device_plan) r = enqueue_plan_only(pk, bufs, c->root_chunk, s);
+    else r = hipMemcpyAsync(bufs.d_blob.p, bufs.h_blob.p, pk.upload, hipMemcpyHostToDevice, s);
+    if (r != hipSuccess) return r;
     if ((r = launch_reset(bufs.work, pk.m, s)) != hipSuccess) return r;
     if ((r = launch_search(pk.cfg, bufs.work, pk.m, c->cap, c->time_limit_ms, s, c->num_cus)) != hipSuccess)
         return r;
@@ -257,7 +353,49 @@ sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std
     }
     const bool dense = choose_dense(c, specs);
     Pack pk;
-    sge_status st = pack_instances(c, sp, dense, policy, c->bufs, pk);
+    sge_status st;
+    if (plan_on_device(c, sp.size())) {
+        st = pack_instances(c, sp, dense, policy, c->bufs, pk);
+    } else {
+        // host plans (threads for larger sets); an empty domain answers its
+        // instance at once
+        const size_t M = sp.size();
+        std::vector<Plan> plans(M);
+        std::vector<std::vector<uint64_t>> bits(M);
+        auto plan_one = [&](size_t i) {
+            build_plan(*sp[i]->t, sp[i]->p->g, sp[i]->mode, sp[i]->labelled, c->root_lo, c->root_hi, plans[i],
+                       dense || sp[i]->mode != SGE_RI, bits[i]);
+        };
+        if (M >= 64) {
+            const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+            std::vector<std::thread> th;
+            for (unsigned w = 0; w < nt; w++)
+                th.emplace_back([&, w]() {
+                    for (size_t i = w; i < M; i += nt) plan_one(i);
+                });
+            for (auto &x : th) x.join();
+        } else {
+            for (size_t i = 0; i < M; i++) plan_one(i);
+        }
+        std::vector<const InstanceSpec *> sp2;
+        std::vector<InstanceOut *> op2;
+        std::vector<const Plan *> pp;
+        std::vector<const std::vector<uint64_t> *> bp;
+        for (size_t i = 0; i < M; i++)
+            if (!plans[i].empty) {
+                sp2.push_back(sp[i]);
+                op2.push_back(op[i]);
+                pp.push_back(&plans[i]);
+                bp.push_back(&bits[i]);
+            }
+        sp.swap(sp2);
+        op.swap(op2);
+        if (sp.empty()) {
+            ms_prep = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+            return SGE_OK;
+        }
+        st = pack_host_planned(c, sp, pp, bp, dense, policy, c->bufs, pk);
+    }
     if (st != SGE_OK) return st;
     hipStream_t s = c->stream;
     ms_prep = std::chrono::duration<double, std::milli>(clk::now() - t0).count();

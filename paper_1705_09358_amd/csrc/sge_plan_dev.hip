@@ -57,6 +57,13 @@ __device__ __forceinline__ unsigned long long wave_max(unsigned long long x) {
     return x;
 }
 
+// value of lane l (uniform l) of a 64-bit per-lane value
+__device__ __forceinline__ unsigned long long readlane64(unsigned long long v, uint32_t l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, (int)l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)l);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 // bits of word t (nodes 64t .. 64t+63) that lie in [lo, hi)
 __device__ __forceinline__ unsigned long long range_mask(uint32_t t, uint32_t lo, uint32_t hi) {
     const unsigned long long base = (unsigned long long)t * 64;
@@ -66,10 +73,11 @@ __device__ __forceinline__ unsigned long long range_mask(uint32_t t, uint32_t lo
     return upto_b & ~((1ull << a) - 1);
 }
 
-__global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs) {
+__global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, uint32_t lds_words) {
     extern __shared__ unsigned long long s_support[];
     __shared__ unsigned long long s_nb[KMAX];
     __shared__ uint32_t s_lab[KMAX], s_deg[KMAX], s_dsize[KMAX], s_order[KMAX], s_pos[KMAX];
+    __shared__ uint32_t s_bw[KMAX], s_aff[KMAX];
     __shared__ int32_t s_par[KMAX];
     __shared__ unsigned long long s_next;
     __shared__ int s_empty;
@@ -83,7 +91,6 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs) 
     const NodeRec *node = R.desc->node;
     const uint32_t *col = R.desc->col;
     uint64_t *D = R.dom;
-    unsigned long long *S = W <= PLAN_LDS_WORDS ? s_support : reinterpret_cast<unsigned long long *>(R.support);
     DevPlan *pl = R.plan;
 
     if ((uint32_t)tid < k) {
@@ -93,6 +100,11 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs) 
     }
     if (tid == 0) s_empty = 0;
     __syncthreads();
+
+    // pattern node data by lane (lane u: node u), read back with readlane
+    const bool mine = (uint32_t)lane < k;
+    const unsigned long long mynb = mine ? s_nb[lane] : 0ull;
+    const uint32_t mylab = mine ? s_lab[lane] : 0u, mydeg = mine ? s_deg[lane] : 0u;
 
     // label and degree domains; lane l of a wave decides node 64 i + l
     for (uint32_t i = wave; i < W; i += PLAN_WAVES) {
@@ -104,53 +116,112 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs) 
             vl = r.label;
             vd = r.deg;
         }
-        unsigned long long mine = 0;
+        unsigned long long row = 0;
         for (uint32_t u = 0; u < k; u++) {
-            const uint32_t lu = s_lab[u];
-            const bool p = valid && (lu == LABEL_ANY || vl == lu) && vd >= s_deg[u];
+            const uint32_t lu = (uint32_t)__builtin_amdgcn_readlane((int)mylab, (int)u);
+            const uint32_t du = (uint32_t)__builtin_amdgcn_readlane((int)mydeg, (int)u);
+            const bool p = valid && (lu == LABEL_ANY || vl == lu) && vd >= du;
             const unsigned long long b = __ballot(p);
-            if ((uint32_t)lane == u) mine = b;
+            if ((uint32_t)lane == u) row = b;
         }
-        if ((uint32_t)lane < k) D[(size_t)lane * W + i] = mine;
+        if (mine) D[(size_t)lane * W + i] = row;
     }
     __syncthreads();
 
-    // arc-consistency to the fixpoint
+    // arc-consistency to the fixpoint.  A round takes the nodes whose domain
+    // changed in the previous round in batches of B: the support sets of a
+    // batch are built side by side (LDS, or device scratch for very wide
+    // rows), then every pattern neighbour of a batch member is revised
+    // against the supports of its neighbours in the batch.
     if (use_dom) {
+        const bool in_lds = W <= lds_words;
+        unsigned long long *Sb = in_lds ? s_support : reinterpret_cast<unsigned long long *>(R.support);
+        const uint32_t B = in_lds ? max(1u, min(k, lds_words / max(W, 1u))) : 1u;
+        const uint64_t *adj = R.desc->adj;
         unsigned long long dirty = 0;
         for (uint32_t u = 0; u < k; u++)
             if (s_nb[u]) dirty |= 1ull << u;
         while (dirty) {
             if (tid == 0) s_next = 0;
-            for (unsigned long long dm = dirty; dm; dm &= dm - 1) {
-                const uint32_t w = (uint32_t)__builtin_ctzll(dm);
-                for (uint32_t i = tid; i < W; i += PLAN_THREADS) S[i] = 0;
+            unsigned long long rest = dirty;
+            while (rest) {
+                unsigned long long batch = 0;
+                uint32_t nbat = 0;
+                for (unsigned long long r = rest; r && nbat < B; r &= r - 1, nbat++) batch |= r & (~r + 1ull);
+                rest &= ~batch;
+                unsigned long long aff = 0;
+                for (unsigned long long m = batch; m; m &= m - 1) aff |= s_nb[__builtin_ctzll(m)];
+                const uint32_t naff = (uint32_t)__popcll(aff);
+                if (tid == 0) {
+                    uint32_t j = 0;
+                    for (unsigned long long m = batch; m; m &= m - 1) s_bw[j++] = (uint32_t)__builtin_ctzll(m);
+                    j = 0;
+                    for (unsigned long long m = aff; m; m &= m - 1) s_aff[j++] = (uint32_t)__builtin_ctzll(m);
+                }
+                for (uint32_t idx = tid; idx < nbat * W; idx += PLAN_THREADS) Sb[idx] = 0;
                 __syncthreads();
-                // S(w): every target neighbour of a member of D(w)
-                for (uint32_t i = wave; i < W; i += PLAN_WAVES) {
-                    const uint64_t word = D[(size_t)w * W + i];
-                    if ((word >> lane) & 1ull) {
+                // S(w) for the batch: every target neighbour of a member of D(w)
+                for (uint32_t it = wave; it < nbat * W; it += PLAN_WAVES) {
+                    const uint32_t j = it / W, i = it - j * W;
+                    const uint64_t word = D[(size_t)s_bw[j] * W + i];
+                    unsigned long long *Sj = Sb + (size_t)j * W;
+                    if (R.rows) {
+                        // adjacency rows, ORed word by word (lane t: word t)
+                        for (uint32_t t0 = 0; t0 < W; t0 += 64) {
+                            const uint32_t t = t0 + lane;
+                            unsigned long long acc = 0;
+                            if (t < W) {
+                                for (unsigned long long m = word; m;) {
+                                    const uint32_t x0 = i * 64 + (uint32_t)__builtin_ctzll(m);
+                                    m &= m - 1;
+                                    const uint32_t x1 = m ? i * 64 + (uint32_t)__builtin_ctzll(m) : x0;
+                                    m &= m ? m - 1 : 0ull;
+                                    const uint32_t x2 = m ? i * 64 + (uint32_t)__builtin_ctzll(m) : x0;
+                                    m &= m ? m - 1 : 0ull;
+                                    const uint32_t x3 = m ? i * 64 + (uint32_t)__builtin_ctzll(m) : x0;
+                                    m &= m ? m - 1 : 0ull;
+                                    acc |= adj[(size_t)x0 * W + t] | adj[(size_t)x1 * W + t] |
+                                           adj[(size_t)x2 * W + t] | adj[(size_t)x3 * W + t];
+                                }
+                            }
+                            if (acc) atomicOr(&Sj[t], acc);
+                        }
+                    } else if ((word >> lane) & 1ull) {
+                        // the member's neighbour list, four entries per round
                         const NodeRec r = node[i * 64 + lane];
-                        for (uint32_t e = r.begin; e < r.begin + r.deg; e++) {
+                        uint32_t e = r.begin;
+                        const uint32_t end = r.begin + r.deg;
+                        for (; e + 4 <= end; e += 4) {
+                            const uint32_t y0 = col[e], y1 = col[e + 1], y2 = col[e + 2], y3 = col[e + 3];
+                            atomicOr(&Sj[y0 >> 6], 1ull << (y0 & 63));
+                            atomicOr(&Sj[y1 >> 6], 1ull << (y1 & 63));
+                            atomicOr(&Sj[y2 >> 6], 1ull << (y2 & 63));
+                            atomicOr(&Sj[y3 >> 6], 1ull << (y3 & 63));
+                        }
+                        for (; e < end; e++) {
                             const uint32_t y = col[e];
-                            atomicOr(&S[y >> 6], 1ull << (y & 63));
+                            atomicOr(&Sj[y >> 6], 1ull << (y & 63));
                         }
                     }
                 }
                 __syncthreads();
-                // revise the pattern neighbours of w against S(w)
-                for (unsigned long long um = s_nb[w]; um; um &= um - 1) {
-                    const uint32_t u = (uint32_t)__builtin_ctzll(um);
-                    bool ch = false;
-                    for (uint32_t i = tid; i < W; i += PLAN_THREADS) {
-                        const uint64_t old = D[(size_t)u * W + i], nw = old & S[i];
-                        if (nw != old) {
-                            D[(size_t)u * W + i] = nw;
-                            ch = true;
-                        }
+                // revise the pattern neighbours of the batch
+                unsigned long long changed = 0;
+                for (uint32_t it = tid; it < naff * W; it += PLAN_THREADS) {
+                    const uint32_t a = it / W, i = it - a * W;
+                    const uint32_t u = s_aff[a];
+                    unsigned long long acc = ~0ull;
+                    for (unsigned long long m = s_nb[u] & batch; m; m &= m - 1) {
+                        const uint32_t j = (uint32_t)__popcll(batch & ((1ull << __builtin_ctzll(m)) - 1));
+                        acc &= Sb[(size_t)j * W + i];
                     }
-                    if (ch) atomicOr(&s_next, 1ull << u);
+                    const uint64_t old = D[(size_t)u * W + i], nw = old & acc;
+                    if (nw != old) {
+                        D[(size_t)u * W + i] = nw;
+                        changed |= 1ull << u;
+                    }
                 }
+                if (changed) atomicOr(&s_next, changed);
                 __syncthreads();
             }
             dirty = s_next;
@@ -214,9 +285,8 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs) 
 
     // the constraint-first order (one wave; lane u scores pattern node u)
     if (!empty && wave == 0) {
-        const bool mine = (uint32_t)lane < k;
-        const unsigned long long mynb = mine ? s_nb[lane] : 0ull;
-        const uint32_t mydeg = mine ? s_deg[lane] : 0u, mysz = mine ? s_dsize[lane] : 0u;
+        const uint32_t mysz = mine ? s_dsize[lane] : 0u;
+        const unsigned long long all = k == 64 ? ~0ull : ((1ull << k) - 1);
         unsigned long long placed = 0;
         uint32_t len = 0;
         if (use_dom) {
@@ -228,12 +298,18 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs) 
             }
         }
         while (len < k) {
+            // w_n(u) counts the placed w sharing an unplaced neighbour x with u:
+            // the placed members of the union of N(x) over unplaced x in N(u)
+            unsigned long long two_hop = 0;
+            for (unsigned long long m = all & ~placed; m; m &= m - 1) {
+                const uint32_t x = (uint32_t)__builtin_ctzll(m);
+                const unsigned long long nbx = readlane64(mynb, x);
+                if ((mynb >> x) & 1ull) two_hop |= nbx;
+            }
             unsigned long long key = 0;
             if (mine && !((placed >> lane) & 1ull)) {
                 const uint32_t wm = (uint32_t)__popcll(mynb & placed);
-                uint32_t wn = 0;
-                for (unsigned long long m = placed; m; m &= m - 1)
-                    if (mynb & s_nb[__builtin_ctzll(m)] & ~placed) wn++;
+                const uint32_t wn = (uint32_t)__popcll(two_hop & placed);
                 // w_m, w_n and degree are below 64; the smaller domain and then
                 // the lower id win the remaining ties
                 key = (1ull << 62) | ((unsigned long long)wm << 50) | ((unsigned long long)wn << 44) |
@@ -382,11 +458,14 @@ __global__ void __launch_bounds__(FIN_THREADS)
 
 }  // namespace
 
-hipError_t launch_plan(const PlanIn *reqs, uint32_t m, uint32_t wmax, InstDesc *desc, unsigned *chunk_prefix,
+hipError_t launch_plan(const PlanIn *reqs, uint32_t m, uint32_t wmax, uint32_t kmax, InstDesc *desc, unsigned *chunk_prefix,
                        int policy, uint32_t root_chunk, uint64_t units, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    const size_t lds = (size_t)std::min<uint32_t>(std::max<uint32_t>(wmax, 1), PLAN_LDS_WORDS) * 8;
-    hipLaunchKernelGGL(plan_kernel, dim3(m), dim3(PLAN_THREADS), lds, s, reqs);
+    // support rows of one batch: up to PLAN_LDS_WORDS words (the widest
+    // instance's rows times the largest pattern, when that is smaller)
+    const uint32_t words =
+        (uint32_t)std::min<uint64_t>((uint64_t)std::max<uint32_t>(wmax, 1) * std::max<uint32_t>(kmax, 1), PLAN_LDS_WORDS);
+    hipLaunchKernelGGL(plan_kernel, dim3(m), dim3(PLAN_THREADS), (size_t)words * 8, s, reqs, words);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(FIN_THREADS), 0, s, desc, chunk_prefix, m, policy, root_chunk,

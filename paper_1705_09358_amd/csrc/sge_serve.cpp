@@ -3,14 +3,16 @@
 // Targets (CSR, node records, adjacency rows, label keys) and patterns stay
 // resident on the device.  A query is admitted when a slot is free and its
 // device bytes (plan, domains, candidate lists) fit in the arena budget;
-// otherwise submit says SGE_E_BUSY and the caller retries.  A dispatcher
-// thread packs every admitted query into one launch on the first idle launch
-// lane (one HIP stream each, with its own scheduler state and buffers): the
-// launch plans each query on the device (order, RI-DS domains with
-// arc-consistency and forward checking) and searches them all, so queries
-// that arrive while earlier ones are on the GPU start at once on another lane
-// and run beside them.  When a lane's launch completes its queries' results
-// become visible to poll and their slots and bytes are released.
+// otherwise submit says SGE_E_BUSY and the caller retries.  Admitted queries
+// are planned (order, RI-DS domains with arc-consistency and forward
+// checking) by a pool of host threads while earlier queries search, or, when
+// the context plans on the device, by the plan kernel at the head of their
+// launch.  A dispatcher thread packs whatever is ready into one persistent
+// search launch on the first idle launch lane (one HIP stream each, with its
+// own scheduler state and buffers), so queries that arrive while earlier ones
+// are on the GPU start at once on another lane and run beside them.  When a
+// lane's launch completes its queries' results become visible to poll and
+// their slots and bytes are released.
 #include <algorithm>
 #include <condition_variable>
 #include <deque>
@@ -26,6 +28,8 @@ namespace sge {
 struct Query {
     uint64_t ticket = 0;
     InstanceSpec spec;
+    Plan plan;                    // host plan (unless planned on the device)
+    std::vector<uint64_t> bits;
     InstanceOut out;
     uint64_t bytes = 0;
     bool done = false;
@@ -46,12 +50,14 @@ struct Server {
     uint32_t slots = 0;
     uint64_t arena = 0;
     std::mutex mu;
-    std::condition_variable cv_disp;
+    std::condition_variable cv_prep, cv_disp;
+    bool device_plan = false;
     std::map<uint64_t, std::unique_ptr<Query>> queries;
     uint64_t next_ticket = 1;
     uint64_t bytes_in_use = 0;
     uint32_t in_flight = 0;
-    std::deque<Query *> ready_q;
+    std::deque<Query *> prep_q, ready_q;
+    std::vector<std::thread> preppers;
     std::thread dispatcher;
     std::vector<LaunchLane> lanes;
     bool stopping = false;
@@ -62,9 +68,37 @@ struct Server {
         bytes_in_use -= q->bytes;
         in_flight--;
     }
+    void prep_loop();
     void dispatch_loop();
 };
 void ServerDeleter::operator()(Server *s) const { delete s; }
+
+void Server::prep_loop() {
+    (void)hipSetDevice(c->device);
+    for (;;) {
+        Query *q;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_prep.wait(lk, [&] { return stopping || !prep_q.empty(); });
+            if (prep_q.empty()) return;
+            q = prep_q.front();
+            prep_q.pop_front();
+        }
+        auto t0 = clk::now();
+        std::vector<InstanceSpec> one{q->spec};
+        const bool dense = choose_dense(c, one);
+        build_plan(*q->spec.t, q->spec.p->g, q->spec.mode, q->spec.labelled, c->root_lo, c->root_hi, q->plan,
+                   dense || q->spec.mode != SGE_RI, q->bits);
+        q->ms_prep = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+        std::lock_guard<std::mutex> lk(mu);
+        if (!q->plan.empty) {
+            ready_q.push_back(q);
+            cv_disp.notify_one();
+        } else {   // an empty domain: no match, nothing to search
+            release(q);
+        }
+    }
+}
 
 void Server::dispatch_loop() {
     (void)hipSetDevice(c->device);
@@ -99,7 +133,7 @@ void Server::dispatch_loop() {
             std::unique_lock<std::mutex> lk(mu);
             bool any_busy = false;
             for (LaunchLane &ln : lanes) any_busy |= ln.busy;
-            if (stopping && ready_q.empty() && !any_busy) return;
+            if (stopping && ready_q.empty() && prep_q.empty() && !any_busy) return;
             for (LaunchLane &ln : lanes)
                 if (!ln.busy) { lane = &ln; break; }
             if (lane && !ready_q.empty() && fatal.empty()) {
@@ -116,14 +150,19 @@ void Server::dispatch_loop() {
         auto t0 = clk::now();
         std::vector<const InstanceSpec *> sp;
         std::vector<InstanceSpec> specs;
+        std::vector<const Plan *> pp;
+        std::vector<const std::vector<uint64_t> *> bp;
         for (Query *q : take) {
             sp.push_back(&q->spec);
             specs.push_back(q->spec);
+            pp.push_back(&q->plan);
+            bp.push_back(&q->bits);
         }
         bool dense = choose_dense(c, specs);
-        sge_status st = pack_instances(c, sp, dense, 2, lane->bufs, lane->pk);
+        sge_status st = device_plan ? pack_instances(c, sp, dense, 2, lane->bufs, lane->pk)
+                                    : pack_host_planned(c, sp, pp, bp, dense, 2, lane->bufs, lane->pk);
         const double ms_pack = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
-        for (Query *q : take) q->ms_prep = ms_pack;
+        for (Query *q : take) q->ms_prep += ms_pack;
         hipError_t e = hipSuccess;
         if (st == SGE_OK) {
             // a share of the device per lane, so launches of several lanes run side by side
@@ -156,7 +195,9 @@ __attribute__((visibility("hidden"))) void sge_serve_shutdown_internal(sge_ctx *
         std::lock_guard<std::mutex> lk(sv->mu);
         sv->stopping = true;
     }
+    sv->cv_prep.notify_all();
     sv->cv_disp.notify_all();
+    for (auto &t : sv->preppers) t.join();
     if (sv->dispatcher.joinable()) sv->dispatcher.join();
     for (LaunchLane &ln : sv->lanes) {
         if (ln.s) (void)hipStreamSynchronize(ln.s);
@@ -186,6 +227,11 @@ sge_status sge_serve_start(sge_ctx *c, uint32_t slots, uint64_t arena_bytes) {
             sge_serve_shutdown_internal(c);
             return hip_fail(c, e, "server streams");
         }
+    }
+    sv->device_plan = c->plan_where == 1;
+    if (!sv->device_plan) {
+        const unsigned np = std::max(2u, std::min(8u, std::thread::hardware_concurrency() / 2));
+        for (unsigned i = 0; i < np; i++) sv->preppers.emplace_back([sv] { sv->prep_loop(); });
     }
     sv->dispatcher = std::thread([sv] { sv->dispatch_loop(); });
     return SGE_OK;
@@ -219,9 +265,12 @@ sge_status sge_serve_submit(sge_ctx *c, const sge_job *job, uint64_t *ticket) {
     if (q->spec.p->g.n == 0) {   // the empty pattern has one (empty) match
         q->out.matches = 1;
         sv->release(q.get());
-    } else {
+    } else if (sv->device_plan) {
         sv->ready_q.push_back(q.get());
         sv->cv_disp.notify_one();
+    } else {
+        sv->prep_q.push_back(q.get());
+        sv->cv_prep.notify_one();
     }
     sv->queries[q->ticket] = std::move(q);
     return SGE_OK;

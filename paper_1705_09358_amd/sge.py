@@ -26,8 +26,8 @@ EXPORTS = [
     "sge_create", "sge_destroy", "sge_last_error", "sge_load_target", "sge_unload_target", "sge_load_pattern",
     "sge_unload_pattern", "sge_set_labelled", "sge_set_mode", "sge_set_state_cap", "sge_set_root_range",
     "sge_count", "sge_enumerate", "sge_batch_run", "sge_set_batch_policy", "sge_serve_start", "sge_serve_submit",
-    "sge_serve_poll", "sge_serve_stop", "sge_plan_host", "sge_plan_device", "sge_set_tuning", "sge_set_time_limit",
-    "sge_last_launch_timing",
+    "sge_serve_poll", "sge_serve_stop", "sge_plan_host", "sge_plan_device", "sge_set_plan_location", "sge_set_tuning",
+    "sge_set_time_limit", "sge_last_launch_timing",
 ]
 
 
@@ -138,6 +138,7 @@ def lib() -> ctypes.CDLL:
             "sge_plan_host": (I32, [U32, P, P, P, U32, P, P, P, I32, I32, P, P, P, ctypes.POINTER(I32)]),
             "sge_plan_device": (I32, [P, U32, U32, I32, I32, P, P, P, ctypes.POINTER(U32), ctypes.POINTER(I32)]),
             "sge_set_tuning": (I32, [P, I32, U32, I32, I32]),
+            "sge_set_plan_location": (I32, [P, I32]),
             "sge_set_time_limit": (I32, [P, U64]),
             "sge_last_launch_timing": (I32, [P, P]),
         }
@@ -281,6 +282,10 @@ class Context:
     def set_tuning(self, lanes: int = 0, root_chunk: int = 0, donate: int = 1, dense: int = -1):
         """donate: 0 off, 1 default period, N > 1 at most one donation per N steps of a unit."""
         self._check(self._L.sge_set_tuning(self._h, lanes, root_chunk, int(donate), dense), "sge_set_tuning")
+
+    def set_plan_location(self, where: int):
+        """-1 automatic, 0 host, 1 device."""
+        self._check(self._L.sge_set_plan_location(self._h, where), "sge_set_plan_location")
 
     def set_batch_policy(self, policy: int):
         self._check(self._L.sge_set_batch_policy(self._h, policy), "sge_set_batch_policy")

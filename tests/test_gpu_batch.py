@@ -88,17 +88,21 @@ def test_batch_mixed_modes_vs_live_oracle(ctx):
 
 @pytest.mark.parametrize("cfg", ["c1", "c2"])
 @pytest.mark.parametrize("policy", [0, 1, 2])
-def test_full_batch(ctx, cfg, policy):
+@pytest.mark.parametrize("where", [-1, 0])
+def test_full_batch(ctx, cfg, policy, where):
+    """where: -1 plans these 100-job batches on the device, 0 on the host."""
     man = manifest(cfg)
-    _note(f"batch {cfg} full x{len(man['instances'])} policy {policy}")
+    _note(f"batch {cfg} full x{len(man['instances'])} policy {policy} plan {where}")
     make = {"c1": synth.c1_instance, "c2": synth.c2_instance}[cfg]
     insts = [make(r["j"], r["attempt"]) for r in man["instances"]]
     jobs = load_jobs(ctx, insts)
     ctx.set_batch_policy(policy)
+    ctx.set_plan_location(where)
     try:
         st, res = ctx.batch_run(jobs)
     finally:
         ctx.set_batch_policy(0)
+        ctx.set_plan_location(-1)
         unload(ctx, jobs)
     assert st == sge.OK
     got = [(r.matches, r.states) for r in res]
@@ -106,17 +110,27 @@ def test_full_batch(ctx, cfg, policy):
     assert got == want
 
 
-def test_c4_full_batch(ctx):
-    """All 4096 pairs of the batching workload in one launch."""
+@pytest.fixture(scope="module")
+def c4_jobs(ctx):
     man = manifest("c4")
     _note("batch c4 x4096: generating")
     insts = [synth.c4_instance(r["j"], r["attempt"]) for r in man["instances"]]
     jobs = load_jobs(ctx, insts)
-    _note("batch c4: running")
+    yield man, jobs
+    unload(ctx, jobs)
+
+
+@pytest.mark.parametrize("where", [-1, 0])
+def test_c4_full_batch(ctx, c4_jobs, where):
+    """All 4096 pairs of the batching workload in one launch, planned on the
+    device (-1: automatic for a batch this size) or on the host (0)."""
+    man, jobs = c4_jobs
+    _note(f"batch c4: running, plan {where}")
+    ctx.set_plan_location(where)
     try:
         st, res = ctx.batch_run(jobs)
     finally:
-        unload(ctx, jobs)
+        ctx.set_plan_location(-1)
     assert st == sge.OK
     bad = [(i, r.matches, r.states, w["matches"], w["states"])
            for i, (r, w) in enumerate(zip(res, man["instances"])) if (r.matches, r.states) != (w["matches"], w["states"])]

@@ -219,3 +219,45 @@ def test_root_range_shards_sum(run, ctx):
     assert tot_m == want["matches"]
     assert tot_s == want["states"]
     assert np.array_equal(_sorted(np.concatenate(allrows)), _sorted(want["rows"]))
+
+
+# ---------------------------------------------------------------- single searches planned on the device
+# (single searches are planned on the host unless the plan location says otherwise)
+
+@pytest.fixture
+def device_plan(ctx):
+    ctx.set_plan_location(1)
+    yield
+    ctx.set_plan_location(-1)
+
+
+@pytest.mark.parametrize("seed", range(0, 40, 3))
+def test_tiny_random_device_plan(run, device_plan, seed):
+    g = np.random.default_rng(seed)
+    n = int(g.integers(2, 12))
+    k = int(g.integers(1, min(6, n) + 1))
+    nlab = int(g.integers(1, 4))
+    T = G.random_graph(g, n, float(g.uniform(0.2, 0.9)), nlab)
+    P = G.random_graph(g, k, float(g.uniform(0.3, 1.0)), nlab)
+    for mode in range(4):
+        for labelled in (False, True):
+            check(run, P, T, mode, labelled, f"tiny/{seed}/device-plan")
+
+
+@pytest.mark.parametrize("mode", [0, 1, 3])
+def test_c2_device_plan(run, device_plan, mode):
+    for j in range(0, synth.C2_COUNT, 9):
+        inst = synth.c2_instance(j)
+        check(run, inst.pattern, inst.target, mode, True, f"c2/{j}/device-plan")
+
+
+def test_root_range_shards_device_plan(run, ctx, device_plan):
+    inst = synth.c2_instance(5)
+    for lo, hi in [(0, 700), (700, 1500), (2990, 3000)]:
+        ctx.set_root_range(lo, hi)
+        try:
+            res, _ = run.run(inst.pattern, inst.target, 3, True)
+        finally:
+            ctx.set_root_range()
+        shard = oracle.run(inst.pattern, inst.target, 3, True, root_range=(lo, hi))
+        assert (res.matches, res.states) == (shard["matches"], shard["states"])

@@ -57,16 +57,21 @@ def ctx():
     c.close()
 
 
-def test_serve_c1_matches_oracle_and_alone(ctx):
+@pytest.mark.parametrize("where", [-1, 1])
+def test_serve_c1_matches_oracle_and_alone(ctx, where):
+    """where: -1 plans each query on the server's host threads, 1 in the plan
+    kernel at the head of its launch."""
     man = manifest("c1")
     insts = [synth.c1_instance(r["j"], r["attempt"]) for r in man["instances"]]
     jobs = [(ctx.load_target(i.target), ctx.load_pattern(i.pattern), i.mode, True) for i in insts]
+    ctx.set_plan_location(where)
     ctx.serve_start(32, 1 << 30)
     try:
-        _note("serve c1 x100")
+        _note(f"serve c1 x100, plan {where}")
         mix = serve_all(ctx, jobs)
     finally:
         ctx.serve_stop()
+        ctx.set_plan_location(-1)
     for r, w in zip(mix, man["instances"]):
         assert r.status == sge.OK
         assert (r.matches, r.states) == (w["matches"], w["states"])
@@ -80,9 +85,11 @@ def test_serve_c1_matches_oracle_and_alone(ctx):
         ctx.unload_target(t)
 
 
-def test_serve_c5_sample_alone_and_mix(ctx):
+@pytest.mark.parametrize("where", [-1, 1])
+def test_serve_c5_sample_alone_and_mix(ctx, where):
     """The serving workload's first queries (resident 5k-20k-node targets,
-    RI-DS-SI-FC, state cap 1e7) against the oracle, in the mix and alone."""
+    RI-DS-SI-FC, state cap 1e7) against the oracle, in the mix and alone,
+    planned on the host (-1) or on the device (1)."""
     man = manifest("c5")
     _note("serve c5: loading 50 resident targets")
     targets = [synth.c5_target(t) for t in range(synth.C5_TARGETS)]
@@ -94,10 +101,11 @@ def test_serve_c5_sample_alone_and_mix(ctx):
         pats.append(P)
         jobs.append((th[t], ctx.load_pattern(P), sge.RIDS_SI_FC, True))
     ctx.set_state_cap(man["state_cap"])
+    ctx.set_plan_location(where)
     try:
         ctx.serve_start(64, 4 << 30)
         try:
-            _note(f"serve c5: {len(jobs)} queries in the mix")
+            _note(f"serve c5: {len(jobs)} queries in the mix, plan {where}")
             mix = serve_all(ctx, jobs)
         finally:
             ctx.serve_stop()
@@ -115,6 +123,7 @@ def test_serve_c5_sample_alone_and_mix(ctx):
                 assert (alone.matches, alone.states) == (r.matches, r.states)
     finally:
         ctx.set_state_cap(0)
+        ctx.set_plan_location(-1)
         for _, p, _, _ in jobs:
             ctx.unload_pattern(p)
         for t in th:
