@@ -3,17 +3,20 @@
 Workload (one step): the 100 random-walk patterns (16-48 nodes) of the
 protein-contact-like workload, searched on the resident 3000-node contact
 target (mean degree 11.4, 20 Zipf-distributed labels), plain RI, labelled --
-host plan (order, parents) plus the persistent search of all 100 patterns in
-one HIP-graph launch.  Inputs are seeded and synthetic (the paper's PDBSv1 /
+one HIP-graph launch that uploads the 100 job descriptors, plans every
+pattern on the device (order, parents, root lists) and runs the persistent
+search of all of them.  Inputs are seeded and synthetic (the paper's PDBSv1 /
 PPIS32 / GRAEMLIN32 collections are not available).  Every step's state and
 match counts are checked against the oracle's stored values.
 
 Also reported: the plain single-instance path (one sge_count per pattern) on
-the same patterns, the kernel's algorithmic-byte rate against the HBM peak,
-and the oracle's own rate on this host (a baseline, not the target).
+the same patterns, the same batch in each of the four search modes (the
+variant study), the C1 / C4 / dense C3 workloads, the serving run (p50/p99
+latency), the kernel's algorithmic-byte rate against the HBM peak, and the
+oracle's own rate on this host (a baseline, not the target).
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--extra c4,c1,c3]
-                    [--c3-patterns 8] [--serve-seconds 10]
+                    [--c3-patterns 8] [--serve-seconds 10] [--no-variants]
 """
 from __future__ import annotations
 
@@ -97,6 +100,37 @@ def run_plain(ctx, torch, jobs, want_states, reps=1):
     el = time.perf_counter() - t0
     return dict(states_per_s=sum(want_states) * reps / el, ms_per_pass=1000 * el / reps,
                 kernel_ms_per_pass=kms / reps)
+
+
+MODE_NAMES = {0: "RI", 1: "RI-DS", 2: "RI-DS-SI", 3: "RI-DS-SI-FC"}
+
+
+def run_variants(ctx, torch, jobs, steps):
+    """The variant study on the headline workload: the same 100 patterns
+    batched in each search mode (RI, RI-DS, RI-DS-SI, RI-DS-SI-FC).  The match
+    set must not change with the mode; states and time show what the domains,
+    the SI tie-break and forward checking save."""
+    from paper_1705_09358_amd import sge
+    out = {}
+    ref_matches = None
+    for mode in range(4):
+        arr = sge.job_array([(t, p, mode, lab) for t, p, _, lab in jobs])
+        st, res = ctx.batch_run(arr)   # first call of this batch size: autotune
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st, res = ctx.batch_run(arr)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        if ref_matches is None:
+            ref_matches = res.matches.copy()
+        elif not np.array_equal(res.matches, ref_matches):
+            raise SystemExit(f"variants: matches of mode {MODE_NAMES[mode]} differ from RI")
+        states = int(res.states.sum())
+        out[MODE_NAMES[mode]] = dict(states_per_step=states, matches_per_step=int(res.matches.sum()),
+                                     ms_per_step=1000 * el, kernel_ms=float(res.ms_search[0]),
+                                     states_per_s=states / el)
+    return out
 
 
 def run_dense(ctx, torch, npat, steps):
@@ -224,9 +258,19 @@ def measured_traffic():
     return float(m.group(1)) if m and m.group(2) == h else None
 
 
-def cpu_baseline(insts, budget_s=12.0):
+def cpu_baseline(insts, budget_s=12.0, variant_sample=34):
     import oracle
     oracle.lib()
+    # the variant study's oracle leg: every third pattern in each mode
+    variants = {}
+    sample = insts[::3][:variant_sample]
+    for mode in range(4):
+        t0 = time.process_time()
+        st = 0
+        for inst in sample:
+            st += oracle.run(inst.pattern, inst.target, mode, inst.labelled)["states"]
+        el = time.process_time() - t0
+        variants[MODE_NAMES[mode]] = dict(states=st, seconds=el, states_per_s=st / el if el > 0 else None)
     t0 = time.process_time()
     states = matches = 0
     n = 0
@@ -243,7 +287,8 @@ def cpu_baseline(insts, budget_s=12.0):
     el = time.process_time() - t0
     return dict(value=states / el, unit="states/s", cores=1, kind="oracle",
                 matches_per_s=matches / el,
-                sample=f"{n} pattern searches ({passes} pass(es) over the workload), single thread, {el:.1f} s CPU")
+                sample=f"{n} pattern searches ({passes} pass(es) over the workload), single thread, {el:.1f} s CPU",
+                variants=dict(sample=f"{len(sample)} of the 100 patterns (every third), each mode", **variants))
 
 
 def main():
@@ -258,6 +303,7 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy a buffer of this many MiB five times (calibrates the HBM byte counters)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--no-variants", action="store_true", help="skip the four-mode variant study")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of "
@@ -291,6 +337,10 @@ def main():
             plain = run_plain(ctx, torch, b["jobs"], [r["states"] for r in man["instances"]], reps=2)
         else:
             plain = None
+        variants = None
+        if not a.no_variants:
+            log("c2: variant study (four modes)")
+            variants = run_variants(ctx, torch, b["jobs"], max(3, a.steps // 4))
         extras = {}
         for cfg in [x for x in a.extra.split(",") if x]:
             if cfg == "c3":
@@ -344,6 +394,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic()},
         "p99_ms": None if serve is None else serve["p99_ms"],
         "serve": serve,
+        "variants": variants,
         "extra": extras,
     }
     if not a.no_cpu:

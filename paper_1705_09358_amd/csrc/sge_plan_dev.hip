@@ -30,8 +30,12 @@ namespace sge {
 
 namespace {
 
-constexpr int PLAN_THREADS = 256;
-constexpr int PLAN_WAVES = PLAN_THREADS / 64;
+// Workgroup sizes: 1024 threads when a launch plans few instances (each
+// plan's latency-bound phases then spread over 16 waves), 256 for large
+// batches (more plans resident per CU).
+constexpr int PLAN_THREADS_SMALL_BATCH = 1024;
+constexpr int PLAN_THREADS_LARGE_BATCH = 256;
+constexpr uint32_t PLAN_LARGE_BATCH = 256;
 
 // dense id of a raw label among the target's increasing label keys
 __device__ uint32_t label_id(const uint32_t *keys, uint32_t nl, uint32_t raw) {
@@ -73,7 +77,9 @@ __device__ __forceinline__ unsigned long long range_mask(uint32_t t, uint32_t lo
     return upto_b & ~((1ull << a) - 1);
 }
 
+template <int PLAN_THREADS>
 __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, uint32_t lds_words) {
+    constexpr int PLAN_WAVES = PLAN_THREADS / 64;
     extern __shared__ unsigned long long s_support[];
     __shared__ unsigned long long s_nb[KMAX];
     __shared__ uint32_t s_lab[KMAX], s_deg[KMAX], s_dsize[KMAX], s_order[KMAX], s_pos[KMAX];
@@ -465,7 +471,12 @@ hipError_t launch_plan(const PlanIn *reqs, uint32_t m, uint32_t wmax, uint32_t k
     // instance's rows times the largest pattern, when that is smaller)
     const uint32_t words =
         (uint32_t)std::min<uint64_t>((uint64_t)std::max<uint32_t>(wmax, 1) * std::max<uint32_t>(kmax, 1), PLAN_LDS_WORDS);
-    hipLaunchKernelGGL(plan_kernel, dim3(m), dim3(PLAN_THREADS), (size_t)words * 8, s, reqs, words);
+    if (m >= PLAN_LARGE_BATCH)
+        hipLaunchKernelGGL(plan_kernel<PLAN_THREADS_LARGE_BATCH>, dim3(m), dim3(PLAN_THREADS_LARGE_BATCH),
+                           (size_t)words * 8, s, reqs, words);
+    else
+        hipLaunchKernelGGL(plan_kernel<PLAN_THREADS_SMALL_BATCH>, dim3(m), dim3(PLAN_THREADS_SMALL_BATCH),
+                           (size_t)words * 8, s, reqs, words);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(FIN_THREADS), 0, s, desc, chunk_prefix, m, policy, root_chunk,

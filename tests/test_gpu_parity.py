@@ -145,7 +145,7 @@ def test_c2_all(run):
         assert res.matches >= 1
 
 
-@pytest.mark.parametrize("mode", [1, 3])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_c2_rids(run, mode):
     for j in range(0, synth.C2_COUNT, 7):
         inst = synth.c2_instance(j)
