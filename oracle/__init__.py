@@ -44,6 +44,13 @@ def lib():
         L.oracle_plan.restype = ctypes.c_int
         L.oracle_plan.argtypes = [ctypes.c_uint32, p, p, p, ctypes.c_uint32, p, p, p, ctypes.c_int, ctypes.c_int,
                                   p, p, p, p]
+        L.oracle_run_ex.restype = ctypes.c_int
+        L.oracle_run_ex.argtypes = [ctypes.c_uint32, p, p, p, p, ctypes.c_int, ctypes.c_uint32, p, p, p, p,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32,
+                                    ctypes.c_uint32, p, ctypes.c_uint64, p]
+        L.oracle_plan_ex.restype = ctypes.c_int
+        L.oracle_plan_ex.argtypes = [ctypes.c_uint32, p, p, p, p, ctypes.c_int, ctypes.c_uint32, p, p, p, p,
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, p, p, p, p]
         L.oracle_forward_check.restype = ctypes.c_int
         L.oracle_forward_check.argtypes = [ctypes.c_uint32, ctypes.c_uint32, p]
         _lib = L
@@ -56,9 +63,14 @@ def _u32(a) -> np.ndarray:
 
 
 def _graph_args(g):
+    """CSR, node labels, edge labels (or NULL) and the directed flag of a graph."""
     rp, col = _u32(g.row_ptr), _u32(g.col)
     lab = _u32(g.labels if g.labels is not None else np.zeros(g.n, dtype=np.uint32))
-    return (rp, col, lab), [rp.ctypes.data, col.ctypes.data, lab.ctypes.data]
+    el = getattr(g, "elabels", None)
+    el = None if el is None else _u32(el)
+    directed = int(bool(getattr(g, "directed", False)))
+    return (rp, col, lab, el), [rp.ctypes.data, col.ctypes.data, lab.ctypes.data,
+                                None if el is None else el.ctypes.data, directed]
 
 
 def run(pattern, target, mode: int, labelled: bool, state_cap: int = 0, rows: bool = False,
@@ -69,9 +81,9 @@ def run(pattern, target, mode: int, labelled: bool, state_cap: int = 0, rows: bo
     keep_t, ta = _graph_args(target)
     cnt = np.zeros(4, dtype=np.uint64)
     buf = np.zeros((cap_rows if rows else 0, max(pattern.n, 1)), dtype=np.uint32)
-    rc = lib().oracle_run(pattern.n, *pa, target.n, *ta, int(mode), int(bool(labelled)), int(state_cap),
-                          int(root_range[0]), int(root_range[1]),
-                          buf.ctypes.data if rows else None, cap_rows if rows else 0, cnt.ctypes.data)
+    rc = lib().oracle_run_ex(pattern.n, *pa, target.n, *ta, int(mode), int(bool(labelled)), int(state_cap),
+                             int(root_range[0]), int(root_range[1]),
+                             buf.ctypes.data if rows else None, cap_rows if rows else 0, cnt.ctypes.data)
     if rc < 0:
         raise ValueError(f"oracle rejected the input (code {rc})")
     out = dict(status=rc, matches=int(cnt[0]), states=int(cnt[1]), candidates=int(cnt[2]),
@@ -91,8 +103,8 @@ def plan(pattern, target, mode: int, labelled: bool) -> dict:
     parent = np.zeros(max(k, 1), dtype=np.int32)
     dom = np.zeros((max(k, 1), max(n, 1)), dtype=np.uint8)
     empty = ctypes.c_int(0)
-    rc = lib().oracle_plan(k, *pa, n, *ta, int(mode), int(bool(labelled)), order.ctypes.data, parent.ctypes.data,
-                           dom.ctypes.data if mode != RI else None, ctypes.byref(empty))
+    rc = lib().oracle_plan_ex(k, *pa, n, *ta, int(mode), int(bool(labelled)), order.ctypes.data,
+                              parent.ctypes.data, dom.ctypes.data if mode != RI else None, ctypes.byref(empty))
     if rc < 0:
         raise ValueError(f"oracle rejected the input (code {rc})")
     return dict(order=order[:k].copy(), parent=parent[:k].copy(), empty=bool(empty.value),

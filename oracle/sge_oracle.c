@@ -8,10 +8,14 @@
  * with the GPU library: it has its own structures and reads only the plain
  * input arrays.
  *
- * What it computes (Section 2.1, eqs. (2)-(3), non-induced as the paper states
- * after eq. (3)):  every injective M : V_p -> V_t with lab(u) = lab(M u) (when
- * labelled) and (M u, M w) in E_t for every pattern edge (u, w).  Graphs are
- * undirected, given as symmetric CSR with sorted rows and no self-loops.
+ * What it computes (Section 2.1, eqs. (2)-(4), non-induced as the paper states
+ * after them):  every injective M : V_p -> V_t with lab(u) = lab(M u) (when
+ * labelled) and (M u, M w) in E_t for every pattern edge (u, w), with equal
+ * edge labels beta(u, w) = beta(M u, M w) (when labelled).  Graphs are given as
+ * CSR with sorted rows, no self-loops and optional edge labels per entry: the
+ * out-edges of a directed graph, or both directions of an undirected one (a
+ * symmetric CSR with symmetric edge labels).  An undirected graph is the
+ * directed graph with both directions of every edge.
  *
  * How (the algorithm's steps in the paper's order):
  *   1. RI-DS domains (Section 4.1): D(u) = target nodes with the label of u and
@@ -44,6 +48,16 @@
  *   - Singleton-domain nodes go first in ascending id; SI applies to the first
  *     greedy pick too.
  *   - k = 0 gives one (empty) match; self-loops are rejected.
+ *   - Directed graphs: the order and the parents ignore directions (as the
+ *     paper says for the order); degree there is |N(v)|, N(v) the nodes with
+ *     an edge to or from v.  Rule 3 and the domain initialisation compare
+ *     in- and out-degree separately.  A parent's candidates are its image's
+ *     out-neighbours when the pattern edge leaves the parent, else its
+ *     in-neighbours.  Arc-consistency asks, for a pattern edge u -> w, an
+ *     out-neighbour of v in D(w) over an edge of the same label, and for
+ *     w -> u an in-neighbour (the paper gives the first case; the second is
+ *     its mirror).
+ *   - Edge labels are compared exactly when node labels are (labelled).
  *
  * Counters: `states` = accepted (position, target) pairs (consistent prefix
  * assignments); `candidates` = pairs considered; `alg_bytes` = bytes the method
@@ -58,21 +72,45 @@ enum { OR_OK = 0, OR_ABORTED = 2, OR_EINVAL = -1, OR_ENOMEM = -2 };
 
 typedef struct {
     uint32_t n;
-    const uint32_t *rp, *col, *lab;
+    const uint32_t *rp, *col, *lab, *elab;   /* out-edges; elab per entry, or NULL for all 0 */
+    uint32_t *irp, *icol, *ielab;            /* in-edges (the transpose), built by og_index */
+    int directed;
 } og;
 
 static uint32_t og_deg(const og *g, uint32_t v) { return g->rp[v + 1] - g->rp[v]; }
+static uint32_t og_indeg(const og *g, uint32_t v) { return g->irp[v + 1] - g->irp[v]; }
 
 static int cmp_u32(const void *a, const void *b) {
     uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
     return (x > y) - (x < y);
 }
 
-/* is b in the (sorted) neighbour list of a */
-static int og_adj(const og *g, uint32_t a, uint32_t b) {
+/* index of b in the (sorted) out-list of a, or -1 */
+static int64_t og_find(const og *g, uint32_t a, uint32_t b) {
     uint32_t d = og_deg(g, a);
-    if (d == 0) return 0;
-    return bsearch(&b, g->col + g->rp[a], d, sizeof(uint32_t), cmp_u32) != NULL;
+    if (d == 0) return -1;
+    const uint32_t *hit = bsearch(&b, g->col + g->rp[a], d, sizeof(uint32_t), cmp_u32);
+    return hit ? (int64_t)(hit - g->col) : -1;
+}
+
+/* is there an edge a -> b */
+static int og_adj(const og *g, uint32_t a, uint32_t b) { return og_find(g, a, b) >= 0; }
+
+static uint32_t og_elab(const og *g, int64_t e) { return g->elab ? g->elab[e] : 0u; }
+
+/* a and b are neighbours (an edge in either direction) */
+static int og_nb(const og *g, uint32_t a, uint32_t b) { return og_adj(g, a, b) || og_adj(g, b, a); }
+
+/* |N(v)|: nodes with an edge to or from v */
+static uint32_t og_nbdeg(const og *g, uint32_t v) {
+    uint32_t c = 0, i = g->rp[v], j = g->irp[v];
+    while (i < g->rp[v + 1] || j < g->irp[v + 1]) {
+        if (j >= g->irp[v + 1] || (i < g->rp[v + 1] && g->col[i] < g->icol[j])) i++;
+        else if (i >= g->rp[v + 1] || g->icol[j] < g->col[i]) j++;
+        else { i++; j++; }
+        c++;
+    }
+    return c;
 }
 
 static int og_valid(const og *g) {
@@ -84,15 +122,48 @@ static int og_valid(const og *g) {
             if (e > g->rp[v] && g->col[e - 1] >= w) return 0;
         }
     }
-    for (uint32_t v = 0; v < g->n; v++)
-        for (uint32_t e = g->rp[v]; e < g->rp[v + 1]; e++)
-            if (!og_adj(g, g->col[e], v)) return 0;
+    if (!g->directed)   /* both directions of every edge, with one label */
+        for (uint32_t v = 0; v < g->n; v++)
+            for (uint32_t e = g->rp[v]; e < g->rp[v + 1]; e++) {
+                int64_t r = og_find(g, g->col[e], v);
+                if (r < 0 || og_elab(g, r) != og_elab(g, e)) return 0;
+            }
     return 1;
+}
+
+/* build the in-edge lists (sorted, with their labels) */
+static int og_index(og *g) {
+    uint32_t n = g->n, m = g->rp[n];
+    g->irp = (uint32_t *)calloc((size_t)n + 1, sizeof(uint32_t));
+    g->icol = (uint32_t *)malloc((m ? m : 1) * sizeof(uint32_t));
+    g->ielab = (uint32_t *)malloc((m ? m : 1) * sizeof(uint32_t));
+    if (!g->irp || !g->icol || !g->ielab) return 0;
+    for (uint32_t e = 0; e < m; e++) g->irp[g->col[e] + 1]++;
+    for (uint32_t v = 0; v < n; v++) g->irp[v + 1] += g->irp[v];
+    uint32_t *fill = (uint32_t *)malloc(((size_t)n + 1) * sizeof(uint32_t));
+    if (!fill) return 0;
+    memcpy(fill, g->irp, ((size_t)n + 1) * sizeof(uint32_t));
+    for (uint32_t v = 0; v < n; v++)   /* sources in increasing order: rows come out sorted */
+        for (uint32_t e = g->rp[v]; e < g->rp[v + 1]; e++) {
+            uint32_t w = g->col[e], at = fill[w]++;
+            g->icol[at] = v;
+            g->ielab[at] = og_elab(g, e);
+        }
+    free(fill);
+    return 1;
+}
+
+static void og_free(og *g) {
+    free(g->irp);
+    free(g->icol);
+    free(g->ielab);
+    g->irp = g->icol = g->ielab = NULL;
 }
 
 typedef struct {
     og P, T;
     int mode, labelled;
+    int directed;         /* either graph is directed: in-edges are checked on their own */
     uint64_t cap;
     uint32_t k, n;
     unsigned char *dom;   /* k*n, dom[u*n + v] (by pattern id); NULL in RI */
@@ -107,10 +178,21 @@ typedef struct {
     int aborted;
 } oracle_t;
 
-/* rules 2-3 of RI and the domain initialisation of RI-DS */
+/* rules 2-3 of RI and the domain initialisation of RI-DS: label, out- and in-degree */
 static int compat(const oracle_t *o, uint32_t u, uint32_t v) {
     if (o->labelled && o->P.lab[u] != o->T.lab[v]) return 0;
-    return og_deg(&o->P, u) <= og_deg(&o->T, v);
+    return og_deg(&o->P, u) <= og_deg(&o->T, v) && og_indeg(&o->P, u) <= og_indeg(&o->T, v);
+}
+
+/* some target edge out of v (in-edges: into v) of label b reaches a member of D(w) */
+static int supported(const oracle_t *o, uint32_t v, uint32_t w, uint32_t b, int in_edges) {
+    const uint32_t *rp = in_edges ? o->T.irp : o->T.rp, *col = in_edges ? o->T.icol : o->T.col;
+    for (uint32_t f = rp[v]; f < rp[v + 1]; f++) {
+        if (!o->dom[(size_t)w * o->n + col[f]]) continue;
+        uint32_t tb = in_edges ? o->T.ielab[f] : og_elab(&o->T, f);
+        if (!o->labelled || tb == b) return 1;
+    }
+    return 0;
 }
 
 static uint64_t dom_size(const oracle_t *o, uint32_t u) {
@@ -127,16 +209,17 @@ static int arc_consistency(oracle_t *o) {
         for (uint32_t u = 0; u < o->k; u++) {
             for (uint32_t v = 0; v < o->n; v++) {
                 if (!o->dom[(size_t)u * o->n + v]) continue;
-                for (uint32_t e = o->P.rp[u]; e < o->P.rp[u + 1]; e++) {
-                    uint32_t w = o->P.col[e];
-                    int supported = 0;
-                    for (uint32_t f = o->T.rp[v]; f < o->T.rp[v + 1] && !supported; f++)
-                        supported = o->dom[(size_t)w * o->n + o->T.col[f]];
-                    if (!supported) {
-                        o->dom[(size_t)u * o->n + v] = 0;
-                        changed = 1;
-                        break;
-                    }
+                int keep = 1;
+                /* pattern edges u -> w need an edge v -> x, x in D(w), of the same label */
+                for (uint32_t e = o->P.rp[u]; e < o->P.rp[u + 1] && keep; e++)
+                    keep = supported(o, v, o->P.col[e], og_elab(&o->P, e), 0);
+                /* directed: pattern edges w -> u need an edge x -> v likewise */
+                if (o->directed)
+                    for (uint32_t e = o->P.irp[u]; e < o->P.irp[u + 1] && keep; e++)
+                        keep = supported(o, v, o->P.icol[e], o->P.ielab[e], 1);
+                if (!keep) {
+                    o->dom[(size_t)u * o->n + v] = 0;
+                    changed = 1;
                 }
             }
         }
@@ -180,7 +263,8 @@ int oracle_forward_check(uint32_t k, uint32_t n, unsigned char *dom) {
     return 0;
 }
 
-static int pattern_adj(const oracle_t *o, uint32_t a, uint32_t b) { return og_adj(&o->P, a, b); }
+/* pattern neighbours, directions ignored (the order and the parents) */
+static int pattern_adj(const oracle_t *o, uint32_t a, uint32_t b) { return og_nb(&o->P, a, b); }
 
 /* The constraint-first ordering and its parent map. */
 static void make_order(oracle_t *o) {
@@ -200,7 +284,7 @@ static void make_order(oracle_t *o) {
         uint64_t bdom = 0;
         for (uint32_t u = 0; u < k; u++) {
             if (placed[u]) continue;
-            int64_t wm = 0, wn = 0, deg = og_deg(&o->P, u);
+            int64_t wm = 0, wn = 0, deg = og_nbdeg(&o->P, u);
             for (uint32_t j = 0; j < len; j++)
                 if (pattern_adj(o, u, o->order[j])) wm++;
             for (uint32_t j = 0; j < len; j++) {
@@ -250,12 +334,29 @@ static void search(oracle_t *o, uint32_t i) {
     uint32_t u = o->order[i];
     int use_dom = o->mode != OR_RI;
     uint32_t lo, hi;
-    const uint32_t *list = NULL;
+    const uint32_t *list = NULL, *labs = NULL;
+    uint32_t pu = 0, pv = 0, plab = 0;
+    int gen_out = 1, both = 0;
     if (o->parent[i] >= 0) {
-        uint32_t pv = o->M[o->parent[i]];
-        lo = o->T.rp[pv];
-        hi = o->T.rp[pv + 1];
-        list = o->T.col;
+        /* candidates: the image's out-neighbours if the pattern edge leaves
+           the parent, else its in-neighbours */
+        pu = o->order[o->parent[i]];
+        pv = o->M[o->parent[i]];
+        int64_t fe = og_find(&o->P, pu, u), re = og_find(&o->P, u, pu);
+        gen_out = fe >= 0;
+        both = fe >= 0 && re >= 0;
+        plab = og_elab(&o->P, gen_out ? fe : re);
+        if (gen_out) {
+            lo = o->T.rp[pv];
+            hi = o->T.rp[pv + 1];
+            list = o->T.col;
+            labs = o->T.elab;
+        } else {
+            lo = o->T.irp[pv];
+            hi = o->T.irp[pv + 1];
+            list = o->T.icol;
+            labs = o->T.ielab;
+        }
         o->alg_bytes += 8 + 4ull * (hi - lo);
     } else {
         lo = 0;
@@ -274,13 +375,38 @@ static void search(oracle_t *o, uint32_t i) {
         if (use_dom && !o->dom[(size_t)u * o->n + v]) continue;
         if (o->used[v]) continue;                                   /* rule 1 */
         if (o->labelled && o->P.lab[u] != o->T.lab[v]) continue;    /* rule 2 */
-        if (og_deg(&o->P, u) > og_deg(&o->T, v)) continue;          /* rule 3 */
+        if (og_deg(&o->P, u) > og_deg(&o->T, v) || og_indeg(&o->P, u) > og_indeg(&o->T, v))
+            continue;                                               /* rule 3 */
         int ok = 1;                                                 /* rule 4 */
+        if (list) {
+            /* the parent edge used to generate v: its label; if the pattern
+               has both directions, the other one too */
+            if (o->labelled && (o->P.elab || o->T.elab)) {
+                o->alg_bytes += 4;
+                ok = (labs ? labs[e] : 0u) == plab;
+            }
+            if (ok && o->directed && both) {
+                o->alg_bytes += 8;
+                int64_t f = og_find(&o->T, v, pv);
+                ok = f >= 0 && (!o->labelled || og_elab(&o->T, f) == og_elab(&o->P, og_find(&o->P, u, pu)));
+            }
+        }
         for (uint32_t j = 0; j < i && ok; j++) {
             if ((int32_t)j == o->parent[i]) continue;
-            if (!pattern_adj(o, u, o->order[j])) continue;
-            o->alg_bytes += 8;
-            ok = og_adj(&o->T, o->M[j], v);
+            uint32_t w = o->order[j];
+            int64_t pe = og_find(&o->P, w, u);   /* w -> u */
+            if (pe >= 0) {
+                o->alg_bytes += 8;
+                int64_t f = og_find(&o->T, o->M[j], v);
+                ok = f >= 0 && (!o->labelled || og_elab(&o->T, f) == og_elab(&o->P, pe));
+            }
+            if (!ok || !o->directed) continue;   /* undirected: w -> u is u -> w */
+            int64_t pr = og_find(&o->P, u, w);   /* u -> w */
+            if (pr >= 0) {
+                o->alg_bytes += 8;
+                int64_t f = og_find(&o->T, v, o->M[j]);
+                ok = f >= 0 && (!o->labelled || og_elab(&o->T, f) == og_elab(&o->P, pr));
+            }
         }
         if (!ok) continue;
         o->states++;
@@ -296,17 +422,21 @@ static void search(oracle_t *o, uint32_t i) {
 static void oracle_free(oracle_t *o) {
     free(o->dom);
     free(o->used);
+    og_free(&o->P);
+    og_free(&o->T);
 }
 
 static int oracle_setup(oracle_t *o, uint32_t k, const uint32_t *prp, const uint32_t *pcol, const uint32_t *plab,
-                        uint32_t n, const uint32_t *trp, const uint32_t *tcol, const uint32_t *tlab,
-                        int mode, int labelled, int *empty) {
+                        const uint32_t *pelab, int pdir, uint32_t n, const uint32_t *trp, const uint32_t *tcol,
+                        const uint32_t *tlab, const uint32_t *telab, int tdir, int mode, int labelled, int *empty) {
     memset(o, 0, sizeof(*o));
     if (k > 64 || mode < OR_RI || mode > OR_RIDS_SI_FC) return OR_EINVAL;
-    o->P = (og){k, prp, pcol, plab};
-    o->T = (og){n, trp, tcol, tlab};
+    o->P = (og){k, prp, pcol, plab, pelab, NULL, NULL, NULL, pdir != 0};
+    o->T = (og){n, trp, tcol, tlab, telab, NULL, NULL, NULL, tdir != 0};
     if (!og_valid(&o->P) || !og_valid(&o->T)) return OR_EINVAL;
     if (labelled && (!plab || !tlab)) return OR_EINVAL;
+    if (!og_index(&o->P) || !og_index(&o->T)) { oracle_free(o); return OR_ENOMEM; }
+    o->directed = pdir || tdir;
     o->k = k;
     o->n = n;
     o->mode = mode;
@@ -332,11 +462,12 @@ static int oracle_setup(oracle_t *o, uint32_t k, const uint32_t *prp, const uint
  * domains, the final domains as k*n bytes indexed by pattern node.  *empty is
  * set to 1 when a domain became empty (no matches; order is then not set).
  */
-int oracle_plan(uint32_t k, const uint32_t *prp, const uint32_t *pcol, const uint32_t *plab,
-                uint32_t n, const uint32_t *trp, const uint32_t *tcol, const uint32_t *tlab,
-                int mode, int labelled, uint32_t *order, int32_t *parent, unsigned char *dom_out, int *empty) {
+int oracle_plan_ex(uint32_t k, const uint32_t *prp, const uint32_t *pcol, const uint32_t *plab,
+                   const uint32_t *pelab, int pdir, uint32_t n, const uint32_t *trp, const uint32_t *tcol,
+                   const uint32_t *tlab, const uint32_t *telab, int tdir, int mode, int labelled, uint32_t *order,
+                   int32_t *parent, unsigned char *dom_out, int *empty) {
     oracle_t o;
-    int rc = oracle_setup(&o, k, prp, pcol, plab, n, trp, tcol, tlab, mode, labelled, empty);
+    int rc = oracle_setup(&o, k, prp, pcol, plab, pelab, pdir, n, trp, tcol, tlab, telab, tdir, mode, labelled, empty);
     if (rc != OR_OK) return rc;
     if (!*empty) {
         memcpy(order, o.order, k * sizeof(uint32_t));
@@ -355,13 +486,15 @@ int oracle_plan(uint32_t k, const uint32_t *prp, const uint32_t *pcol, const uin
  * Returns OR_OK, OR_ABORTED when states exceed state_cap (> 0), or a negative
  * error.
  */
-int oracle_run(uint32_t k, const uint32_t *prp, const uint32_t *pcol, const uint32_t *plab,
-               uint32_t n, const uint32_t *trp, const uint32_t *tcol, const uint32_t *tlab,
-               int mode, int labelled, uint64_t state_cap, uint32_t root_lo, uint32_t root_hi,
-               uint32_t *rows, uint64_t cap_rows, uint64_t *counters) {
+int oracle_run_ex(uint32_t k, const uint32_t *prp, const uint32_t *pcol, const uint32_t *plab,
+                  const uint32_t *pelab, int pdir, uint32_t n, const uint32_t *trp, const uint32_t *tcol,
+                  const uint32_t *tlab, const uint32_t *telab, int tdir, int mode, int labelled,
+                  uint64_t state_cap, uint32_t root_lo, uint32_t root_hi, uint32_t *rows, uint64_t cap_rows,
+                  uint64_t *counters) {
     oracle_t o;
     int empty = 0;
-    int rc = oracle_setup(&o, k, prp, pcol, plab, n, trp, tcol, tlab, mode, labelled, &empty);
+    int rc = oracle_setup(&o, k, prp, pcol, plab, pelab, pdir, n, trp, tcol, tlab, telab, tdir, mode, labelled,
+                          &empty);
     if (rc != OR_OK) return rc;
     o.root_lo = root_lo;
     o.root_hi = root_hi;
@@ -376,4 +509,20 @@ int oracle_run(uint32_t k, const uint32_t *prp, const uint32_t *pcol, const uint
     rc = o.aborted ? OR_ABORTED : OR_OK;
     oracle_free(&o);
     return rc;
+}
+
+/* The undirected, edge-unlabelled entry points (symmetric CSR in and out). */
+int oracle_plan(uint32_t k, const uint32_t *prp, const uint32_t *pcol, const uint32_t *plab,
+                uint32_t n, const uint32_t *trp, const uint32_t *tcol, const uint32_t *tlab,
+                int mode, int labelled, uint32_t *order, int32_t *parent, unsigned char *dom_out, int *empty) {
+    return oracle_plan_ex(k, prp, pcol, plab, NULL, 0, n, trp, tcol, tlab, NULL, 0, mode, labelled, order, parent,
+                          dom_out, empty);
+}
+
+int oracle_run(uint32_t k, const uint32_t *prp, const uint32_t *pcol, const uint32_t *plab,
+               uint32_t n, const uint32_t *trp, const uint32_t *tcol, const uint32_t *tlab,
+               int mode, int labelled, uint64_t state_cap, uint32_t root_lo, uint32_t root_hi,
+               uint32_t *rows, uint64_t cap_rows, uint64_t *counters) {
+    return oracle_run_ex(k, prp, pcol, plab, NULL, 0, n, trp, tcol, tlab, NULL, 0, mode, labelled, state_cap,
+                         root_lo, root_hi, rows, cap_rows, counters);
 }

@@ -55,11 +55,15 @@ def rng(cfg: int, role: int, j: int, attempt: int = 0) -> np.random.Generator:
 
 @dataclasses.dataclass
 class Graph:
-    """Undirected simple graph in CSR form; ``labels`` is one uint32 per node."""
+    """Simple graph in CSR form with sorted rows: both directions of every edge
+    when undirected, the out-edges when ``directed``.  ``labels``: one uint32
+    per node; ``elabels``: one uint32 per CSR entry (edge labels), or None."""
     n: int
     row_ptr: np.ndarray
     col: np.ndarray
     labels: np.ndarray
+    elabels: np.ndarray | None = None
+    directed: bool = False
 
     @property
     def m2(self) -> int:

@@ -116,3 +116,137 @@ def brute_states(P: Graph, T: Graph, labelled: bool, order, domains) -> int:
 def random_graph(g: np.random.Generator, n: int, p: float, nlab: int) -> Graph:
     edges = [(i, j) for i in range(n) for j in range(i + 1, n) if g.random() < p]
     return from_edges(n, edges, g.integers(0, nlab, size=n))
+
+
+# ---------------------------------------------------------------- directed and edge-labelled graphs
+
+def from_arcs(n: int, arcs, labels=None, elabels=None, directed: bool = True) -> Graph:
+    """CSR of the arcs (a, b) (sorted rows); elabels[i] is the label of arcs[i].
+    With directed=False every arc must appear in both directions."""
+    arcs = [tuple(int(x) for x in a) for a in arcs]
+    el = [0] * len(arcs) if elabels is None else [int(x) for x in elabels]
+    order = sorted(range(len(arcs)), key=lambda i: arcs[i])
+    rp = np.zeros(n + 1, dtype=np.uint32)
+    for a, _ in arcs:
+        rp[a + 1] += 1
+    rp = np.cumsum(rp).astype(np.uint32)
+    col = np.array([arcs[i][1] for i in order], dtype=np.uint32)
+    elab = np.array([el[i] for i in order], dtype=np.uint32) if elabels is not None else None
+    lab = np.zeros(n, dtype=np.uint32) if labels is None else np.asarray(labels, dtype=np.uint32)
+    return Graph(n, rp, col, lab, elab, directed)
+
+
+def arcs_of(g: Graph):
+    """{(a, b): label} over the CSR entries."""
+    out = {}
+    for a in range(g.n):
+        for e in range(int(g.row_ptr[a]), int(g.row_ptr[a + 1])):
+            out[(a, int(g.col[e]))] = 0 if g.elabels is None else int(g.elabels[e])
+    return out
+
+
+def reverse(g: Graph) -> Graph:
+    arcs = arcs_of(g)
+    return from_arcs(g.n, [(b, a) for a, b in arcs], g.labels, [arcs[x] for x in arcs] if g.elabels is not None
+                     else None, g.directed)
+
+
+def random_digraph(g: np.random.Generator, n: int, p: float, nlab: int, nelab: int) -> Graph:
+    arcs, el = [], []
+    for a in range(n):
+        for b in range(n):
+            if a != b and g.random() < p:
+                arcs.append((a, b))
+                el.append(int(g.integers(0, nelab)))
+    return from_arcs(n, arcs, g.integers(0, nlab, size=n), el if nelab > 1 else None)
+
+
+def random_undirected_elabelled(g: np.random.Generator, n: int, p: float, nlab: int, nelab: int) -> Graph:
+    arcs, el = [], []
+    for a in range(n):
+        for b in range(a + 1, n):
+            if g.random() < p:
+                lb = int(g.integers(0, nelab))
+                arcs += [(a, b), (b, a)]
+                el += [lb, lb]
+    return from_arcs(n, arcs, g.integers(0, nlab, size=n), el, directed=False)
+
+
+def brute_matches_ex(P: Graph, T: Graph, labelled: bool) -> np.ndarray:
+    """All injections mapping every pattern arc onto a target arc (with equal
+    node and edge labels when labelled), rows in pattern-id order, sorted."""
+    pa, ta = arcs_of(P), arcs_of(T)
+    rows = []
+    for m in itertools.permutations(range(T.n), P.n):
+        if labelled and any(P.labels[u] != T.labels[m[u]] for u in range(P.n)):
+            continue
+        if all((m[a], m[b]) in ta and (not labelled or ta[(m[a], m[b])] == lb) for (a, b), lb in pa.items()):
+            rows.append(m)
+    r = np.array(rows, dtype=np.uint32).reshape(-1, P.n)
+    return r[np.lexsort(r.T[::-1])] if len(rows) > 1 else r
+
+
+def brute_states_ex(P: Graph, T: Graph, labelled: bool, order, domains) -> int:
+    """Consistent prefix assignments (summed over prefix lengths 1..k): injective,
+    unary checks (label, out-degree, in-degree, domain) and every pattern arc
+    inside the prefix on a target arc of the same label (labelled)."""
+    pa, ta = arcs_of(P), arcs_of(T)
+    pout = np.diff(P.row_ptr.astype(np.int64))
+    tout = np.diff(T.row_ptr.astype(np.int64))
+    pin = np.bincount(P.col.astype(np.int64), minlength=P.n) if P.col.size else np.zeros(P.n, np.int64)
+    tin = np.bincount(T.col.astype(np.int64), minlength=T.n) if T.col.size else np.zeros(T.n, np.int64)
+    order = [int(u) for u in order]
+
+    def unary(u, v):
+        if labelled and P.labels[u] != T.labels[v]:
+            return False
+        if pout[u] > tout[v] or pin[u] > tin[v]:
+            return False
+        return domains is None or bool(domains[u, v])
+
+    total = 0
+    for d in range(1, P.n + 1):
+        us = order[:d]
+        pos = {u: i for i, u in enumerate(us)}
+        inner = [(pos[a], pos[b], lb) for (a, b), lb in pa.items() if a in pos and b in pos]
+        for m in itertools.permutations(range(T.n), d):
+            if not all(unary(us[i], m[i]) for i in range(d)):
+                continue
+            if all((m[i], m[j]) in ta and (not labelled or ta[(m[i], m[j])] == lb) for i, j, lb in inner):
+                total += 1
+    return total
+
+
+def brute_ac_domains(P: Graph, T: Graph, labelled: bool) -> np.ndarray:
+    """Greatest arc-consistent domains by naive iteration: start from label,
+    out-degree and in-degree compatibility; remove v from D(u) while some
+    pattern arc u -> w (w -> u) has no target arc v -> x (x -> v) of the same
+    label (labelled) with x in D(w).  Returns bool [k, n]."""
+    pa, ta = arcs_of(P), arcs_of(T)
+    pout = np.diff(P.row_ptr.astype(np.int64))
+    tout = np.diff(T.row_ptr.astype(np.int64))
+    pin = np.bincount(P.col.astype(np.int64), minlength=P.n) if P.col.size else np.zeros(P.n, np.int64)
+    tin = np.bincount(T.col.astype(np.int64), minlength=T.n) if T.col.size else np.zeros(T.n, np.int64)
+    D = np.zeros((P.n, T.n), dtype=bool)
+    for u in range(P.n):
+        for v in range(T.n):
+            D[u, v] = (not labelled or P.labels[u] == T.labels[v]) and pout[u] <= tout[v] and pin[u] <= tin[v]
+    changed = True
+    while changed:
+        changed = False
+        for u in range(P.n):
+            for v in range(T.n):
+                if not D[u, v]:
+                    continue
+                ok = True
+                for (a, b), lb in pa.items():
+                    if a == u:
+                        ok = any(x == v and D[b, y] and (not labelled or tl == lb) for (x, y), tl in ta.items())
+                    elif b == u:
+                        ok = any(y == v and D[a, x] and (not labelled or tl == lb) for (x, y), tl in ta.items())
+                    if not ok:
+                        break
+                if not ok:
+                    D[u, v] = False
+                    changed = True
+    return D
