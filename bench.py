@@ -11,11 +11,11 @@ match counts are checked against the oracle's stored values.
 
 Also reported: the plain single-instance path (one sge_count per pattern) on
 the same patterns, the same batch in each of the four search modes (the
-variant study), the C1 / C4 / dense C3 workloads, the serving run (p50/p99
-latency), the kernel's algorithmic-byte rate against the HBM peak, and the
+variant study), the C1 / C4 / dense C3 workloads, the directed edge-labelled
+workload (c2d), the serving run (p50/p99 latency), the kernel's algorithmic-byte rate against the HBM peak, and the
 oracle's own rate on this host (a baseline, not the target).
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--extra c4,c1,c3]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--extra c1,c4,c3,c2d]
                     [--c3-patterns 8] [--serve-seconds 10] [--no-variants]
 """
 from __future__ import annotations
@@ -46,7 +46,8 @@ def load_manifest(cfg):
 
 def instances(cfg, man):
     from paper_1705_09358_amd import synth
-    make = {"c1": synth.c1_instance, "c2": synth.c2_instance, "c4": synth.c4_instance}[cfg]
+    make = {"c1": synth.c1_instance, "c2": synth.c2_instance, "c4": synth.c4_instance,
+            "c2d": synth.c2d_instance}[cfg]
     return [make(r["j"], r["attempt"]) for r in man["instances"]]
 
 
@@ -296,7 +297,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--extra", default="c1,c4,c3", help="comma list of extra workloads: c1, c4, c3 ('' for none)")
+    ap.add_argument("--extra", default="c1,c4,c3,c2d",
+                    help="comma list of extra workloads: c1, c4, c3, c2d (directed, edge labels) ('' for none)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--c3-patterns", type=int, default=4)

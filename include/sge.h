@@ -108,6 +108,24 @@ sge_status sge_load_pattern(sge_ctx *ctx, uint32_t k, const uint32_t *row_ptr, c
                             const uint32_t *labels, uint32_t *handle);
 sge_status sge_unload_pattern(sge_ctx *ctx, uint32_t handle);
 
+/* The general graphs of Section 2.1: directed, with node and edge labels.
+ * directed = 1: row_ptr/col list the out-edges (arcs) of each node; the
+ * library builds the in-edges.  directed = 0: as sge_load_target (both
+ * directions of every edge).  edge_labels: row_ptr[n] uint32, the label of
+ * each CSR entry (an undirected edge carries one label in both directions),
+ * or NULL (all 0).  Duplicate entries must carry one label (else
+ * SGE_E_INVAL).  Edge labels are compared exactly when node labels are
+ * (sge_set_labelled, sge_job.labelled).  A search with a directed graph on
+ * either side keeps directions: rule 3 compares in- and out-degree, every
+ * pattern arc must map onto a target arc of the same direction (and label);
+ * the order and parents ignore directions (Section "RI").  Such searches are
+ * planned on the host and run the CSR search kernel. */
+sge_status sge_load_target_ex(sge_ctx *ctx, uint32_t n, const uint32_t *row_ptr, const uint32_t *col,
+                              const uint32_t *labels, const uint32_t *edge_labels, int directed, uint32_t *handle);
+sge_status sge_load_pattern_ex(sge_ctx *ctx, uint32_t k, const uint32_t *row_ptr, const uint32_t *col,
+                               const uint32_t *labels, const uint32_t *edge_labels, int directed,
+                               uint32_t *handle);
+
 /* labelled = 0: labels are ignored (every node equivalent, Section 2.1). */
 sge_status sge_set_labelled(sge_ctx *ctx, int labelled);
 /* mode: SGE_RI | SGE_RIDS | SGE_RIDS_SI | SGE_RIDS_SI_FC. */
@@ -175,6 +193,13 @@ sge_status sge_serve_stop(sge_ctx *ctx);
 sge_status sge_plan_host(uint32_t k, const uint32_t *p_row_ptr, const uint32_t *p_col, const uint32_t *p_labels,
                          uint32_t n, const uint32_t *t_row_ptr, const uint32_t *t_col, const uint32_t *t_labels,
                          int mode, int labelled, uint32_t *order, int32_t *parent, uint64_t *dom, int *empty);
+/* The same for general graphs (edge labels or NULL, directed flags as in
+ * sge_load_target_ex). */
+sge_status sge_plan_host_ex(uint32_t k, const uint32_t *p_row_ptr, const uint32_t *p_col, const uint32_t *p_labels,
+                            const uint32_t *p_edge_labels, int p_directed, uint32_t n, const uint32_t *t_row_ptr,
+                            const uint32_t *t_col, const uint32_t *t_labels, const uint32_t *t_edge_labels,
+                            int t_directed, int mode, int labelled, uint32_t *order, int32_t *parent, uint64_t *dom,
+                            int *empty);
 
 /* The plan the device computes for one instance, as every search launch
  * computes it before searching (domains of Section 4.1 with arc-consistency,

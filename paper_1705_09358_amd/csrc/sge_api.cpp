@@ -58,7 +58,7 @@ static constexpr uint32_t ADJ_BITSET_MAX_N = 65536;
 sge_status upload_target(sge_ctx *c, Target &t) {
     const HostGraph &g = t.g;
     std::vector<NodeRec> rec(g.n);
-    for (uint32_t v = 0; v < g.n; v++) rec[v] = NodeRec{g.rp[v], g.rp[v + 1] - g.rp[v], t.dlab[v], 0};
+    for (uint32_t v = 0; v < g.n; v++) rec[v] = NodeRec{g.rp[v], g.outdeg(v), t.dlab[v], g.indeg(v)};
     size_t mcol = std::max<size_t>(g.col.size(), 1);
     hipError_t e;
     if ((e = hipMalloc(&t.d_col, mcol * 4)) != hipSuccess) return hip_fail(c, e, "hipMalloc(col)");
@@ -69,7 +69,26 @@ sge_status upload_target(sge_ctx *c, Target &t) {
         return hip_fail(c, e, "upload col");
     if (g.n && (e = hipMemcpy(t.d_node, rec.data(), g.n * sizeof(NodeRec), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(c, e, "upload node records");
-    if (g.n && g.n <= ADJ_BITSET_MAX_N) {
+    auto up = [&](uint32_t *&dst, const std::vector<uint32_t> &src, const char *what) -> sge_status {
+        const size_t bytes = std::max<size_t>(src.size(), 1) * 4;
+        hipError_t e2 = hipMalloc(&dst, bytes);
+        if (e2 != hipSuccess) return hip_fail(c, e2, what);
+        if (!src.empty() && (e2 = hipMemcpy(dst, src.data(), src.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(c, e2, what);
+        t.dev_bytes += bytes;
+        return SGE_OK;
+    };
+    sge_status st;
+    if (g.directed) {
+        if ((st = up(t.d_irp, g.irp, "upload in-edge rows")) != SGE_OK) return st;
+        if ((st = up(t.d_icol, g.icol, "upload in-edges")) != SGE_OK) return st;
+    }
+    if (g.has_elab()) {
+        if ((st = up(t.d_elab, g.elab, "upload edge labels")) != SGE_OK) return st;
+        if (g.directed && (st = up(t.d_ielab, g.ielab, "upload in-edge labels")) != SGE_OK) return st;
+    }
+    // adjacency rows (undirected targets: the dense search and direct edge tests)
+    if (g.n && g.n <= ADJ_BITSET_MAX_N && !g.directed) {
         std::vector<uint64_t> adj((size_t)g.n * t.W, 0);
         for (uint32_t v = 0; v < g.n; v++)
             for (uint32_t i = g.rp[v]; i < g.rp[v + 1]; i++) {
@@ -96,6 +115,9 @@ void free_target(Target &t) {
     if (t.d_node) (void)hipFree(t.d_node);
     if (t.d_adj) (void)hipFree(t.d_adj);
     if (t.d_label_keys) (void)hipFree(t.d_label_keys);
+    for (uint32_t *q : {t.d_irp, t.d_icol, t.d_elab, t.d_ielab})
+        if (q) (void)hipFree(q);
+    t.d_irp = t.d_icol = t.d_elab = t.d_ielab = nullptr;
     t.d_col = nullptr;
     t.d_node = nullptr;
     t.d_adj = nullptr;
@@ -115,11 +137,15 @@ sge_status upload_pattern(sge_ctx *c, Pattern &p) {
         while (!stack.empty()) {
             const uint32_t u = stack.back();
             stack.pop_back();
-            for (uint32_t e = g.rp[u]; e < g.rp[u + 1]; e++)
-                if (comp[g.col[e]] == 0xFFFFFFFFu) {
-                    comp[g.col[e]] = dp.ncomp;
-                    stack.push_back(g.col[e]);
-                }
+            // arcs in either direction join a component
+            for (int dir = 0; dir < 2; dir++) {
+                const std::vector<uint32_t> &rp = dir ? g.in_rp() : g.rp, &cl = dir ? g.in_col() : g.col;
+                for (uint32_t e = rp[u]; e < rp[u + 1]; e++)
+                    if (comp[cl[e]] == 0xFFFFFFFFu) {
+                        comp[cl[e]] = dp.ncomp;
+                        stack.push_back(cl[e]);
+                    }
+            }
         }
         dp.ncomp++;
     }
@@ -199,9 +225,14 @@ sge_status sge_last_launch_timing(const sge_ctx *c, double *ms) {
 
 sge_status sge_load_target(sge_ctx *c, uint32_t n, const uint32_t *row_ptr, const uint32_t *col,
                            const uint32_t *labels, uint32_t *handle) {
+    return sge_load_target_ex(c, n, row_ptr, col, labels, nullptr, 0, handle);
+}
+
+sge_status sge_load_target_ex(sge_ctx *c, uint32_t n, const uint32_t *row_ptr, const uint32_t *col,
+                              const uint32_t *labels, const uint32_t *edge_labels, int directed, uint32_t *handle) {
     if (!c || !handle) return SGE_E_INVAL;
     auto t = std::make_unique<Target>();
-    std::string why = normalise_graph(n, row_ptr, col, labels, t->g);
+    std::string why = normalise_graph(n, row_ptr, col, labels, edge_labels, directed != 0, t->g);
     if (!why.empty()) return fail(c, SGE_E_INVAL, "target: " + why);
     index_target(*t);
     (void)hipSetDevice(c->device);
@@ -228,10 +259,16 @@ sge_status sge_unload_target(sge_ctx *c, uint32_t handle) {
 
 sge_status sge_load_pattern(sge_ctx *c, uint32_t k, const uint32_t *row_ptr, const uint32_t *col,
                             const uint32_t *labels, uint32_t *handle) {
+    return sge_load_pattern_ex(c, k, row_ptr, col, labels, nullptr, 0, handle);
+}
+
+sge_status sge_load_pattern_ex(sge_ctx *c, uint32_t k, const uint32_t *row_ptr, const uint32_t *col,
+                               const uint32_t *labels, const uint32_t *edge_labels, int directed,
+                               uint32_t *handle) {
     if (!c || !handle) return SGE_E_INVAL;
     if (k > KMAX) return fail(c, SGE_E_INVAL, "pattern has more than 64 nodes");
     auto p = std::make_unique<Pattern>();
-    std::string why = normalise_graph(k, row_ptr, col, labels, p->g);
+    std::string why = normalise_graph(k, row_ptr, col, labels, edge_labels, directed != 0, p->g);
     if (!why.empty()) return fail(c, SGE_E_INVAL, "pattern: " + why);
     (void)hipSetDevice(c->device);
     sge_status st = upload_pattern(c, *p);
@@ -388,6 +425,7 @@ sge_status sge_plan_device(sge_ctx *c, uint32_t target, uint32_t pattern, int mo
     s.p = ip->second.get();
     s.mode = mode;
     s.labelled = labelled != 0;
+    if (general_instance(s)) return fail(c, SGE_E_INVAL, "the plan kernel covers undirected graphs without edge labels");
     std::vector<const InstanceSpec *> sp{&s};
     Pack pk;
     sge_status st = pack_instances(c, sp, false, 2, c->bufs, pk);
@@ -415,12 +453,20 @@ sge_status sge_plan_device(sge_ctx *c, uint32_t target, uint32_t pattern, int mo
 sge_status sge_plan_host(uint32_t k, const uint32_t *p_rp, const uint32_t *p_col, const uint32_t *p_lab, uint32_t n,
                          const uint32_t *t_rp, const uint32_t *t_col, const uint32_t *t_lab, int mode, int labelled,
                          uint32_t *order, int32_t *parent, uint64_t *dom, int *empty) {
+    return sge_plan_host_ex(k, p_rp, p_col, p_lab, nullptr, 0, n, t_rp, t_col, t_lab, nullptr, 0, mode, labelled, order,
+                            parent, dom, empty);
+}
+
+sge_status sge_plan_host_ex(uint32_t k, const uint32_t *p_rp, const uint32_t *p_col, const uint32_t *p_lab,
+                            const uint32_t *p_elab, int p_dir, uint32_t n, const uint32_t *t_rp, const uint32_t *t_col,
+                            const uint32_t *t_lab, const uint32_t *t_elab, int t_dir, int mode, int labelled,
+                            uint32_t *order, int32_t *parent, uint64_t *dom, int *empty) {
     if (k > KMAX || !order || !parent || !empty) return SGE_E_INVAL;
     if (mode < SGE_RI || mode > SGE_RIDS_SI_FC) return SGE_E_INVAL;
     Target t;
-    if (!normalise_graph(n, t_rp, t_col, t_lab, t.g).empty()) return SGE_E_INVAL;
+    if (!normalise_graph(n, t_rp, t_col, t_lab, t_elab, t_dir != 0, t.g).empty()) return SGE_E_INVAL;
     HostGraph p;
-    if (!normalise_graph(k, p_rp, p_col, p_lab, p).empty()) return SGE_E_INVAL;
+    if (!normalise_graph(k, p_rp, p_col, p_lab, p_elab, p_dir != 0, p).empty()) return SGE_E_INVAL;
     index_target(t);
     Plan pl;
     std::vector<uint64_t> bits;

@@ -136,7 +136,9 @@ sge_status pack_host_planned(sge_ctx *c, const std::vector<const InstanceSpec *>
 // searches and small launches are planned on the host, where the short serial
 // work of one plan finishes sooner.
 constexpr size_t PLAN_DEVICE_MIN_INSTANCES = 64;
-bool plan_on_device(const sge_ctx *c, size_t ninst);
+bool plan_on_device(const sge_ctx *c, const std::vector<const InstanceSpec *> &specs);
+// A search with a directed graph, or edge labels that are compared.
+bool general_instance(const InstanceSpec &s);
 // Upload, plan, reset, search and read back on `s` (asynchronous).
 hipError_t enqueue_pack(sge_ctx *c, const Pack &pk, LaunchBufs &bufs, hipStream_t s);
 // Upload and plan only (the plan of instance 0 is then read back by the caller).

@@ -1,6 +1,7 @@
-// Graph ingest: validation and normalisation of symmetric CSR input, and the
-// per-target label index the planner reads.  Graphs are undirected and simple
-// (Section 2.1 with undirected edges); labels are compared for equality only.
+// Graph ingest: validation and normalisation of CSR input, and the per-target
+// label index the planner reads.  Graphs are simple (Section 2.1), directed or
+// undirected (both directions of every edge), with node and optional edge
+// labels compared for equality only.
 #include <algorithm>
 #include <unordered_map>
 
@@ -9,7 +10,7 @@
 namespace sge {
 
 std::string normalise_graph(uint32_t n, const uint32_t *row_ptr, const uint32_t *col, const uint32_t *labels,
-                            HostGraph &out) {
+                            const uint32_t *edge_labels, bool directed, HostGraph &out) {
     if (!row_ptr) return "row_ptr is NULL";
     if (row_ptr[0] != 0) return "row_ptr[0] must be 0";
     for (uint32_t v = 0; v < n; v++)
@@ -17,30 +18,63 @@ std::string normalise_graph(uint32_t n, const uint32_t *row_ptr, const uint32_t 
     uint64_t m = row_ptr[n];
     if (m && !col) return "col is NULL";
     if (m > 0xFFFFFFF0ull) return "too many adjacency entries";
+    out = HostGraph{};
     out.n = n;
+    out.directed = directed;
     out.rp.assign(n + 1, 0);
-    out.col.clear();
     out.col.reserve(m);
-    std::vector<uint32_t> row;
+    if (edge_labels) out.elab.reserve(m);
+    std::vector<std::pair<uint32_t, uint32_t>> row;   // (neighbour, edge label)
     for (uint32_t v = 0; v < n; v++) {
-        row.assign(col + row_ptr[v], col + row_ptr[v + 1]);
-        for (uint32_t w : row) {
+        row.clear();
+        for (uint64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) {
+            const uint32_t w = col[e];
             if (w >= n) return "neighbour id out of range at node " + std::to_string(v);
             if (w == v) return "self-loop at node " + std::to_string(v);
+            row.emplace_back(w, edge_labels ? edge_labels[e] : 0u);
         }
         std::sort(row.begin(), row.end());
-        row.erase(std::unique(row.begin(), row.end()), row.end());
-        out.col.insert(out.col.end(), row.begin(), row.end());
+        for (size_t i = 0; i < row.size(); i++) {
+            if (i && row[i].first == row[i - 1].first) {
+                if (row[i].second != row[i - 1].second)
+                    return "edge " + std::to_string(v) + " -> " + std::to_string(row[i].first) +
+                           " given twice with different labels";
+                continue;
+            }
+            out.col.push_back(row[i].first);
+            if (edge_labels) out.elab.push_back(row[i].second);
+        }
         out.rp[v + 1] = (uint32_t)out.col.size();
     }
-    // symmetry: every (v, w) needs (w, v)
-    for (uint32_t v = 0; v < n; v++) {
-        for (uint32_t e = out.rp[v]; e < out.rp[v + 1]; e++) {
-            uint32_t w = out.col[e];
-            if (!std::binary_search(out.col.begin() + out.rp[w], out.col.begin() + out.rp[w + 1], v))
-                return "asymmetric adjacency: " + std::to_string(v) + " -> " + std::to_string(w) +
-                       " has no reverse entry";
+    if (!directed) {
+        // every (v, w) needs (w, v), with the same label
+        for (uint32_t v = 0; v < n; v++) {
+            for (uint32_t e = out.rp[v]; e < out.rp[v + 1]; e++) {
+                const uint32_t w = out.col[e];
+                auto b = out.col.begin() + out.rp[w], en = out.col.begin() + out.rp[w + 1];
+                auto it = std::lower_bound(b, en, v);
+                if (it == en || *it != v)
+                    return "asymmetric adjacency: " + std::to_string(v) + " -> " + std::to_string(w) +
+                           " has no reverse entry";
+                if (edge_labels && out.elab[it - out.col.begin()] != out.elab[e])
+                    return "undirected edge " + std::to_string(v) + " - " + std::to_string(w) +
+                           " has different labels in its two directions";
+            }
         }
+    } else {
+        // in-edges: the transpose, rows sorted by source
+        out.irp.assign(n + 1, 0);
+        for (uint32_t w : out.col) out.irp[w + 1]++;
+        for (uint32_t v = 0; v < n; v++) out.irp[v + 1] += out.irp[v];
+        out.icol.resize(out.col.size());
+        if (edge_labels) out.ielab.resize(out.col.size());
+        std::vector<uint32_t> fill(out.irp.begin(), out.irp.end() - 1);
+        for (uint32_t v = 0; v < n; v++)
+            for (uint32_t e = out.rp[v]; e < out.rp[v + 1]; e++) {
+                const uint32_t at = fill[out.col[e]]++;
+                out.icol[at] = v;
+                if (edge_labels) out.ielab[at] = out.elab[e];
+            }
     }
     out.has_labels = labels != nullptr;
     out.lab.assign(n, 0);

@@ -17,16 +17,35 @@ constexpr uint32_t LABEL_NONE = 0xFFFFFFFFu; // pattern label absent from the ta
 constexpr uint32_t QUEUE_SLOTS = 4096;     // work-queue capacity (tasks)
 
 // ---------------------------------------------------------------- host graphs
+// A graph as the host keeps it.  rp/col: the out-edges (both directions of
+// every edge when undirected), sorted rows; elab: one label per col entry, or
+// empty (all 0).  A directed graph also keeps its in-edges (irp/icol/ielab,
+// rows sorted by source); an undirected one reads them from rp/col/elab.
 struct HostGraph {
     uint32_t n = 0;
     std::vector<uint32_t> rp, col, lab;  // lab: raw labels as given (0 if none)
-    bool has_labels = false;
+    std::vector<uint32_t> elab;
+    std::vector<uint32_t> irp, icol, ielab;
+    bool has_labels = false, directed = false;
+
+    uint32_t outdeg(uint32_t v) const { return rp[v + 1] - rp[v]; }
+    uint32_t indeg(uint32_t v) const { return directed ? irp[v + 1] - irp[v] : rp[v + 1] - rp[v]; }
+    const std::vector<uint32_t> &in_rp() const { return directed ? irp : rp; }
+    const std::vector<uint32_t> &in_col() const { return directed ? icol : col; }
+    const std::vector<uint32_t> &in_elab() const { return directed ? ielab : elab; }
+    bool has_elab() const { return !elab.empty(); }
 };
 
-// Validate and normalise symmetric CSR input (sort rows, merge duplicates).
+// Validate and normalise CSR input: sort rows, merge duplicate entries
+// (which must carry one label), reject self-loops and out-of-range ids;
+// undirected input must hold both directions of every edge with one label.
 // Returns an empty string on success, else the reason.
 std::string normalise_graph(uint32_t n, const uint32_t *row_ptr, const uint32_t *col, const uint32_t *labels,
-                            HostGraph &out);
+                            const uint32_t *edge_labels, bool directed, HostGraph &out);
+inline std::string normalise_graph(uint32_t n, const uint32_t *row_ptr, const uint32_t *col, const uint32_t *labels,
+                                   HostGraph &out) {
+    return normalise_graph(n, row_ptr, col, labels, nullptr, false, out);
+}
 
 // Per-node record read by the search: row start and degree in the CSR, and
 // the dense label id.
@@ -52,6 +71,8 @@ struct Target {
     NodeRec *d_node = nullptr;
     uint64_t *d_adj = nullptr;                   // n * W, or null when too large
     uint32_t *d_label_keys = nullptr;            // label_keys on the device
+    uint32_t *d_irp = nullptr, *d_icol = nullptr;   // directed: in-edges
+    uint32_t *d_elab = nullptr, *d_ielab = nullptr; // edge labels (out, in), or null
     uint64_t dev_bytes = 0;
 };
 
@@ -70,17 +91,27 @@ struct Pattern {
     DevPattern *d_pat = nullptr;
 };
 
+// Plan flags: directions or edge labels take part in the search.
+constexpr uint32_t PLAN_DIRECTED = 1u, PLAN_EDGE_LABELS = 2u;
+
 // Search plan of one (pattern, target, mode, labelled) instance.
 struct Plan {
     uint32_t k = 0, n = 0, W = 0;
     int mode = SGE_RI;
     bool labelled = true;
     bool empty = false;        // a domain became empty: no match, nothing to search
+    uint32_t flags = 0;        // PLAN_DIRECTED | PLAN_EDGE_LABELS
     uint32_t order[KMAX];      // position -> pattern node
     int32_t parent[KMAX];      // position -> earlier position or -1
     uint64_t back[KMAX];       // earlier adjacent positions other than the parent
+    uint64_t bout[KMAX];       // directed: earlier positions (not the parent) with an arc into this one
+    uint64_t bin[KMAX];        // directed: earlier positions (not the parent) this one has an arc to
+    uint64_t pdir_out = 0;     // bit i: position i's candidates are out-neighbours of its parent's image
+    uint64_t pboth = 0;        // bit i: arcs both ways between position i and its parent
     uint32_t plabel[KMAX];     // dense target label id, LABEL_ANY or LABEL_NONE
-    uint32_t pdeg[KMAX];
+    uint32_t pdeg[KMAX];       // out-degree (the degree when undirected)
+    uint32_t pindeg[KMAX];     // in-degree
+    std::vector<uint32_t> lmat;   // edge labels: k*k, [a*k+b] = label of arc order[a] -> order[b] or LABEL_NONE
     std::vector<uint64_t> dom_node;   // RI-DS: k * W final domains by pattern node
     std::vector<uint32_t> lists;      // candidate lists of parentless positions
     uint32_t list_off[KMAX], list_len[KMAX];
@@ -102,19 +133,28 @@ void index_target(Target &t);
 // Everything one instance of the search needs, as the kernels read it.
 struct DevPlan {
     uint32_t k, W, n, use_dom;
-    uint32_t labelled, empty, pad1, pad2;   // empty: a domain became empty (nothing to search)
+    uint32_t labelled, empty, flags, pad2;   // empty: a domain became empty (nothing to search)
     int32_t parent[KMAX];
     uint64_t back[KMAX];
     uint32_t plabel[KMAX];
-    uint32_t pdeg[KMAX];
+    uint32_t pdeg[KMAX];                     // out-degree (the degree when undirected)
     uint32_t order[KMAX];
     uint32_t list_off[KMAX];
     uint32_t list_len[KMAX];
+    // with PLAN_DIRECTED or PLAN_EDGE_LABELS (plans built on the host)
+    uint32_t pindeg[KMAX];
+    uint64_t bout[KMAX], bin[KMAX];
+    uint64_t pdir_out, pboth;
 };
 
 struct InstDesc {
-    const uint32_t *col;      // target CSR column array
-    const NodeRec *node;      // target node records
+    const uint32_t *col;      // target CSR column array (out-edges)
+    const NodeRec *node;      // target node records (pad = in-degree)
+    const uint32_t *irp;      // directed target: in-edge row starts (n+1), else null
+    const uint32_t *icol;     // directed target: in-edges, rows sorted by source, else null
+    const uint32_t *elab;     // target edge labels per out entry, or null (all 0)
+    const uint32_t *ielab;    // target edge labels per in entry, or null
+    const uint32_t *lmat;     // k*k pattern arc labels by position pair (PLAN_EDGE_LABELS), or null
     const uint64_t *adj;      // target adjacency bitsets (n*W) or null
     const DevPlan *plan;
     const uint64_t *bits;     // k*W by position: domains (CSR RI-DS) or dense-mode sets, or null

@@ -27,10 +27,17 @@ void LaunchBufs::release() {
     work = DevWork{};
 }
 
+bool general_instance(const InstanceSpec &s) {
+    return s.t->g.directed || s.p->g.directed || (s.labelled && (s.t->g.has_elab() || s.p->g.has_elab()));
+}
+
 bool choose_dense(const sge_ctx *c, const std::vector<InstanceSpec> &specs) {
     // dense-bitset search when every target has adjacency rows and is dense
-    // enough that a row of W words costs no more than walking a neighbour list
+    // enough that a row of W words costs no more than walking a neighbour list;
+    // directed or edge-labelled searches take the CSR kernel
     if (c->dense == 0 || specs.empty()) return false;
+    for (const InstanceSpec &s : specs)
+        if (general_instance(s)) return false;
     bool all_adj = true;
     double deg = 0, words = 0;
     for (const InstanceSpec &s : specs) {
@@ -49,9 +56,11 @@ static uint64_t list_entries(const InstanceSpec &s) {
     return (uint64_t)std::max<uint32_t>(s.p->ncomp, 1) * s.t->g.n + s.p->g.n;
 }
 
-bool plan_on_device(const sge_ctx *c, size_t ninst) {
+bool plan_on_device(const sge_ctx *c, const std::vector<const InstanceSpec *> &specs) {
+    for (const InstanceSpec *s : specs)
+        if (general_instance(*s)) return false;   // the plan kernel covers undirected graphs without edge labels
     if (c->plan_where >= 0) return c->plan_where == 1;
-    return ninst >= PLAN_DEVICE_MIN_INSTANCES;
+    return specs.size() >= PLAN_DEVICE_MIN_INSTANCES;
 }
 
 uint64_t instance_device_bytes(const InstanceSpec &s) {
@@ -209,10 +218,12 @@ sge_status pack_host_planned(sge_ctx *c, const std::vector<const InstanceSpec *>
     pk.off_pref = align_up(off_desc + m * sizeof(InstDesc), 256);
     const size_t off_plan = align_up(pk.off_pref + (m + 1) * sizeof(unsigned), 256);
     size_t cur = align_up(off_plan + m * sizeof(DevPlan), 256);
-    std::vector<size_t> list_at(m), bits_at(m);
+    std::vector<size_t> list_at(m), bits_at(m), lmat_at(m);
     for (uint32_t j = 0; j < m; j++) {
         list_at[j] = cur;
         cur = align_up(cur + plans[j]->lists.size() * 4, 16);
+        lmat_at[j] = cur;
+        cur = align_up(cur + plans[j]->lmat.size() * 4, 16);
     }
     cur = align_up(cur, 256);
     for (uint32_t j = 0; j < m; j++) {
@@ -250,14 +261,26 @@ sge_status pack_host_planned(sge_ctx *c, const std::vector<const InstanceSpec *>
             dp.order[i] = pl.order[i];
             dp.list_off[i] = pl.list_off[i];
             dp.list_len[i] = pl.list_len[i];
+            dp.pindeg[i] = pl.pindeg[i];
+            dp.bout[i] = pl.bout[i];
+            dp.bin[i] = pl.bin[i];
         }
+        dp.flags = pl.flags;
+        dp.pdir_out = pl.pdir_out;
+        dp.pboth = pl.pboth;
         std::memcpy(hb + list_at[j], pl.lists.data(), pl.lists.size() * 4);
+        std::memcpy(hb + lmat_at[j], pl.lmat.data(), pl.lmat.size() * 4);
         std::memcpy(hb + bits_at[j], bits[j]->data(), bits[j]->size() * 8);
         InstDesc &d = ((InstDesc *)(hb + off_desc))[j];
         d = InstDesc{};
         d.col = sp.t->d_col;
         d.node = sp.t->d_node;
         d.adj = sp.t->d_adj;
+        d.irp = sp.t->d_irp;
+        d.icol = sp.t->d_icol;
+        d.elab = sp.t->d_elab;
+        d.ielab = sp.t->d_ielab;
+        d.lmat = pl.lmat.empty() ? nullptr : (const uint32_t *)(db + lmat_at[j]);
         d.plan = (const DevPlan *)(db + off_plan) + j;
         d.bits = bits[j]->empty() ? nullptr : (const uint64_t *)(db + bits_at[j]);
         d.lists = (const uint32_t *)(db + list_at[j]);
@@ -352,9 +375,18 @@ sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std
         return SGE_OK;
     }
     const bool dense = choose_dense(c, specs);
+    if (c->dense == 1 && !dense) {
+        for (const InstanceSpec *x : sp)
+            if (general_instance(*x)) return fail(c, SGE_E_INVAL, "the dense search covers undirected graphs without edge labels");
+    }
+    if (c->plan_where == 1) {
+        for (const InstanceSpec *x : sp)
+            if (general_instance(*x))
+                return fail(c, SGE_E_INVAL, "the plan kernel covers undirected graphs without edge labels");
+    }
     Pack pk;
     sge_status st;
-    if (plan_on_device(c, sp.size())) {
+    if (plan_on_device(c, sp)) {
         st = pack_instances(c, sp, dense, policy, c->bufs, pk);
     } else {
         // host plans (threads for larger sets); an empty domain answers its

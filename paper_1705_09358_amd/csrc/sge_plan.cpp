@@ -3,10 +3,13 @@
 // tie-break (Section "RI" ordering; Section 4.2.1), parents and back-edges.
 //
 // Pattern neighbourhoods are 64-bit masks (k <= 64); domains are bitsets of
-// ceil(n/64) words.  Arc-consistency keeps v in D(u) iff for every pattern
-// neighbour w of u some target neighbour of v lies in D(w) (the graphs are
-// undirected).  Values are removed until nothing changes; every order of
-// removals reaches the same greatest arc-consistent domains.
+// ceil(n/64) words.  Arc-consistency keeps v in D(u) iff every pattern arc
+// u -> w has a target arc v -> x with x in D(w), and every arc w -> u a target
+// arc x -> v with x in D(w), with equal edge labels when labels are compared
+// (for undirected graphs the two cases coincide).  Values are removed until
+// nothing changes; every order of removals reaches the same greatest
+// arc-consistent domains.  Directed graphs: the order and the parents ignore
+// directions (Section "RI"); rule 3 compares in- and out-degree.
 #include <algorithm>
 #include <cstring>
 
@@ -34,14 +37,28 @@ void build_plan(const Target &t, const HostGraph &p, int mode, bool labelled, ui
     pl.empty = false;
     pl.dom_node.clear();
     pl.lists.clear();
+    pl.lmat.clear();
+    // directions and edge labels matter only if a graph is directed or
+    // carries edge labels that are compared
+    const bool directed = p.directed || tg.directed;
+    const bool elabelled = labelled && (p.has_elab() || tg.has_elab());
+    pl.flags = (directed ? PLAN_DIRECTED : 0u) | (elabelled ? PLAN_EDGE_LABELS : 0u);
 
-    // pattern node data: neighbourhood mask, degree, target label id
-    uint64_t nb[KMAX];
-    uint32_t deg[KMAX], lab[KMAX];
+    // pattern node data: neighbourhood (directions ignored), out-degree,
+    // in-degree, degree for the order, target label id
+    uint64_t nb[KMAX], outm[KMAX];
+    uint32_t deg[KMAX], indeg[KMAX], odeg[KMAX], lab[KMAX];
+    for (uint32_t u = 0; u < k; u++) nb[u] = outm[u] = 0;
+    for (uint32_t u = 0; u < k; u++)
+        for (uint32_t e = p.rp[u]; e < p.rp[u + 1]; e++) {
+            outm[u] |= 1ull << p.col[e];
+            nb[u] |= 1ull << p.col[e];
+            nb[p.col[e]] |= 1ull << u;
+        }
     for (uint32_t u = 0; u < k; u++) {
-        nb[u] = 0;
-        for (uint32_t e = p.rp[u]; e < p.rp[u + 1]; e++) nb[u] |= 1ull << p.col[e];
-        deg[u] = p.rp[u + 1] - p.rp[u];
+        deg[u] = p.outdeg(u);
+        indeg[u] = p.indeg(u);
+        odeg[u] = (uint32_t)__builtin_popcountll(nb[u]);
         if (!labelled) {
             lab[u] = LABEL_ANY;
         } else {
@@ -50,17 +67,23 @@ void build_plan(const Target &t, const HostGraph &p, int mode, bool labelled, ui
                 if (t.label_keys[id] == p.lab[u]) { lab[u] = id; break; }
         }
     }
-    auto tdeg = [&](uint32_t v) { return tg.rp[v + 1] - tg.rp[v]; };
+    auto tdeg_ok = [&](uint32_t u, uint32_t v) { return tg.outdeg(v) >= deg[u] && tg.indeg(v) >= indeg[u]; };
     // nodes of V_t passing the label and degree rules for pattern node u
     auto compat_nodes = [&](uint32_t u, auto &&fn) {
         if (lab[u] == LABEL_NONE) return;
         if (lab[u] == LABEL_ANY) {
             for (uint32_t v = 0; v < n; v++)
-                if (tdeg(v) >= deg[u]) fn(v);
+                if (tdeg_ok(u, v)) fn(v);
         } else {
             for (uint32_t v : t.by_label[lab[u]])
-                if (tdeg(v) >= deg[u]) fn(v);
+                if (tdeg_ok(u, v)) fn(v);
         }
+    };
+    // label of the pattern arc a -> b (must exist)
+    auto parc = [&](uint32_t a, uint32_t b) -> uint32_t {
+        if (!p.has_elab()) return 0u;
+        auto it = std::lower_bound(p.col.begin() + p.rp[a], p.col.begin() + p.rp[a + 1], b);
+        return p.elab[it - p.col.begin()];
     };
 
     const bool use_dom = mode != SGE_RI;
@@ -77,7 +100,7 @@ void build_plan(const Target &t, const HostGraph &p, int mode, bool labelled, ui
         bool any_empty = false;
         for (uint32_t u = 0; u < k; u++) any_empty |= popcount_row(&D[(size_t)u * W], W) == 0;
         uint64_t dirty = 0;   // nodes whose domain changed since their neighbours were revised against it
-        if (!any_empty && !t.nbr_deg.empty()) {
+        if (!any_empty && !t.nbr_deg.empty() && !directed && !elabelled) {
             // first round against the label-and-degree domains: a target node
             // has a neighbour in D(w) iff it has a neighbour of w's label whose
             // degree is at least w's, which the target's table answers
@@ -106,6 +129,15 @@ void build_plan(const Target &t, const HostGraph &p, int mode, bool labelled, ui
             for (uint32_t u = 0; u < k; u++)
                 if (nb[u]) dirty |= 1ull << u;
         }
+        const std::vector<uint32_t> &irp = tg.in_rp(), &icol = tg.in_col(), &ielab = tg.in_elab();
+        // a target arc out of v (in: into v) of label b reaching a member of D(w)
+        auto supported = [&](uint32_t v, const uint64_t *dw, bool in, uint32_t b) {
+            const std::vector<uint32_t> &rp = in ? irp : tg.rp, &cl = in ? icol : tg.col;
+            const std::vector<uint32_t> &el = in ? ielab : tg.elab;
+            for (uint32_t e = rp[v]; e < rp[v + 1]; e++)
+                if (test_bit(dw, cl[e]) && (!elabelled || (el.empty() ? 0u : el[e]) == b)) return true;
+            return false;
+        };
         while (dirty) {
             uint64_t next = 0;
             for (uint32_t u = 0; u < k; u++) {
@@ -116,9 +148,16 @@ void build_plan(const Target &t, const HostGraph &p, int mode, bool labelled, ui
                     for (uint64_t bits = d[i]; bits; bits &= bits - 1) {
                         const uint32_t v = i * 64 + (uint32_t)__builtin_ctzll(bits);
                         for (uint64_t m = ws; m; m &= m - 1) {
-                            const uint64_t *dw = &D[(size_t)__builtin_ctzll(m) * W];
-                            bool sup = false;
-                            for (uint32_t e = tg.rp[v]; e < tg.rp[v + 1] && !sup; e++) sup = test_bit(dw, tg.col[e]);
+                            const uint32_t w = (uint32_t)__builtin_ctzll(m);
+                            const uint64_t *dw = &D[(size_t)w * W];
+                            bool sup;
+                            if (!directed) {
+                                sup = supported(v, dw, false, elabelled ? parc(u, w) : 0u);
+                            } else {
+                                sup = true;
+                                if ((outm[u] >> w) & 1) sup = supported(v, dw, false, elabelled ? parc(u, w) : 0u);
+                                if (sup && ((outm[w] >> u) & 1)) sup = supported(v, dw, true, elabelled ? parc(w, u) : 0u);
+                            }
                             if (!sup) {
                                 d[i] &= ~(1ull << (v & 63));
                                 next |= 1ull << u;
@@ -184,9 +223,9 @@ void build_plan(const Target &t, const HostGraph &p, int mode, bool labelled, ui
             if (best < 0) take = true;
             else if (wm != bwm) take = wm > bwm;
             else if (wn != bwn) take = wn > bwn;
-            else if (deg[u] != bdeg) take = deg[u] > bdeg;
+            else if (odeg[u] != bdeg) take = odeg[u] > bdeg;
             else take = use_si && dsize[u] < bdom;
-            if (take) { best = (int)u; bwm = wm; bwn = wn; bdeg = deg[u]; bdom = dsize[u]; }
+            if (take) { best = (int)u; bwm = wm; bwn = wn; bdeg = odeg[u]; bdom = dsize[u]; }
         }
         pl.order[len++] = (uint32_t)best;
         placed |= 1ull << best;
@@ -194,6 +233,14 @@ void build_plan(const Target &t, const HostGraph &p, int mode, bool labelled, ui
 
     uint32_t pos_of[KMAX];
     for (uint32_t i = 0; i < k; i++) pos_of[pl.order[i]] = i;
+    pl.pdir_out = pl.pboth = 0;
+    if (elabelled) {
+        // edge labels by position pair: lmat[a * k + b] = label of arc order[a] -> order[b]
+        pl.lmat.assign((size_t)k * k, LABEL_NONE);
+        for (uint32_t a = 0; a < k; a++)
+            for (uint32_t e = p.rp[pl.order[a]]; e < p.rp[pl.order[a] + 1]; e++)
+                pl.lmat[(size_t)a * k + pos_of[p.col[e]]] = p.elab.empty() ? 0u : p.elab[e];
+    }
     for (uint32_t i = 0; i < k; i++) {
         uint32_t u = pl.order[i];
         uint64_t earlier = 0;
@@ -205,6 +252,23 @@ void build_plan(const Target &t, const HostGraph &p, int mode, bool labelled, ui
         pl.back[i] = earlier ? (earlier & (earlier - 1)) : 0;
         pl.plabel[i] = lab[u];
         pl.pdeg[i] = deg[u];
+        pl.pindeg[i] = indeg[u];
+        // directed: which earlier positions have an arc into u, which an arc
+        // from u; the parent's candidates follow the arc parent -> u if there
+        // is one, else u -> parent
+        pl.bout[i] = pl.bin[i] = 0;
+        for (uint64_t m = earlier; m; m &= m - 1) {
+            const uint32_t j = (uint32_t)__builtin_ctzll(m), w = pl.order[j];
+            if ((outm[w] >> u) & 1) pl.bout[i] |= 1ull << j;
+            if ((outm[u] >> w) & 1) pl.bin[i] |= 1ull << j;
+        }
+        if (pl.parent[i] >= 0) {
+            const uint64_t pb = 1ull << pl.parent[i];
+            if (pl.bout[i] & pb) pl.pdir_out |= 1ull << i;
+            if ((pl.bout[i] & pb) && (pl.bin[i] & pb)) pl.pboth |= 1ull << i;
+            pl.bout[i] &= ~pb;
+            pl.bin[i] &= ~pb;
+        }
         pl.list_off[i] = pl.list_len[i] = 0;
         if (pl.parent[i] >= 0) continue;
         // parentless position: candidates are V_t (RI) or D(u) (RI-DS), here

@@ -338,6 +338,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
         pl->use_dom = use_dom ? 1u : 0u;
         pl->labelled = R.labelled;
         pl->empty = empty ? 1u : 0u;
+        pl->flags = 0;   // undirected, edge labels not compared
         if (empty) {
             pl->list_len[0] = 0;
             R.desc->nroot = 0;

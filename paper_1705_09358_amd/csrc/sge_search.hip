@@ -199,6 +199,20 @@ __device__ __forceinline__ bool adjacent(const InstDesc &d, unsigned W, unsigned
     return lo < b + deg && d.col[lo] == v;
 }
 
+// is there a target arc from the node whose out-row is [b, b+deg) to v; with
+// `check`, the arc's label must be `want` (rule 4 for general graphs)
+__device__ __forceinline__ bool arc_to(const InstDesc &d, unsigned b, unsigned deg, unsigned v, bool check,
+                                       unsigned want) {
+    unsigned lo = b, hi = b + deg;
+    while (lo < hi) {
+        const unsigned mid = (lo + hi) >> 1;
+        if (d.col[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo >= b + deg || d.col[lo] != v) return false;
+    return !check || (d.elab ? d.elab[lo] : 0u) == want;
+}
+
 template <int G, bool DENSE>
 __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
     extern __shared__ unsigned lds[];
@@ -269,8 +283,21 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
     auto open_frame = [&](unsigned pos, unsigned lo, unsigned hi) {
         int p = P->parent[pos];
         unsigned start, len;
-        if (p >= 0) { start = L.MB[p]; len = L.MD[p]; }
-        else { start = P->list_off[pos]; len = P->list_len[pos]; }
+        if (p >= 0) {
+            if ((P->flags & PLAN_DIRECTED) && !((P->pdir_out >> pos) & 1ull) && d.irp) {
+                // the pattern arc points at the parent: its image's in-neighbours
+                // (an undirected target's rows hold both directions)
+                const unsigned mp = L.M[p];
+                start = d.irp[mp];
+                len = d.irp[mp + 1] - start;
+            } else {
+                start = L.MB[p];
+                len = L.MD[p];
+            }
+        } else {
+            start = P->list_off[pos];
+            len = P->list_len[pos];
+        }
         unsigned e = (hi == FULL_RANGE || hi > len) ? len : hi;
         L.cur[pos] = lo;
         L.end[pos] = e;
@@ -674,10 +701,15 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
             const unsigned idx = c0 + gl;
             bool ok = idx < e;
             const bool has_parent = P->parent[lvl] >= 0;
+            const unsigned flags = P->flags;
+            // the pattern arc to the parent leaves the parent (pout), else it
+            // points at it and candidates come from the image's in-row
+            const bool pout = (P->pdir_out >> lvl) & 1ull;
+            const bool in_row = has_parent && (flags & PLAN_DIRECTED) && !pout && d.irp != nullptr;
             unsigned v = 0;
             NodeRec r{0, 0, 0, 0};
             if (ok) {
-                v = has_parent ? d.col[lb + idx] : d.lists[lb + idx];
+                v = has_parent ? (in_row ? d.icol[lb + idx] : d.col[lb + idx]) : d.lists[lb + idx];
                 r = d.node[v];
             }
             if (ok && d.bits) ok = (d.bits[(size_t)lvl * W + (v >> 6)] >> (v & 63)) & 1ull;
@@ -685,11 +717,38 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
             const unsigned pl = P->plabel[lvl];
             if (ok && pl != LABEL_ANY) ok = r.label == pl;
             if (ok) ok = r.deg >= P->pdeg[lvl];
-            unsigned long long bm = P->back[lvl];
-            while (bm) {
-                unsigned j = (unsigned)__builtin_ctzll(bm);
-                bm &= bm - 1;
-                if (ok) ok = adjacent(d, W, L.M[j], L.MB[j], L.MD[j], v);
+            if (!flags) {
+                unsigned long long bm = P->back[lvl];
+                while (bm) {
+                    unsigned j = (unsigned)__builtin_ctzll(bm);
+                    bm &= bm - 1;
+                    if (ok) ok = adjacent(d, W, L.M[j], L.MB[j], L.MD[j], v);
+                }
+            } else {
+                // general graphs: in-degree (r.pad), the label of the arc the
+                // candidate came over, the reverse arc to the parent, and every
+                // arc to an earlier position in its direction with its label
+                const uint32_t *lm = d.lmat;
+                const bool dir = flags & PLAN_DIRECTED;
+                if (ok) ok = r.pad >= P->pindeg[lvl];
+                if (ok && has_parent && lm) {
+                    const unsigned pp = (unsigned)P->parent[lvl];
+                    const unsigned tl = in_row ? (d.ielab ? d.ielab[lb + idx] : 0u) : (d.elab ? d.elab[lb + idx] : 0u);
+                    ok = tl == (pout ? lm[pp * k + lvl] : lm[lvl * k + pp]);
+                }
+                if (ok && dir && has_parent && ((P->pboth >> lvl) & 1ull)) {
+                    const unsigned pp = (unsigned)P->parent[lvl];
+                    ok = arc_to(d, r.begin, r.deg, L.M[pp], lm != nullptr, lm ? lm[lvl * k + pp] : 0u);
+                }
+                for (unsigned long long bm = P->bout[lvl]; bm && ok; bm &= bm - 1) {   // M[j] -> v
+                    const unsigned j = (unsigned)__builtin_ctzll(bm);
+                    ok = arc_to(d, L.MB[j], L.MD[j], v, lm != nullptr, lm ? lm[j * k + lvl] : 0u);
+                }
+                if (dir)
+                    for (unsigned long long bm = P->bin[lvl]; bm && ok; bm &= bm - 1) {   // v -> M[j]
+                        const unsigned j = (unsigned)__builtin_ctzll(bm);
+                        ok = arc_to(d, r.begin, r.deg, L.M[j], lm != nullptr, lm ? lm[lvl * k + j] : 0u);
+                    }
             }
             c_cands += min((unsigned)G, e - c0);
             unsigned long long acc = group_mask<G>(__ballot(ok), gbase);

@@ -252,6 +252,8 @@ sge_status sge_serve_submit(sge_ctx *c, const sge_job *job, uint64_t *ticket) {
     q->spec.mode = job->mode;
     q->spec.labelled = job->labelled != 0;
     q->bytes = instance_device_bytes(q->spec);
+    if (sv->device_plan && general_instance(q->spec))
+        return fail(c, SGE_E_INVAL, "the plan kernel covers undirected graphs without edge labels");
     std::lock_guard<std::mutex> lk(sv->mu);
     if (!sv->fatal.empty()) return fail(c, SGE_E_DEVICE, sv->fatal);
     if (sv->stopping) return fail(c, SGE_E_INVAL, "server is stopping");

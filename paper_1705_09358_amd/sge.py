@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "OK", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_OV
 
 EXPORTS = [
     "sge_create", "sge_destroy", "sge_last_error", "sge_load_target", "sge_unload_target", "sge_load_pattern",
-    "sge_unload_pattern", "sge_set_labelled", "sge_set_mode", "sge_set_state_cap", "sge_set_root_range",
+    "sge_unload_pattern", "sge_load_target_ex", "sge_load_pattern_ex", "sge_plan_host_ex", "sge_set_labelled", "sge_set_mode", "sge_set_state_cap", "sge_set_root_range",
     "sge_count", "sge_enumerate", "sge_batch_run", "sge_set_batch_policy", "sge_serve_start", "sge_serve_submit",
     "sge_serve_poll", "sge_serve_stop", "sge_plan_host", "sge_plan_device", "sge_set_plan_location", "sge_set_tuning",
     "sge_set_time_limit", "sge_last_launch_timing",
@@ -122,6 +122,10 @@ def lib() -> ctypes.CDLL:
             "sge_load_target": (I32, [P, U32, P, P, P, ctypes.POINTER(U32)]),
             "sge_unload_target": (I32, [P, U32]),
             "sge_load_pattern": (I32, [P, U32, P, P, P, ctypes.POINTER(U32)]),
+            "sge_load_target_ex": (I32, [P, U32, P, P, P, P, I32, ctypes.POINTER(U32)]),
+            "sge_load_pattern_ex": (I32, [P, U32, P, P, P, P, I32, ctypes.POINTER(U32)]),
+            "sge_plan_host_ex": (I32, [U32, P, P, P, P, I32, U32, P, P, P, P, I32, I32, I32, P, P, P,
+                                       ctypes.POINTER(I32)]),
             "sge_unload_pattern": (I32, [P, U32]),
             "sge_set_labelled": (I32, [P, I32]),
             "sge_set_mode": (I32, [P, I32]),
@@ -155,19 +159,28 @@ def _u32(a) -> np.ndarray:
     return a if a.size else np.zeros(1, dtype=np.uint32)
 
 
+def _elabels(g):
+    el = getattr(g, "elabels", None)
+    return None if el is None else _u32(el)
+
+
 def plan_host(pattern, target, mode: int, labelled: bool) -> dict:
     """The library's host plan (order, parents, domains as bool [k, n]); no device use."""
     k, n = pattern.n, target.n
     prp, pcol, plab = _u32(pattern.row_ptr), _u32(pattern.col), _u32(pattern.labels)
     trp, tcol, tlab = _u32(target.row_ptr), _u32(target.col), _u32(target.labels)
+    pel, tel = _elabels(pattern), _elabels(target)
     W = (n + 63) // 64
     order = np.zeros(max(k, 1), np.uint32)
     parent = np.zeros(max(k, 1), np.int32)
     dom = np.zeros(max(k * W, 1), np.uint64)
     empty = ctypes.c_int(0)
-    st = lib().sge_plan_host(k, prp.ctypes.data, pcol.ctypes.data, plab.ctypes.data, n, trp.ctypes.data,
-                             tcol.ctypes.data, tlab.ctypes.data, mode, int(labelled), order.ctypes.data,
-                             parent.ctypes.data, dom.ctypes.data, ctypes.byref(empty))
+    st = lib().sge_plan_host_ex(k, prp.ctypes.data, pcol.ctypes.data, plab.ctypes.data,
+                                None if pel is None else pel.ctypes.data, int(getattr(pattern, "directed", False)),
+                                n, trp.ctypes.data, tcol.ctypes.data, tlab.ctypes.data,
+                                None if tel is None else tel.ctypes.data, int(getattr(target, "directed", False)),
+                                mode, int(labelled), order.ctypes.data, parent.ctypes.data, dom.ctypes.data,
+                                ctypes.byref(empty))
     if st != OK:
         raise SgeError(st, "sge_plan_host rejected the input")
     domains = None
@@ -245,18 +258,21 @@ class Context:
         return m.decode() if m else ""
 
     def _load(self, fn, g, what):
+        """Graphs with edge labels (``elabels``) or ``directed`` set go through the _ex loaders."""
         rp, col = _u32(g.row_ptr), _u32(g.col)
         lab = None if g.labels is None else _u32(g.labels)
+        el = _elabels(g)
         out = ctypes.c_uint32()
         self._check(fn(self._h, g.n, rp.ctypes.data, col.ctypes.data, None if lab is None else lab.ctypes.data,
+                       None if el is None else el.ctypes.data, int(bool(getattr(g, "directed", False))),
                        ctypes.byref(out)), what)
         return out.value
 
     def load_target(self, g) -> int:
-        return self._load(self._L.sge_load_target, g, "sge_load_target")
+        return self._load(self._L.sge_load_target_ex, g, "sge_load_target")
 
     def load_pattern(self, g) -> int:
-        return self._load(self._L.sge_load_pattern, g, "sge_load_pattern")
+        return self._load(self._L.sge_load_pattern_ex, g, "sge_load_pattern")
 
     def unload_target(self, h: int):
         self._check(self._L.sge_unload_target(self._h, h), "sge_unload_target")

@@ -336,3 +336,85 @@ def c5_query(q: int, targets: list[Graph]) -> tuple[int, Graph, np.ndarray]:
     k = int(g.integers(4, 65))
     P, planted = induced_pattern(g, targets[t], walk_selection(g, targets[t], k))
     return t, P, planted
+
+
+# ---------------------------------------------------------------- directed workload
+# The general problem (directed graphs, edge labels) on contact-like data: the
+# 3000-node contact graph with each edge kept in both directions with
+# probability 1/4 and otherwise in one uniformly chosen direction, every arc
+# labelled with one of three bond types (uniform, drawn per arc).  100
+# patterns, selected by a random walk over the undirected graph, with every
+# arc among the selected nodes and its label: even j labelled (node and edge
+# labels), 8-24 nodes, RI; odd j unlabelled (directions only), 4-7 nodes,
+# RI-DS-SI-FC.
+C2D_COUNT = 100
+C2D_BOTH = 0.25
+C2D_EDGE_LABELS = 3
+_c2d_target = None
+
+
+def arcs_csr(n: int, a: np.ndarray, b: np.ndarray, lab: np.ndarray) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Out-edge CSR (sorted rows) of the arcs a[i] -> b[i] with labels lab[i] (no duplicates)."""
+    a = np.asarray(a, dtype=np.int64)
+    b = np.asarray(b, dtype=np.int64)
+    order = np.argsort(a * max(n, 1) + b, kind="stable")
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(row_ptr, a + 1, 1)
+    row_ptr = np.cumsum(row_ptr).astype(np.uint32)
+    return row_ptr, b[order].astype(np.uint32), np.asarray(lab, dtype=np.uint32)[order]
+
+
+def orient(g: np.random.Generator, T: Graph, p_both: float = C2D_BOTH, nelab: int = C2D_EDGE_LABELS) -> Graph:
+    """Directed, arc-labelled version of an undirected graph (see above)."""
+    src = np.repeat(np.arange(T.n, dtype=np.int64), np.diff(T.row_ptr.astype(np.int64)))
+    dst = T.col.astype(np.int64)
+    keep = src < dst
+    u, v = src[keep], dst[keep]
+    r = g.random(u.shape[0])
+    both = r < p_both
+    fwd = (~both) & (r < p_both + (1.0 - p_both) / 2)
+    bwd = ~(both | fwd)
+    a = np.concatenate([u[both], v[both], u[fwd], v[bwd]])
+    b = np.concatenate([v[both], u[both], v[fwd], u[bwd]])
+    lab = g.integers(0, nelab, size=a.shape[0])
+    rp, col, el = arcs_csr(T.n, a, b, lab)
+    return Graph(T.n, rp, col, T.labels, el, True)
+
+
+def induced_directed_pattern(g: np.random.Generator, T: Graph, sel: list[int]) -> tuple[Graph, np.ndarray]:
+    """Pattern on the selected nodes of a directed target with every arc among
+    them and its label; pattern ids are a seeded permutation of selection order."""
+    k = len(sel)
+    perm = g.permutation(k)
+    pos = {int(t): int(perm[j]) for j, t in enumerate(sel)}
+    a, b, lab = [], [], []
+    for t in sel:
+        t = int(t)
+        for e in range(int(T.row_ptr[t]), int(T.row_ptr[t + 1])):
+            w = int(T.col[e])
+            if w in pos:
+                a.append(pos[t])
+                b.append(pos[w])
+                lab.append(int(T.elabels[e]) if T.elabels is not None else 0)
+    rp, col, el = arcs_csr(k, np.array(a, dtype=np.int64), np.array(b, dtype=np.int64), np.array(lab))
+    planted = np.empty(k, dtype=np.uint32)
+    for j, t in enumerate(sel):
+        planted[perm[j]] = t
+    return Graph(k, rp, col, T.labels[planted].astype(np.uint32), el, True), planted
+
+
+def c2d_target() -> Graph:
+    global _c2d_target
+    if _c2d_target is None:
+        _c2d_target = orient(rng(6, 0, 0, 0), c2_target())
+    return _c2d_target
+
+
+def c2d_instance(j: int, attempt: int = 0) -> Instance:
+    T = c2d_target()
+    gp = rng(6, 1, j, attempt)
+    labelled = j % 2 == 0
+    k = int(gp.integers(8, 25)) if labelled else int(gp.integers(4, 8))
+    P, planted = induced_directed_pattern(gp, T, walk_selection(gp, c2_target(), k))
+    mode = MODE_RI if labelled else MODE_RIDS_SI_FC
+    return Instance(T, P, mode, labelled, planted, f"c2d/{j}/{attempt}")

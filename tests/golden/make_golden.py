@@ -6,7 +6,7 @@ instance whose search exceeds the cap is redrawn with the next `attempt`
 (the counterpart of the paper's per-instance time limit), and the attempt
 used is recorded.
 
-    python tests/golden/make_golden.py c1 c2 c4 [--procs 8]
+    python tests/golden/make_golden.py c1 c2 c4 c3 c5 c2d [--procs 8]
 """
 from __future__ import annotations
 
@@ -24,10 +24,11 @@ sys.path.insert(0, REPO)
 import oracle  # noqa: E402
 from paper_1705_09358_amd import synth  # noqa: E402
 
-CAPS = {"c1": 10 ** 8, "c2": 10 ** 8, "c4": 10 ** 8, "c3": 0, "c5": 10 ** 7}
+CAPS = {"c1": 10 ** 8, "c2": 10 ** 8, "c4": 10 ** 8, "c3": 0, "c5": 10 ** 7, "c2d": 10 ** 8}
 C5_SAMPLE = 48   # serving queries checked against the oracle (the first of the arrival stream)
-MAKERS = {"c1": synth.c1_instance, "c2": synth.c2_instance, "c4": synth.c4_instance}
-COUNTS = {"c1": synth.C1_COUNT, "c2": synth.C2_COUNT, "c4": synth.C4_COUNT, "c3": synth.C3_COUNT, "c5": C5_SAMPLE}
+MAKERS = {"c1": synth.c1_instance, "c2": synth.c2_instance, "c4": synth.c4_instance, "c2d": synth.c2d_instance}
+COUNTS = {"c1": synth.C1_COUNT, "c2": synth.C2_COUNT, "c4": synth.C4_COUNT, "c3": synth.C3_COUNT, "c5": C5_SAMPLE,
+          "c2d": synth.C2D_COUNT}
 
 
 def c3_shard(j):

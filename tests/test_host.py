@@ -142,3 +142,70 @@ def test_create_without_device_fails_cleanly():
     with pytest.raises(sge.SgeError) as e:
         sge.Context(0)
     assert e.value.code in (sge.E_DEVICE, sge.E_INVAL)
+
+
+# ---------------------------------------------------------------- directed graphs and edge labels
+
+@pytest.mark.parametrize("seed", range(40))
+def test_plan_matches_oracle_directed(orc, seed):
+    g = np.random.default_rng(15000 + seed)
+    n = int(g.integers(2, 14))
+    k = int(g.integers(1, min(7, n) + 1))
+    T = G.random_digraph(g, n, float(g.uniform(0.15, 0.6)), int(g.integers(1, 3)), int(g.integers(1, 4)))
+    P = G.random_digraph(g, k, float(g.uniform(0.2, 0.9)), int(g.integers(1, 3)), int(g.integers(1, 4)))
+    for mode in range(4):
+        for labelled in (False, True):
+            _cmp_plan(P, T, mode, labelled, orc)
+
+
+@pytest.mark.parametrize("seed", range(15))
+def test_plan_matches_oracle_mixed_and_undirected_edge_labels(orc, seed):
+    g = np.random.default_rng(16000 + seed)
+    T = G.random_undirected_elabelled(g, int(g.integers(3, 12)), 0.4, 2, 3)
+    P = G.random_digraph(g, int(g.integers(2, 6)), 0.5, 2, 3)
+    Pu = G.random_undirected_elabelled(g, int(g.integers(2, 6)), 0.6, 2, 3)
+    Td = G.random_digraph(g, int(g.integers(3, 12)), 0.3, 2, 3)
+    for mode in range(4):
+        for labelled in (False, True):
+            _cmp_plan(P, T, mode, labelled, orc)     # directed pattern, undirected target
+            _cmp_plan(Pu, T, mode, labelled, orc)    # undirected, edge labels
+            _cmp_plan(Pu, Td, mode, labelled, orc)   # undirected pattern, directed target
+
+
+def _plan_rc(P, T):
+    """Status of sge_plan_host_ex on raw arrays (no exception)."""
+    import ctypes
+    k, n = P.n, T.n
+    arr = [np.ascontiguousarray(np.asarray(x, dtype=np.uint32)) for x in
+           (P.row_ptr, P.col, P.labels, P.elabels if P.elabels is not None else [0],
+            T.row_ptr, T.col, T.labels, T.elabels if T.elabels is not None else [0])]
+    o = np.zeros(max(k, 1), np.uint32)
+    pa = np.zeros(max(k, 1), np.int32)
+    e = ctypes.c_int(0)
+    return sge.lib().sge_plan_host_ex(k, arr[0].ctypes.data, arr[1].ctypes.data, arr[2].ctypes.data,
+                                      arr[3].ctypes.data if P.elabels is not None else None, int(P.directed),
+                                      n, arr[4].ctypes.data, arr[5].ctypes.data, arr[6].ctypes.data,
+                                      arr[7].ctypes.data if T.elabels is not None else None, int(T.directed),
+                                      0, 1, o.ctypes.data, pa.ctypes.data, None, ctypes.byref(e))
+
+
+def test_validation_of_edge_labels_and_directions():
+    P = G.from_arcs(2, [(0, 1)])
+    good = G.from_arcs(3, [(0, 1), (1, 2)], None, [1, 2])
+    assert _plan_rc(P, good) == sge.OK
+    # a duplicate arc must carry one label
+    dup = G.Graph(3, np.array([0, 2, 2, 2], np.uint32), np.array([1, 1], np.uint32), np.zeros(3, np.uint32),
+                  np.array([4, 5], np.uint32), True)
+    assert _plan_rc(P, dup) == sge.E_INVAL
+    same = G.Graph(3, np.array([0, 2, 2, 2], np.uint32), np.array([1, 1], np.uint32), np.zeros(3, np.uint32),
+                   np.array([4, 4], np.uint32), True)
+    assert _plan_rc(P, same) == sge.OK
+    # an undirected edge carries one label in both directions
+    asym = G.from_arcs(2, [(0, 1), (1, 0)], None, [3, 4], directed=False)
+    assert _plan_rc(P, asym) == sge.E_INVAL
+    sym = G.from_arcs(2, [(0, 1), (1, 0)], None, [3, 3], directed=False)
+    assert _plan_rc(P, sym) == sge.OK
+    # undirected input must hold both directions; directed input need not
+    one_way = G.from_arcs(2, [(0, 1)], directed=False)
+    assert _plan_rc(P, one_way) == sge.E_INVAL
+    assert _plan_rc(P, G.from_arcs(2, [(0, 1)])) == sge.OK
