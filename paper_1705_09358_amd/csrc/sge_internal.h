@@ -248,6 +248,7 @@ struct LaunchCfg {
     uint32_t kmax = 0, nmax = 0, wmax = 0;
     int blocks = 0;           // 0 = fill the device
     int used_bitset = 1;
+    int general = 0;          // some plan is directed or compares edge labels (CSR kernel with those checks)
 };
 
 // Device-side work state of a context (allocated once, reused per launch).

@@ -112,6 +112,7 @@ static void launch_config(const sge_ctx *c, const std::vector<const InstanceSpec
         cfg.wmax = std::max(cfg.wmax, sp->t->W);
     }
     cfg.dense = dense ? 1 : 0;
+    for (const InstanceSpec *sp : specs) cfg.general |= general_instance(*sp) ? 1 : 0;
     if (c->lanes) {
         cfg.lanes = c->lanes;
     } else if (dense) {

@@ -213,7 +213,9 @@ __device__ __forceinline__ bool arc_to(const InstDesc &d, unsigned b, unsigned d
     return !check || (d.elab ? d.elab[lo] : 0u) == want;
 }
 
-template <int G, bool DENSE>
+// GEN: the launch holds plans with PLAN_DIRECTED or PLAN_EDGE_LABELS (CSR
+// only); other launches compile without those checks.
+template <int G, bool DENSE, bool GEN>
 __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
     extern __shared__ unsigned lds[];
     const int lane = threadIdx.x & 63;
@@ -284,7 +286,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
         int p = P->parent[pos];
         unsigned start, len;
         if (p >= 0) {
-            if ((P->flags & PLAN_DIRECTED) && !((P->pdir_out >> pos) & 1ull) && d.irp) {
+            if (GEN && (P->flags & PLAN_DIRECTED) && !((P->pdir_out >> pos) & 1ull) && d.irp) {
                 // the pattern arc points at the parent: its image's in-neighbours
                 // (an undirected target's rows hold both directions)
                 const unsigned mp = L.M[p];
@@ -701,11 +703,11 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
             const unsigned idx = c0 + gl;
             bool ok = idx < e;
             const bool has_parent = P->parent[lvl] >= 0;
-            const unsigned flags = P->flags;
+            const unsigned flags = GEN ? P->flags : 0u;
             // the pattern arc to the parent leaves the parent (pout), else it
             // points at it and candidates come from the image's in-row
-            const bool pout = (P->pdir_out >> lvl) & 1ull;
-            const bool in_row = has_parent && (flags & PLAN_DIRECTED) && !pout && d.irp != nullptr;
+            const bool pout = GEN && ((P->pdir_out >> lvl) & 1ull);
+            const bool in_row = GEN && has_parent && (flags & PLAN_DIRECTED) && !pout && d.irp != nullptr;
             unsigned v = 0;
             NodeRec r{0, 0, 0, 0};
             if (ok) {
@@ -717,14 +719,14 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
             const unsigned pl = P->plabel[lvl];
             if (ok && pl != LABEL_ANY) ok = r.label == pl;
             if (ok) ok = r.deg >= P->pdeg[lvl];
-            if (!flags) {
+            if (!GEN || !flags) {
                 unsigned long long bm = P->back[lvl];
                 while (bm) {
                     unsigned j = (unsigned)__builtin_ctzll(bm);
                     bm &= bm - 1;
                     if (ok) ok = adjacent(d, W, L.M[j], L.MB[j], L.MD[j], v);
                 }
-            } else {
+            } else if constexpr (GEN) {
                 // general graphs: in-degree (r.pad), the label of the arc the
                 // candidate came over, the reverse arc to the parent, and every
                 // arc to an earlier position in its direction with its label
@@ -946,20 +948,21 @@ __global__ void reset_kernel(Sched *s, InstCounters *c, unsigned ninst, QTask *q
     for (unsigned j = i; j < QUEUE_SLOTS; j += stride) q[j].seq = 2 * (j % QUEUE_GROUP_SLOTS);
 }
 
-template <int G, bool DENSE>
+template <int G, bool DENSE, bool GEN = false>
 hipError_t launch_g(SearchArgs args, int blocks, int threads, size_t lds, hipStream_t s, int num_cus) {
     if (blocks <= 0) {
         // resident blocks only (a persistent grid); the kernel trims it to
         // what the root chunks can keep busy before work is handed around
         int per_cu = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel<G, DENSE>, threads, lds);
+        hipError_t e =
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel<G, DENSE, GEN>, threads, lds);
         if (e != hipSuccess) return e;
         if (per_cu < 1) per_cu = 1;
         blocks = per_cu * num_cus;
     }
     args.min_blocks = (unsigned)std::max(1, 2 * num_cus);
     args.units_per_block = (unsigned)(threads / G);
-    hipLaunchKernelGGL((search_kernel<G, DENSE>), dim3(blocks), dim3(threads), lds, s, args);
+    hipLaunchKernelGGL((search_kernel<G, DENSE, GEN>), dim3(blocks), dim3(threads), lds, s, args);
     return hipGetLastError();
 }
 
@@ -1018,6 +1021,15 @@ hipError_t launch_search(const LaunchCfg &cfg, DevWork &w, uint32_t ninst, uint6
             case 16: return launch_g<16, true>(a, blocks, threads, lds, s, num_cus);
             case 32: return launch_g<32, true>(a, blocks, threads, lds, s, num_cus);
             case 64: return launch_g<64, true>(a, blocks, threads, lds, s, num_cus);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (cfg.general) {
+        switch (cfg.lanes) {
+            case 8: return launch_g<8, false, true>(a, blocks, threads, lds, s, num_cus);
+            case 16: return launch_g<16, false, true>(a, blocks, threads, lds, s, num_cus);
+            case 32: return launch_g<32, false, true>(a, blocks, threads, lds, s, num_cus);
+            case 64: return launch_g<64, false, true>(a, blocks, threads, lds, s, num_cus);
             default: return hipErrorInvalidValue;
         }
     }
