@@ -87,6 +87,21 @@ sge_status upload_target(sge_ctx *c, Target &t) {
         if ((st = up(t.d_elab, g.elab, "upload edge labels")) != SGE_OK) return st;
         if (g.directed && (st = up(t.d_ielab, g.ielab, "upload in-edge labels")) != SGE_OK) return st;
     }
+    // wide CSR (undirected targets): a candidate's id, row start, degree and
+    // label in one 16-byte load, so the search step needs no second
+    // dependent load for the node record
+    if (!g.directed && !g.col.empty()) {
+        std::vector<WideEntry> w(g.col.size());
+        for (size_t e = 0; e < g.col.size(); e++) {
+            const uint32_t x = g.col[e];
+            w[e] = WideEntry{x, g.rp[x], g.outdeg(x), t.dlab[x]};
+        }
+        hipError_t e2 = hipMalloc(&t.d_wcol, w.size() * sizeof(WideEntry));
+        if (e2 != hipSuccess) return hip_fail(c, e2, "hipMalloc(wide CSR)");
+        if ((e2 = hipMemcpy(t.d_wcol, w.data(), w.size() * sizeof(WideEntry), hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(c, e2, "upload wide CSR");
+        t.dev_bytes += w.size() * sizeof(WideEntry);
+    }
     // adjacency rows (undirected targets: the dense search and direct edge tests)
     if (g.n && g.n <= ADJ_BITSET_MAX_N && !g.directed) {
         std::vector<uint64_t> adj((size_t)g.n * t.W, 0);
@@ -117,7 +132,9 @@ void free_target(Target &t) {
     if (t.d_label_keys) (void)hipFree(t.d_label_keys);
     for (uint32_t *q : {t.d_irp, t.d_icol, t.d_elab, t.d_ielab})
         if (q) (void)hipFree(q);
+    if (t.d_wcol) (void)hipFree(t.d_wcol);
     t.d_irp = t.d_icol = t.d_elab = t.d_ielab = nullptr;
+    t.d_wcol = nullptr;
     t.d_col = nullptr;
     t.d_node = nullptr;
     t.d_adj = nullptr;

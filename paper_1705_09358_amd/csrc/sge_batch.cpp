@@ -39,31 +39,51 @@ sge_status sge_batch_run(sge_ctx *c, uint32_t njobs, const sge_job *jobs, sge_re
     double mp = 0, ms = 0;
     int policy = c->batch_policy;
     int saved_lanes = c->lanes;
+    const int saved_donate = c->donate;
     if (policy == 0) {
         auto it = c->batch_tune.find(njobs);   // repeated runs of one workload reuse the choice
         if (it == c->batch_tune.end()) {
-            // autotune: time each candidate launch shape on this batch; lanes:
-            // the automatic choice (0) and the two widest units
+            // autotune on this batch: the default shape first (root chunks,
+            // automatic width, default donation period), then one unit per job,
+            // the two widest units and a shorter donation period.  Exploring
+            // stops once a trial runs longer than TUNE_MAX_TRIAL_MS: long
+            // launches keep the best shape tried so far.
+            constexpr double TUNE_MAX_TRIAL_MS = 100.0;
             double best = 1e300;
-            std::pair<int, int> choice{2, 0};
-            const int policies[2] = {1, 2};
+            BatchTune choice{2, 0, saved_donate};
             const int lanes[3] = {0, 32, 64};
-            for (int p : policies)
-                for (int l : lanes) {
-                    if (saved_lanes && l != 0) continue;   // a width set by the caller is kept
-                    c->lanes = saved_lanes ? saved_lanes : l;
-                    sge_status st = run_instances(c, specs, out, mp, ms, true, p);
-                    c->lanes = saved_lanes;
-                    if (st != SGE_OK) return st;
-                    if (ms < best) { best = ms; choice = {p, l}; }
-                }
+            const int policies[2] = {2, 1};
+            const int periods[2] = {1, 16};   // 1 = the default period
+            bool stop = false;
+            for (int l : lanes)
+                for (int d : periods)
+                    for (int p : policies) {
+                        if (stop) continue;
+                        if (saved_lanes && l != 0) continue;      // a width set by the caller is kept
+                        if (saved_donate != 1 && d != 1) continue; // so is a donation setting
+                        c->lanes = saved_lanes ? saved_lanes : l;
+                        c->donate = saved_donate != 1 ? saved_donate : d;
+                        sge_status st = run_instances(c, specs, out, mp, ms, true, p);
+                        if (st == SGE_OK && ms <= TUNE_MAX_TRIAL_MS) {   // short launches: the better of two
+                            double ms2 = 0;
+                            st = run_instances(c, specs, out, mp, ms2, true, p);
+                            ms = std::min(ms, ms2);
+                        }
+                        c->lanes = saved_lanes;
+                        c->donate = saved_donate;
+                        if (st != SGE_OK) return st;
+                        if (ms < best) { best = ms; choice = BatchTune{p, l, saved_donate != 1 ? saved_donate : d}; }
+                        if (ms > TUNE_MAX_TRIAL_MS) stop = true;
+                    }
             it = c->batch_tune.emplace(njobs, choice).first;
         }
-        policy = it->second.first;
-        c->lanes = saved_lanes ? saved_lanes : it->second.second;
+        policy = it->second.policy;
+        c->lanes = saved_lanes ? saved_lanes : it->second.lanes;
+        c->donate = it->second.donate;
     }
     sge_status st = run_instances(c, specs, out, mp, ms, true, policy);
     c->lanes = saved_lanes;
+    c->donate = saved_donate;
     if (st != SGE_OK) return st;
     bool aborted = false, timed_out = false;
     for (uint32_t i = 0; i < njobs; i++) {

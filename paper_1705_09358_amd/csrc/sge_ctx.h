@@ -52,6 +52,11 @@ struct LaunchBufs {
     void release();
 };
 
+// A batch launch shape chosen by the autotuner.
+struct BatchTune {
+    int policy = 2, lanes = 0, donate = 1;
+};
+
 struct Server;
 struct ServerDeleter {
     void operator()(Server *s) const;
@@ -72,8 +77,8 @@ struct sge_ctx {
     uint32_t root_chunk = 0;
     int batch_policy = 0;
     int plan_where = -1;   // -1 automatic, 0 host, 1 device
-    // batch autotuner's choice by batch size: (policy, lanes); cleared when tuning changes
-    std::map<uint32_t, std::pair<int, int>> batch_tune;
+    // batch autotuner's choice by batch size; cleared when tuning changes
+    std::map<uint32_t, sge::BatchTune> batch_tune;
     int num_cus = 0;
     size_t lds_per_cu = 0;
     std::map<uint32_t, std::unique_ptr<sge::Target>> targets;

@@ -53,6 +53,11 @@ struct NodeRec {
     uint32_t begin, deg, label, pad;
 };
 
+// One entry of a wide CSR row: the neighbour and its node record fields.
+struct WideEntry {
+    uint32_t v, begin, deg, label;
+};
+
 // A target resident on the device, with the host copies the planner reads.
 struct Target {
     HostGraph g;
@@ -71,6 +76,7 @@ struct Target {
     NodeRec *d_node = nullptr;
     uint64_t *d_adj = nullptr;                   // n * W, or null when too large
     uint32_t *d_label_keys = nullptr;            // label_keys on the device
+    WideEntry *d_wcol = nullptr;                 // undirected: per CSR entry {neighbour, its row start, degree, label}
     uint32_t *d_irp = nullptr, *d_icol = nullptr;   // directed: in-edges
     uint32_t *d_elab = nullptr, *d_ielab = nullptr; // edge labels (out, in), or null
     uint64_t dev_bytes = 0;
@@ -150,6 +156,7 @@ struct DevPlan {
 struct InstDesc {
     const uint32_t *col;      // target CSR column array (out-edges)
     const NodeRec *node;      // target node records (pad = in-degree)
+    const WideEntry *wcol;    // undirected target: per CSR entry {neighbour, row start, degree, label}, or null
     const uint32_t *irp;      // directed target: in-edge row starts (n+1), else null
     const uint32_t *icol;     // directed target: in-edges, rows sorted by source, else null
     const uint32_t *elab;     // target edge labels per out entry, or null (all 0)

@@ -174,6 +174,7 @@ sge_status pack_instances(sge_ctx *c, const std::vector<const InstanceSpec *> &s
         d = InstDesc{};
         d.col = sp.t->d_col;
         d.node = sp.t->d_node;
+        d.wcol = sp.t->d_wcol;
         d.adj = sp.t->d_adj;
         d.plan = (const DevPlan *)(da + off_plans) + j;
         d.bits = with_bits ? (const uint64_t *)(da + pos_at[j]) : nullptr;
@@ -276,6 +277,7 @@ sge_status pack_host_planned(sge_ctx *c, const std::vector<const InstanceSpec *>
         d = InstDesc{};
         d.col = sp.t->d_col;
         d.node = sp.t->d_node;
+        d.wcol = sp.t->d_wcol;
         d.adj = sp.t->d_adj;
         d.irp = sp.t->d_irp;
         d.icol = sp.t->d_icol;

@@ -124,6 +124,16 @@ __device__ __forceinline__ void vm_drain() {
 
 __device__ __forceinline__ unsigned long long now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
 
+// Timing stamps shared by every wave: read first, so that only a stamp that
+// moves the value takes the atomic (thousands of waves start and exit at
+// nearly the same time, and atomics on one word serialise)
+__device__ __forceinline__ void stamp_min(unsigned long long *p, unsigned long long t) {
+    if (t < __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(p, t);
+}
+__device__ __forceinline__ void stamp_max(unsigned long long *p, unsigned long long t) {
+    if (t > __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(p, t);
+}
+
 template <int G>
 __device__ __forceinline__ unsigned long long group_mask(unsigned long long ballot, int gbase) {
     if constexpr (G == 64) return ballot;
@@ -239,9 +249,9 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
     // blocks beyond four units per root chunk (and the minimum) have nothing to start with
     const unsigned long long want = (4ull * nchunks + a.units_per_block - 1) / a.units_per_block;
     if (blockIdx.x >= max((unsigned long long)min(gridDim.x, a.min_blocks), want)) return;
-    if (threadIdx.x == 0) atomicMin(&S->t_start, now_ticks());
+    if (threadIdx.x == 0) stamp_min(&S->t_start, now_ticks());
     if (nchunks == 0) {   // no root candidate anywhere: nothing to search
-        if (lane == 0) atomicMax(&S->t_end, now_ticks());
+        if (lane == 0) stamp_max(&S->t_end, now_ticks());
         return;
     }
     const unsigned home = blockIdx.x % QUEUE_GROUPS;
@@ -257,6 +267,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
     unsigned since_donate = 0;     // steps since this unit's task began or it last gave work away
     unsigned iter = 0, backoff = 0, polls = 0;
     bool donate_hint = false;
+    unsigned cn_seen = 0;          // the root chunk counter as this wave last read it
     unsigned long long last_finish = 0;   // device clock of this wave's last task finish
     // every wave ends by the deadline, whatever the state of the search
     const unsigned long long deadline = a.limit_ticks ? now_ticks() + a.limit_ticks : ~0ull;
@@ -420,8 +431,9 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
                 const unsigned av = ld_rlx(&HG->avail);
                 const unsigned fr = ld_rlx(&HG->free);
                 if (av) src = home;
-                // give work away only once the roots are all claimed and the home group runs low
-                if (cn >= nchunks && av < 4 && fr > 32) flags |= 4;
+                // give work away when the home group runs low (and, per unit, once
+                // its own instance's root chunks are all claimed)
+                if (av < 4 && fr > 32) flags |= 4;
                 if (poll && !av && cn >= nchunks) {
                     for (unsigned g = 1; g < QUEUE_GROUPS && src == NO_GROUP; g++) {
                         const unsigned gg = (home + g) % QUEUE_GROUPS;
@@ -451,6 +463,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
             if (flags & 1) break;                    // time limit: every wave stops
             if ((flags & 2) && wave_idle) break;     // the search is complete
             donate_hint = a.donate && (flags & 4);
+            cn_seen = max(cn_seen, cn);
             if (poll && (src != NO_GROUP || cn < nchunks)) {
                 // ---------------------------------------- task acquisition, one unit at a time
                 for (int g = 0; g < 64 / G; g++) {
@@ -541,6 +554,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
                             }
                         }
                         ti = __shfl(lo, gbase);
+                        cn_seen = max(cn_seen, val + 1);   // the counter is past the chunk just claimed
                         const InstDesc &dd = a.inst[ti];
                         tlo = (val - a.chunk_prefix[ti]) * dd.chunk;
                         thi = min(tlo + dd.chunk, dd.nroot);
@@ -711,8 +725,14 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
             unsigned v = 0;
             NodeRec r{0, 0, 0, 0};
             if (ok) {
-                v = has_parent ? (in_row ? d.icol[lb + idx] : d.col[lb + idx]) : d.lists[lb + idx];
-                r = d.node[v];
+                if (!GEN && has_parent && d.wcol) {
+                    const WideEntry we = d.wcol[lb + idx];   // id, row start, degree, label in one load
+                    v = we.v;
+                    r = NodeRec{we.begin, we.deg, we.label, 0};
+                } else {
+                    v = has_parent ? (in_row ? d.icol[lb + idx] : d.col[lb + idx]) : d.lists[lb + idx];
+                    r = d.node[v];
+                }
             }
             if (ok && d.bits) ok = (d.bits[(size_t)lvl * W + (v >> 6)] >> (v & 63)) & 1ull;
             if (ok) ok = !used_test(L.used, v);
@@ -804,6 +824,8 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
         if (donate_hint && (iter & 7) == 0 && __ballot(since_donate >= a.donate_period) != 0) {
             for (int g = 0; g < 64 / G; g++) {
                 if (!((lane / G) == g && inst != NO_TASK && since_donate >= a.donate_period)) continue;
+                // while roots of this instance wait in the chunk counter, idle units take those
+                if (cn_seen < a.chunk_prefix[inst + 1]) continue;
                 // the shallowest frame with something to spare
                 unsigned f = base, kind = 0;
                 for (; f <= lvl; f++) {
@@ -929,8 +951,8 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
     }
     flush();
     if (lane == 0) {
-        if (last_finish) atomicMax(&S->t_work, last_finish);
-        atomicMax(&S->t_end, now_ticks());
+        if (last_finish) stamp_max(&S->t_work, last_finish);
+        stamp_max(&S->t_end, now_ticks());
     }
 }
 
