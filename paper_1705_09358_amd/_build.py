@@ -71,6 +71,21 @@ def build_sge() -> str:
     return SGE_SO
 
 
+CPU_WS_SO = os.path.join(LIBDIR, "libsge_cpuws.so")
+
+
+def build_cpu_baseline() -> str:
+    """The paper's parallel CPU search (a measurement baseline, host code only)."""
+    os.makedirs(LIBDIR, exist_ok=True)
+    srcs = [os.path.join(HERE, "cpu", "sge_cpu_ws.cpp"), os.path.join(CSRC, "sge_plan.cpp"),
+            os.path.join(CSRC, "sge_graph.cpp")]
+    inc = ["-I", INCLUDE, "-I", CSRC, "-I", os.path.join(ROCM, "include")]
+    _atomic_link(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-Wall", "-D__HIP_PLATFORM_AMD__", *inc, *srcs,
+                  "-lpthread"], CPU_WS_SO)
+    return CPU_WS_SO
+
+
 def build_all() -> None:
     build_synth()
     build_sge()
+    build_cpu_baseline()
