@@ -95,6 +95,13 @@ const char *sge_last_error(const sge_ctx *ctx);
  * wave exited (the kernel), ms[1] until the last task finished, ms[2] until
  * termination was detected. */
 sge_status sge_last_launch_timing(const sge_ctx *ctx, double *ms);
+/* Occupancy of the same launch (the parallel search of Section 3 as run on
+ * the device): *busy_unit_ms receives the sum over search units of the time
+ * each held a task, *units the number of units that entered the search loop
+ * (resident units the root chunks could keep busy).  busy_unit_ms / ms[0] is
+ * the mean number of busy units; divided by the launch's steps it is the
+ * mean duration of one step.  Both are 0 before any launch. */
+sge_status sge_last_launch_occupancy(const sge_ctx *ctx, double *busy_unit_ms, uint32_t *units);
 
 /* Load a target graph and keep it resident in device memory (CSR, per-node
  * records and, when the graph is small enough, a dense adjacency bitset).
@@ -226,6 +233,13 @@ sge_status sge_set_plan_location(sge_ctx *ctx, int where);
  * once per N of its steps), dense-bitset search (-1 = automatic, 0 = off,
  * 1 = on). */
 sge_status sge_set_tuning(sge_ctx *ctx, int lanes_per_unit, uint32_t root_chunk, int donate, int dense);
+
+/* Resident search blocks per compute unit (each block is four wavefronts of
+ * search units, the workers of Section 3): N >= 1 launches at most N per CU,
+ * 0 = automatic (as many as fit, or for batches the autotuner's choice).
+ * Searches whose work sits in few deep subtrees run faster with fewer
+ * resident waves; broad workloads with more.  SGE_E_INVAL outside 0..64. */
+sge_status sge_set_blocks_per_cu(sge_ctx *ctx, int blocks_per_cu);
 
 #ifdef __cplusplus
 }

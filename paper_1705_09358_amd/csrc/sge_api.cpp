@@ -240,6 +240,13 @@ sge_status sge_last_launch_timing(const sge_ctx *c, double *ms) {
     return SGE_OK;
 }
 
+sge_status sge_last_launch_occupancy(const sge_ctx *c, double *busy_unit_ms, uint32_t *units) {
+    if (!c || !busy_unit_ms || !units) return SGE_E_INVAL;
+    *busy_unit_ms = c->last_busy_ms;
+    *units = c->last_units;
+    return SGE_OK;
+}
+
 sge_status sge_load_target(sge_ctx *c, uint32_t n, const uint32_t *row_ptr, const uint32_t *col,
                            const uint32_t *labels, uint32_t *handle) {
     return sge_load_target_ex(c, n, row_ptr, col, labels, nullptr, 0, handle);
@@ -358,6 +365,14 @@ sge_status sge_set_tuning(sge_ctx *c, int lanes, uint32_t root_chunk, int donate
     c->root_chunk = root_chunk;
     c->donate = donate < 0 ? 0 : donate;
     c->dense = dense;
+    c->batch_tune.clear();
+    return SGE_OK;
+}
+
+sge_status sge_set_blocks_per_cu(sge_ctx *c, int blocks_per_cu) {
+    if (!c) return SGE_E_INVAL;
+    if (blocks_per_cu < 0 || blocks_per_cu > 64) return fail(c, SGE_E_INVAL, "blocks per CU must be 0..64");
+    c->per_cu = blocks_per_cu;
     c->batch_tune.clear();
     return SGE_OK;
 }

@@ -38,52 +38,65 @@ sge_status sge_batch_run(sge_ctx *c, uint32_t njobs, const sge_job *jobs, sge_re
     std::vector<InstanceOut> out;
     double mp = 0, ms = 0;
     int policy = c->batch_policy;
-    int saved_lanes = c->lanes;
-    const int saved_donate = c->donate;
+    const int saved_lanes = c->lanes, saved_donate = c->donate, saved_per_cu = c->per_cu;
     if (policy == 0) {
         auto it = c->batch_tune.find(njobs);   // repeated runs of one workload reuse the choice
         if (it == c->batch_tune.end()) {
-            // autotune on this batch: the default shape first (root chunks,
-            // automatic width, default donation period), then one unit per job,
-            // the two widest units and a shorter donation period.  Exploring
-            // stops once a trial runs longer than TUNE_MAX_TRIAL_MS: long
-            // launches keep the best shape tried so far.
+            // autotune on this batch, one knob at a time from the default shape
+            // (root chunks, automatic width, default donation period, all
+            // resident blocks): resident blocks per CU, then the unit width,
+            // then one unit per job, then a shorter donation period.  A knob
+            // the caller set is kept.  Short launches are timed twice (the
+            // better counts); exploring stops once a trial runs longer than
+            // TUNE_MAX_TRIAL_MS, and long launches keep the best shape so far.
             constexpr double TUNE_MAX_TRIAL_MS = 100.0;
             double best = 1e300;
-            BatchTune choice{2, 0, saved_donate};
-            const int lanes[3] = {0, 32, 64};
-            const int policies[2] = {2, 1};
-            const int periods[2] = {1, 16};   // 1 = the default period
+            BatchTune cur{2, saved_lanes, saved_donate, saved_per_cu};
             bool stop = false;
-            for (int l : lanes)
-                for (int d : periods)
-                    for (int p : policies) {
-                        if (stop) continue;
-                        if (saved_lanes && l != 0) continue;      // a width set by the caller is kept
-                        if (saved_donate != 1 && d != 1) continue; // so is a donation setting
-                        c->lanes = saved_lanes ? saved_lanes : l;
-                        c->donate = saved_donate != 1 ? saved_donate : d;
-                        sge_status st = run_instances(c, specs, out, mp, ms, true, p);
-                        if (st == SGE_OK && ms <= TUNE_MAX_TRIAL_MS) {   // short launches: the better of two
-                            double ms2 = 0;
-                            st = run_instances(c, specs, out, mp, ms2, true, p);
-                            ms = std::min(ms, ms2);
-                        }
-                        c->lanes = saved_lanes;
-                        c->donate = saved_donate;
-                        if (st != SGE_OK) return st;
-                        if (ms < best) { best = ms; choice = BatchTune{p, l, saved_donate != 1 ? saved_donate : d}; }
-                        if (ms > TUNE_MAX_TRIAL_MS) stop = true;
-                    }
-            it = c->batch_tune.emplace(njobs, choice).first;
+            auto trial = [&](const BatchTune &t) -> sge_status {
+                if (stop) return SGE_OK;
+                c->lanes = t.lanes;
+                c->donate = t.donate;
+                c->per_cu = t.per_cu;
+                sge_status st = run_instances(c, specs, out, mp, ms, true, t.policy);
+                if (st == SGE_OK && ms <= TUNE_MAX_TRIAL_MS) {
+                    double ms2 = 0;
+                    st = run_instances(c, specs, out, mp, ms2, true, t.policy);
+                    ms = std::min(ms, ms2);
+                }
+                c->lanes = saved_lanes;
+                c->donate = saved_donate;
+                c->per_cu = saved_per_cu;
+                if (st != SGE_OK) return st;
+                if (ms < best) {
+                    best = ms;
+                    cur = t;
+                }
+                if (ms > TUNE_MAX_TRIAL_MS) stop = true;
+                return SGE_OK;
+            };
+            sge_status st = trial(cur);
+            if (st == SGE_OK && saved_per_cu == 0)
+                for (int b : {1, 2})
+                    if (st == SGE_OK) st = trial(BatchTune{cur.policy, cur.lanes, cur.donate, b});
+            const BatchTune after_blocks = cur;
+            if (saved_lanes == 0)
+                for (int l : {32, 64})
+                    if (st == SGE_OK) st = trial(BatchTune{after_blocks.policy, l, after_blocks.donate, after_blocks.per_cu});
+            if (st == SGE_OK) st = trial(BatchTune{1, cur.lanes, cur.donate, cur.per_cu});
+            if (st == SGE_OK && saved_donate == 1) st = trial(BatchTune{cur.policy, cur.lanes, 16, cur.per_cu});
+            if (st != SGE_OK) return st;
+            it = c->batch_tune.emplace(njobs, cur).first;
         }
         policy = it->second.policy;
-        c->lanes = saved_lanes ? saved_lanes : it->second.lanes;
+        c->lanes = it->second.lanes;
         c->donate = it->second.donate;
+        c->per_cu = it->second.per_cu;
     }
     sge_status st = run_instances(c, specs, out, mp, ms, true, policy);
     c->lanes = saved_lanes;
     c->donate = saved_donate;
+    c->per_cu = saved_per_cu;
     if (st != SGE_OK) return st;
     bool aborted = false, timed_out = false;
     for (uint32_t i = 0; i < njobs; i++) {

@@ -54,7 +54,7 @@ struct LaunchBufs {
 
 // A batch launch shape chosen by the autotuner.
 struct BatchTune {
-    int policy = 2, lanes = 0, donate = 1;
+    int policy = 2, lanes = 0, donate = 1, per_cu = 0;
 };
 
 struct Server;
@@ -74,6 +74,7 @@ struct sge_ctx {
     uint64_t time_limit_ms = 120000;   // every search launch ends by this time
     uint32_t root_lo = 0, root_hi = 0xFFFFFFFFu;
     int lanes = 0, dense = -1, donate = 1;
+    int per_cu = 0;   // resident search blocks per compute unit (0 = as many as fit)
     uint32_t root_chunk = 0;
     int batch_policy = 0;
     int plan_where = -1;   // -1 automatic, 0 host, 1 device
@@ -87,6 +88,8 @@ struct sge_ctx {
     sge::LaunchBufs bufs;
     sge::DevBuf d_rows;
     double last_ms[3] = {0, 0, 0};   // last launch: kernel, until the last task finished, until done was set
+    double last_busy_ms = 0;         // last launch: unit-milliseconds spent holding tasks
+    uint32_t last_units = 0;         // last launch: units that entered the search loop
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::unique_ptr<sge::Server, sge::ServerDeleter> server;
     std::mutex serve_mu;
@@ -120,6 +123,8 @@ struct Pack {
     bool device_plan = true;           // planned by the plan kernel (else uploaded host plans)
     uint64_t units = 1;                // approximate search units (root chunk sizing)
     double ms_work = 0, ms_done = 0;   // filled by read_pack
+    double busy_ms = 0;                // unit-milliseconds holding tasks (read_pack)
+    uint32_t units_run = 0;            // units that entered the search loop (read_pack)
     bool bad_task = false;             // filled by read_pack: the work queue delivered an invalid task
     size_t blob = 0, upload = 0, arena = 0, ctr_bytes = 0;
     size_t off_req = 0, off_pref = 0;  // in the blob

@@ -227,12 +227,14 @@ struct Sched {
     unsigned int done;         // set once every task is finished
     unsigned int abort;        // set when the launch's time limit is reached
     unsigned int bad;          // set when a dequeued task fails validation (never expected)
-    unsigned int p1[29];
+    unsigned int units;        // units that entered the search loop
+    unsigned int p1[28];
     unsigned long long t_start;  // earliest block start (s_memrealtime, 100 MHz)
     unsigned long long t_end;    // latest wave exit
     unsigned long long t_work;   // latest task finish
     unsigned long long t_done;   // when `done` was set
-    unsigned long long p2[12];
+    unsigned long long t_busy;   // sum over units of the ticks each held a task
+    unsigned long long p2[11];
     QGroup grp[QUEUE_GROUPS];
 };
 
@@ -254,6 +256,7 @@ struct LaunchCfg {
     int donate = 1;            // 0 off, 1 default period, N > 1: period of N steps
     uint32_t kmax = 0, nmax = 0, wmax = 0;
     int blocks = 0;           // 0 = fill the device
+    int per_cu = 0;           // with blocks = 0: at most this many resident blocks per CU (0 = all that fit)
     int used_bitset = 1;
     int general = 0;          // some plan is directed or compares edge labels (CSR kernel with those checks)
 };

@@ -122,8 +122,10 @@ static void launch_config(const sge_ctx *c, const std::vector<const InstanceSpec
         cfg.lanes = auto_lanes(specs);
     }
     cfg.donate = c->donate;
-    // approximate number of search units (for the root chunk size)
-    pk.units = (uint64_t)c->num_cus * 4 * 8 * (64 / cfg.lanes) / 2;
+    cfg.per_cu = c->per_cu;
+    // approximate number of search units (for the root chunk size): up to
+    // four blocks of four waves per CU
+    pk.units = (uint64_t)c->num_cus * (c->per_cu > 0 ? std::min(c->per_cu, 4) : 4) * 4 * (64 / cfg.lanes);
 }
 
 sge_status pack_instances(sge_ctx *c, const std::vector<const InstanceSpec *> &specs, bool dense, int policy,
@@ -335,6 +337,8 @@ void read_pack(const sge_ctx *c, Pack &pk, const LaunchBufs &bufs, const std::ve
     ms_search = since(hs->t_end);
     pk.ms_work = since(hs->t_work);
     pk.ms_done = since(hs->t_done);
+    pk.busy_ms = (double)hs->t_busy / 1e5;
+    pk.units_run = hs->units;
     pk.bad_task = hs->bad != 0;
     for (uint32_t j = 0; j < pk.m; j++) {
         InstanceOut &o = *out[j];
@@ -465,6 +469,8 @@ sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std
     c->last_ms[0] = ms_search;
     c->last_ms[1] = pk.ms_work;
     c->last_ms[2] = pk.ms_done;
+    c->last_busy_ms = pk.busy_ms;
+    c->last_units = pk.units_run;
     if (pk.bad_task) return fail(c, SGE_E_DEVICE, "the work queue delivered an invalid task; counters are unreliable");
     if (op[0]->timed_out) c->err = "search stopped at the time limit; counters are partial";
     return SGE_OK;

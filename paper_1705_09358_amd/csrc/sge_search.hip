@@ -196,7 +196,61 @@ __device__ __forceinline__ DenseLds carve_dense(unsigned *base, unsigned kmax, u
 __device__ __forceinline__ bool used_test(const unsigned *used, unsigned v) { return (used[v >> 5] >> (v & 31)) & 1u; }
 
 // is v a target neighbour of node a (row [b, b+deg))
-__device__ __forceinline__ bool adjacent(const InstDesc &d, unsigned W, unsigned a, unsigned b, unsigned deg,
+// Device memory in the global address space.  Pointers that the kernel loads
+// from memory (an instance's descriptor and plan) are generic to the compiler,
+// and a generic (flat) access waits on both the vector-memory and the LDS
+// counters, which would hold a step's LDS work behind its outstanding loads.
+template <class T>
+using gp = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gp<T> glob(T *p) {
+    return (gp<T>)p;
+}
+
+// 16-byte records in one load
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ NodeRec ld_node(gp<const NodeRec> p) {
+    const u32x4 x = *(gp<const u32x4>)p;
+    return NodeRec{x.x, x.y, x.z, x.w};
+}
+__device__ __forceinline__ WideEntry ld_wide(gp<const WideEntry> p) {
+    const u32x4 x = *(gp<const u32x4>)p;
+    return WideEntry{x.x, x.y, x.z, x.w};
+}
+
+// An instance's search descriptor with global-address-space pointers.
+struct GDesc {
+    gp<const uint32_t> col;
+    gp<const NodeRec> node;
+    gp<const WideEntry> wcol;
+    gp<const uint32_t> irp, icol, elab, ielab, lmat;
+    gp<const uint64_t> adj;
+    gp<const DevPlan> plan;
+    gp<const uint64_t> bits;
+    gp<const uint32_t> lists;
+    gp<uint32_t> rows;
+    unsigned long long cap_rows;
+};
+__device__ __forceinline__ GDesc gdesc(gp<const InstDesc> s) {
+    GDesc d;
+    d.col = glob(s->col);
+    d.node = glob(s->node);
+    d.wcol = glob(s->wcol);
+    d.irp = glob(s->irp);
+    d.icol = glob(s->icol);
+    d.elab = glob(s->elab);
+    d.ielab = glob(s->ielab);
+    d.lmat = glob(s->lmat);
+    d.adj = glob(s->adj);
+    d.plan = glob(s->plan);
+    d.bits = glob(s->bits);
+    d.lists = glob(s->lists);
+    d.rows = glob(s->rows);
+    d.cap_rows = s->cap_rows;
+    return d;
+}
+
+__device__ __forceinline__ bool adjacent(const GDesc &d, unsigned W, unsigned a, unsigned b, unsigned deg,
                                          unsigned v) {
     if (d.adj) return (d.adj[(size_t)a * W + (v >> 6)] >> (v & 63)) & 1ull;
     unsigned lo = b, hi = b + deg;
@@ -211,7 +265,7 @@ __device__ __forceinline__ bool adjacent(const InstDesc &d, unsigned W, unsigned
 
 // is there a target arc from the node whose out-row is [b, b+deg) to v; with
 // `check`, the arc's label must be `want` (rule 4 for general graphs)
-__device__ __forceinline__ bool arc_to(const InstDesc &d, unsigned b, unsigned deg, unsigned v, bool check,
+__device__ __forceinline__ bool arc_to(const GDesc &d, unsigned b, unsigned deg, unsigned v, bool check,
                                        unsigned want) {
     unsigned lo = b, hi = b + deg;
     while (lo < hi) {
@@ -226,7 +280,7 @@ __device__ __forceinline__ bool arc_to(const InstDesc &d, unsigned b, unsigned d
 // GEN: the launch holds plans with PLAN_DIRECTED or PLAN_EDGE_LABELS (CSR
 // only); other launches compile without those checks.
 template <int G, bool DENSE, bool GEN>
-__global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
+__global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a) {
     extern __shared__ unsigned lds[];
     const int lane = threadIdx.x & 63;
     const int gl = lane & (G - 1);
@@ -256,12 +310,13 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
     }
     const unsigned home = blockIdx.x % QUEUE_GROUPS;
     QGroup *HG = &S->grp[home];
+    if (lane == 0) fadd(&S->units, 64u / G);
     const bool checker = blockIdx.x == 0 && threadIdx.x < 64;   // the wave that detects termination
 
     // unit state (identical in the G lanes of a unit)
     unsigned inst = NO_TASK, cinst = NO_TASK, lvl = 0, base = 0, etop = 0, k = 0, W = 0;
-    InstDesc d{};
-    const DevPlan *P = nullptr;
+    GDesc d{};
+    gp<const DevPlan> P = nullptr;
     unsigned long long c_states = 0, c_matches = 0, c_cands = 0, c_steals = 0, c_steps = 0;
     bool roots_done = false;
     unsigned since_donate = 0;     // steps since this unit's task began or it last gave work away
@@ -269,6 +324,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
     bool donate_hint = false;
     unsigned cn_seen = 0;          // the root chunk counter as this wave last read it
     unsigned long long last_finish = 0;   // device clock of this wave's last task finish
+    unsigned long long busy_ticks = 0, task_t0 = 0;   // this unit's time holding tasks
     // every wave ends by the deadline, whatever the state of the search
     const unsigned long long deadline = a.limit_ticks ? now_ticks() + a.limit_ticks : ~0ull;
 
@@ -383,7 +439,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
                         const unsigned v = w * 64 + (unsigned)__builtin_ctzll(y);
                         unsigned long long slot = atomicAdd(&a.ctr[inst].row_next, 1ull);
                         if (slot < d.cap_rows) {
-                            uint32_t *row = d.rows + slot * k;
+                            gp<uint32_t> row = d.rows + slot * k;
                             for (unsigned i = 0; i + 1 < k; i++) row[P->order[i]] = D.M[i];
                             row[P->order[k - 1]] = v;
                         }
@@ -407,6 +463,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
         // that task's `created` count to complete
         if (gl == 0) fadd(&HG->finished, 1);
         last_finish = now_ticks();
+        busy_ticks += last_finish - task_t0;
         inst = NO_TASK;
         etop = 0;
     };
@@ -509,22 +566,44 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
                         bool bad = ti >= a.ninst || tkind > TK_WINDOW || tne > TASK_ENTRIES;
                         unsigned tn = 0;
                         if (!bad) {
-                            const DevPlan *tp = a.inst[ti].plan;
+                            gp<const DevPlan> tp = glob(glob(a.inst)[ti].plan);
                             tn = tp->n;
                             bad = tL >= tp->k || (tkind == TK_WINDOW && (tlo > thi || thi > tp->W));
                         }
                         if (!bad) {
+                            // every payload load is issued before any is used
+                            // (prefix length below 64, at most TASK_ENTRIES entries)
                             bool bl = false;
-                            for (unsigned i = gl; i < tL; i += G) {
-                                const unsigned v = ld_rlx(&q->M[i]);
-                                bl |= v >= tn;
-                                L.M[i] = v;
+                            constexpr unsigned PR = 64 / G, ER = (TASK_ENTRIES + G - 1) / G;
+                            unsigned mv[PR], evv[DENSE ? 1 : ER];
+#pragma unroll
+                            for (unsigned r = 0; r < PR; r++) {
+                                const unsigned i = r * G + gl;
+                                mv[r] = i < tL ? ld_rlx(&q->M[i]) : 0u;
                             }
                             if constexpr (!DENSE) {
-                                for (unsigned i = gl; i < tne; i += G) {
-                                    const unsigned v = ld_rlx(&q->ent[i]);
-                                    bl |= v >= tn;
-                                    L.ev[i] = v;
+#pragma unroll
+                                for (unsigned r = 0; r < ER; r++) {
+                                    const unsigned i = r * G + gl;
+                                    evv[r] = i < tne ? ld_rlx(&q->ent[i]) : 0u;
+                                }
+                            }
+#pragma unroll
+                            for (unsigned r = 0; r < PR; r++) {
+                                const unsigned i = r * G + gl;
+                                if (i < tL) {
+                                    bl |= mv[r] >= tn;
+                                    L.M[i] = mv[r];
+                                }
+                            }
+                            if constexpr (!DENSE) {
+#pragma unroll
+                                for (unsigned r = 0; r < ER; r++) {
+                                    const unsigned i = r * G + gl;
+                                    if (i < tne) {
+                                        bl |= evv[r] >= tn;
+                                        L.ev[i] = evv[r];
+                                    }
                                 }
                             }
                             bad = group_mask<G>(__ballot(bl), gbase) != 0;
@@ -555,20 +634,21 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
                         }
                         ti = __shfl(lo, gbase);
                         cn_seen = max(cn_seen, val + 1);   // the counter is past the chunk just claimed
-                        const InstDesc &dd = a.inst[ti];
-                        tlo = (val - a.chunk_prefix[ti]) * dd.chunk;
-                        thi = min(tlo + dd.chunk, dd.nroot);
+                        gp<const InstDesc> dd = glob(a.inst) + ti;
+                        tlo = (val - a.chunk_prefix[ti]) * dd->chunk;
+                        thi = min(tlo + dd->chunk, dd->nroot);
                     }
                     // start the task
                     if (ti != cinst) {
                         flush();
                         cinst = ti;
-                        d = a.inst[ti];
+                        d = gdesc(glob(a.inst) + ti);
                         P = d.plan;
                         k = P->k;
                         W = P->W;
                     }
                     inst = ti;
+                    task_t0 = now_ticks();
                     since_donate = 0;
                     if (kind == 1) c_steals++;
                     etop = 0;
@@ -585,7 +665,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
                             // a root chunk: its list entries are the accepted candidates of position 0
                             for (unsigned w = gl; w < W; w += G) D.cand[w] = 0ull;
                             WAVE_SYNC();
-                            const uint32_t *lst = d.lists + P->list_off[0] + tlo;
+                            gp<const uint32_t> lst = d.lists + P->list_off[0] + tlo;
                             const unsigned cnt = thi - tlo;
                             for (unsigned i = gl; i < cnt; i += G) {
                                 const unsigned v = lst[i];
@@ -621,7 +701,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
                     } else {
                         for (unsigned i = gl; i < tL; i += G) {
                             unsigned v = L.M[i];
-                            NodeRec r = d.node[v];
+                            NodeRec r = ld_node(d.node + v);
                             L.MB[i] = r.begin;
                             L.MD[i] = r.deg;
                             mark(v);
@@ -633,7 +713,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
                             open_frame(tL, 0, 0);
                             for (unsigned i = gl; i < tne; i += G) {
                                 const unsigned v = L.ev[i];
-                                const NodeRec r = d.node[v];
+                                const NodeRec r = ld_node(d.node + v);
                                 L.ebg[i] = r.begin;
                                 L.edg[i] = r.deg;
                             }
@@ -647,7 +727,9 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
         }
         if (__ballot(inst != NO_TASK) == 0) {
             // the whole wave is idle: back off before polling again
-            backoff = backoff < 8 ? backoff + 1 : 8;
+            // (the terminating wave keeps its polls frequent)
+            const unsigned bmax = checker ? 4u : 32u;
+            backoff = backoff < bmax ? backoff + 1 : bmax;
             for (unsigned z = 0; z < backoff; z++) __builtin_amdgcn_s_sleep(32);
             continue;
         }
@@ -726,12 +808,12 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
             NodeRec r{0, 0, 0, 0};
             if (ok) {
                 if (!GEN && has_parent && d.wcol) {
-                    const WideEntry we = d.wcol[lb + idx];   // id, row start, degree, label in one load
+                    const WideEntry we = ld_wide(d.wcol + lb + idx);   // id, row start, degree, label in one load
                     v = we.v;
                     r = NodeRec{we.begin, we.deg, we.label, 0};
                 } else {
                     v = has_parent ? (in_row ? d.icol[lb + idx] : d.col[lb + idx]) : d.lists[lb + idx];
-                    r = d.node[v];
+                    r = ld_node(d.node + v);
                 }
             }
             if (ok && d.bits) ok = (d.bits[(size_t)lvl * W + (v >> 6)] >> (v & 63)) & 1ull;
@@ -739,7 +821,30 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
             const unsigned pl = P->plabel[lvl];
             if (ok && pl != LABEL_ANY) ok = r.label == pl;
             if (ok) ok = r.deg >= P->pdeg[lvl];
-            if (!GEN || !flags) {
+            if ((!GEN || !flags) && d.adj) {
+                // one adjacency-row word per back edge, four rows per round with
+                // their loads issued together (every lane's address is in range:
+                // v is a node id, 0 for an idle lane)
+                unsigned long long bm = P->back[lvl];
+                const size_t wv = v >> 6;
+                unsigned long long hit = ~0ull;
+                while (bm) {
+                    const unsigned j0 = (unsigned)__builtin_ctzll(bm);
+                    bm &= bm - 1;
+                    const unsigned j1 = bm ? (unsigned)__builtin_ctzll(bm) : j0;
+                    bm &= bm ? bm - 1 : 0ull;
+                    const unsigned j2 = bm ? (unsigned)__builtin_ctzll(bm) : j0;
+                    bm &= bm ? bm - 1 : 0ull;
+                    const unsigned j3 = bm ? (unsigned)__builtin_ctzll(bm) : j0;
+                    bm &= bm ? bm - 1 : 0ull;
+                    const unsigned long long a0 = d.adj[(size_t)L.M[j0] * W + wv];
+                    const unsigned long long a1 = d.adj[(size_t)L.M[j1] * W + wv];
+                    const unsigned long long a2 = d.adj[(size_t)L.M[j2] * W + wv];
+                    const unsigned long long a3 = d.adj[(size_t)L.M[j3] * W + wv];
+                    hit &= a0 & a1 & a2 & a3;
+                }
+                ok = ok && ((hit >> (v & 63)) & 1ull);
+            } else if (!GEN || !flags) {
                 unsigned long long bm = P->back[lvl];
                 while (bm) {
                     unsigned j = (unsigned)__builtin_ctzll(bm);
@@ -750,7 +855,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
                 // general graphs: in-degree (r.pad), the label of the arc the
                 // candidate came over, the reverse arc to the parent, and every
                 // arc to an earlier position in its direction with its label
-                const uint32_t *lm = d.lmat;
+                gp<const uint32_t> lm = d.lmat;
                 const bool dir = flags & PLAN_DIRECTED;
                 if (ok) ok = r.pad >= P->pindeg[lvl];
                 if (ok && has_parent && lm) {
@@ -781,7 +886,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
                 if (d.rows && ok) {
                     unsigned long long slot = atomicAdd(&a.ctr[inst].row_next, 1ull);
                     if (slot < d.cap_rows) {
-                        uint32_t *row = d.rows + slot * k;
+                        gp<uint32_t> row = d.rows + slot * k;
                         for (unsigned i = 0; i + 1 < k; i++) row[P->order[i]] = L.M[i];
                         row[P->order[k - 1]] = v;
                     }
@@ -950,6 +1055,7 @@ __global__ void __launch_bounds__(256) search_kernel(SearchArgs a) {
         }
     }
     flush();
+    if (gl == 0) fadd64(&S->t_busy, busy_ticks);
     if (lane == 0) {
         if (last_finish) stamp_max(&S->t_work, last_finish);
         stamp_max(&S->t_end, now_ticks());
@@ -971,7 +1077,7 @@ __global__ void reset_kernel(Sched *s, InstCounters *c, unsigned ninst, QTask *q
 }
 
 template <int G, bool DENSE, bool GEN = false>
-hipError_t launch_g(SearchArgs args, int blocks, int threads, size_t lds, hipStream_t s, int num_cus) {
+hipError_t launch_g(SearchArgs args, int blocks, int per_cu_cap, int threads, size_t lds, hipStream_t s, int num_cus) {
     if (blocks <= 0) {
         // resident blocks only (a persistent grid); the kernel trims it to
         // what the root chunks can keep busy before work is handed around
@@ -979,6 +1085,7 @@ hipError_t launch_g(SearchArgs args, int blocks, int threads, size_t lds, hipStr
         hipError_t e =
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, search_kernel<G, DENSE, GEN>, threads, lds);
         if (e != hipSuccess) return e;
+        if (per_cu_cap > 0) per_cu = std::min(per_cu, per_cu_cap);
         if (per_cu < 1) per_cu = 1;
         blocks = per_cu * num_cus;
     }
@@ -1039,27 +1146,27 @@ hipError_t launch_search(const LaunchCfg &cfg, DevWork &w, uint32_t ninst, uint6
     int blocks = cfg.blocks;
     if (cfg.dense) {
         switch (cfg.lanes) {
-            case 8: return launch_g<8, true>(a, blocks, threads, lds, s, num_cus);
-            case 16: return launch_g<16, true>(a, blocks, threads, lds, s, num_cus);
-            case 32: return launch_g<32, true>(a, blocks, threads, lds, s, num_cus);
-            case 64: return launch_g<64, true>(a, blocks, threads, lds, s, num_cus);
+            case 8: return launch_g<8, true>(a, blocks, cfg.per_cu, threads, lds, s, num_cus);
+            case 16: return launch_g<16, true>(a, blocks, cfg.per_cu, threads, lds, s, num_cus);
+            case 32: return launch_g<32, true>(a, blocks, cfg.per_cu, threads, lds, s, num_cus);
+            case 64: return launch_g<64, true>(a, blocks, cfg.per_cu, threads, lds, s, num_cus);
             default: return hipErrorInvalidValue;
         }
     }
     if (cfg.general) {
         switch (cfg.lanes) {
-            case 8: return launch_g<8, false, true>(a, blocks, threads, lds, s, num_cus);
-            case 16: return launch_g<16, false, true>(a, blocks, threads, lds, s, num_cus);
-            case 32: return launch_g<32, false, true>(a, blocks, threads, lds, s, num_cus);
-            case 64: return launch_g<64, false, true>(a, blocks, threads, lds, s, num_cus);
+            case 8: return launch_g<8, false, true>(a, blocks, cfg.per_cu, threads, lds, s, num_cus);
+            case 16: return launch_g<16, false, true>(a, blocks, cfg.per_cu, threads, lds, s, num_cus);
+            case 32: return launch_g<32, false, true>(a, blocks, cfg.per_cu, threads, lds, s, num_cus);
+            case 64: return launch_g<64, false, true>(a, blocks, cfg.per_cu, threads, lds, s, num_cus);
             default: return hipErrorInvalidValue;
         }
     }
     switch (cfg.lanes) {
-        case 8: return launch_g<8, false>(a, blocks, threads, lds, s, num_cus);
-        case 16: return launch_g<16, false>(a, blocks, threads, lds, s, num_cus);
-        case 32: return launch_g<32, false>(a, blocks, threads, lds, s, num_cus);
-        case 64: return launch_g<64, false>(a, blocks, threads, lds, s, num_cus);
+        case 8: return launch_g<8, false>(a, blocks, cfg.per_cu, threads, lds, s, num_cus);
+        case 16: return launch_g<16, false>(a, blocks, cfg.per_cu, threads, lds, s, num_cus);
+        case 32: return launch_g<32, false>(a, blocks, cfg.per_cu, threads, lds, s, num_cus);
+        case 64: return launch_g<64, false>(a, blocks, cfg.per_cu, threads, lds, s, num_cus);
         default: return hipErrorInvalidValue;
     }
 }

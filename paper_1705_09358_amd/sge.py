@@ -27,7 +27,7 @@ EXPORTS = [
     "sge_unload_pattern", "sge_load_target_ex", "sge_load_pattern_ex", "sge_plan_host_ex", "sge_set_labelled", "sge_set_mode", "sge_set_state_cap", "sge_set_root_range",
     "sge_count", "sge_enumerate", "sge_batch_run", "sge_set_batch_policy", "sge_serve_start", "sge_serve_submit",
     "sge_serve_poll", "sge_serve_stop", "sge_plan_host", "sge_plan_device", "sge_set_plan_location", "sge_set_tuning",
-    "sge_set_time_limit", "sge_last_launch_timing",
+    "sge_set_time_limit", "sge_last_launch_timing", "sge_last_launch_occupancy", "sge_set_blocks_per_cu",
 ]
 
 
@@ -145,6 +145,8 @@ def lib() -> ctypes.CDLL:
             "sge_set_plan_location": (I32, [P, I32]),
             "sge_set_time_limit": (I32, [P, U64]),
             "sge_last_launch_timing": (I32, [P, P]),
+            "sge_last_launch_occupancy": (I32, [P, P, P]),
+            "sge_set_blocks_per_cu": (I32, [P, I32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -234,6 +236,15 @@ class Context:
         self._check(self._L.sge_last_launch_timing(self._h, ctypes.addressof(out)), "sge_last_launch_timing")
         return tuple(out)
 
+    def last_launch_occupancy(self):
+        """(sum over units of the ms each held a task, units that entered the
+        search loop) for the last launch."""
+        busy = ctypes.c_double()
+        units = ctypes.c_uint32()
+        self._check(self._L.sge_last_launch_occupancy(self._h, ctypes.byref(busy), ctypes.byref(units)),
+                    "sge_last_launch_occupancy")
+        return busy.value, units.value
+
     def plan_device(self, target: int, pattern: int, k: int, n: int, mode: int, labelled: bool) -> dict:
         """The plan the device computes before a search: order, parents, the
         number of root candidates and (RI-DS modes) domains as bool [k, n]."""
@@ -298,6 +309,10 @@ class Context:
     def set_tuning(self, lanes: int = 0, root_chunk: int = 0, donate: int = 1, dense: int = -1):
         """donate: 0 off, 1 default period, N > 1 at most one donation per N steps of a unit."""
         self._check(self._L.sge_set_tuning(self._h, lanes, root_chunk, int(donate), dense), "sge_set_tuning")
+
+    def set_blocks_per_cu(self, blocks_per_cu: int):
+        """Resident search blocks per CU: 0 automatic, N >= 1 at most N."""
+        self._check(self._L.sge_set_blocks_per_cu(self._h, int(blocks_per_cu)), "sge_set_blocks_per_cu")
 
     def set_plan_location(self, where: int):
         """-1 automatic, 0 host, 1 device."""

@@ -155,3 +155,34 @@ def test_batch_state_cap(ctx):
             assert (r.matches, r.states) == (w["matches"], w["states"])
         else:
             assert r.states > cap
+
+
+@pytest.mark.parametrize("per_cu", [1, 2, 3])
+def test_blocks_per_cu_cap(ctx, per_cu):
+    # the same counts with fewer resident blocks; the launch keeps to the cap
+    import torch
+    man = manifest("c2")
+    _note(f"batch c2 with at most {per_cu} blocks per CU")
+    insts = [synth.c2_instance(r["j"], r["attempt"]) for r in man["instances"]]
+    jobs = load_jobs(ctx, insts)
+    ctx.set_blocks_per_cu(per_cu)
+    ctx.set_batch_policy(2)
+    try:
+        st, res = ctx.batch_run(jobs)
+        busy, units = ctx.last_launch_occupancy()
+    finally:
+        ctx.set_blocks_per_cu(0)
+        ctx.set_batch_policy(0)
+        unload(ctx, jobs)
+    assert st == sge.OK
+    assert [(r.matches, r.states) for r in res] == [(w["matches"], w["states"]) for w in man["instances"]]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert 1 <= units <= per_cu * cus * 256 // 8     # at most 256 threads of 8-lane units per block
+    assert busy > 0
+
+
+def test_blocks_per_cu_rejects_out_of_range(ctx):
+    for bad in (-1, 65):
+        with pytest.raises(sge.SgeError) as e:
+            ctx.set_blocks_per_cu(bad)
+        assert e.value.code == sge.E_INVAL

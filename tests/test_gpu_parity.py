@@ -166,6 +166,19 @@ def test_schedule_independence(run, ctx, lanes, chunk, donate):
         ctx.set_tuning(0, 0, 1)
 
 
+def test_launch_occupancy(run, ctx):
+    # busy unit-time is positive and bounded by units x kernel time; steps take
+    # a positive mean time
+    inst = synth.c2_instance(5)
+    res, _ = check(run, inst.pattern, inst.target, 0, True, "c2/5 occupancy")
+    kernel_ms, work_ms, done_ms = ctx.last_launch_timing()
+    busy, units = ctx.last_launch_occupancy()
+    assert units >= 1 and busy > 0
+    assert 0 < work_ms <= kernel_ms and 0 < done_ms <= kernel_ms
+    assert busy <= units * kernel_ms * 1.001 + 1e-3, (busy, units, kernel_ms)
+    assert res.steps >= 1
+
+
 def test_empty_pattern(run):
     res, rows = run.run(G.edgeless(0), G.complete(4), 0, False)
     assert res.matches == 1 and res.states == 0
