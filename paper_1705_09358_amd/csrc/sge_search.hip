@@ -148,6 +148,9 @@ __device__ __forceinline__ unsigned group_sum(unsigned x) {
 
 // Per-unit LDS arrays of the CSR variant.
 struct UnitLds {
+    unsigned long long *pback;    // the current instance's plan by position: back-edge masks,
+    int *pp;                      //   parent positions,
+    unsigned *plab, *pdeg;        //   labels and degrees (copied when the unit changes instance)
     unsigned *M, *MB, *MD;        // mapping by position, row start and degree of M[i]
     unsigned *cur, *end, *lb;     // frame: next candidate index, list length, list start
     unsigned *eb, *dn;            // frame: first stack entry, entries given away from the bottom
@@ -157,7 +160,11 @@ struct UnitLds {
 
 __device__ __forceinline__ UnitLds carve(unsigned *base, unsigned kmax, unsigned E) {
     UnitLds u;
-    u.M = base;
+    u.pback = reinterpret_cast<unsigned long long *>(base);   // the unit's area starts 8-byte aligned
+    u.pp = reinterpret_cast<int *>(base + 2 * kmax);
+    u.plab = base + 3 * kmax;
+    u.pdeg = base + 4 * kmax;
+    u.M = base + 5 * kmax;
     u.MB = u.M + kmax;
     u.MD = u.MB + kmax;
     u.cur = u.MD + kmax;
@@ -281,7 +288,7 @@ __device__ __forceinline__ bool arc_to(const GDesc &d, unsigned b, unsigned deg,
 // only); other launches compile without those checks.
 template <int G, bool DENSE, bool GEN>
 __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a) {
-    extern __shared__ unsigned lds[];
+    extern __shared__ __attribute__((aligned(16))) unsigned lds[];
     const int lane = threadIdx.x & 63;
     const int gl = lane & (G - 1);
     const int gbase = lane & ~(G - 1);
@@ -350,7 +357,7 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
     };
     // open the frame of position `pos` (lists follow the mapped parent)
     auto open_frame = [&](unsigned pos, unsigned lo, unsigned hi) {
-        int p = P->parent[pos];
+        int p = L.pp[pos];
         unsigned start, len;
         if (p >= 0) {
             if (GEN && (P->flags & PLAN_DIRECTED) && !((P->pdir_out >> pos) & 1ull) && d.irp) {
@@ -646,6 +653,15 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                         P = d.plan;
                         k = P->k;
                         W = P->W;
+                        if constexpr (!DENSE) {
+                            for (unsigned i = gl; i < k; i += G) {
+                                L.pback[i] = P->back[i];
+                                L.pp[i] = P->parent[i];
+                                L.plab[i] = P->plabel[i];
+                                L.pdeg[i] = P->pdeg[i];
+                            }
+                            WAVE_SYNC();
+                        }
                     }
                     inst = ti;
                     task_t0 = now_ticks();
@@ -798,7 +814,7 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
             const unsigned c0 = L.cur[lvl], e = L.end[lvl], lb = L.lb[lvl];
             const unsigned idx = c0 + gl;
             bool ok = idx < e;
-            const bool has_parent = P->parent[lvl] >= 0;
+            const bool has_parent = L.pp[lvl] >= 0;
             const unsigned flags = GEN ? P->flags : 0u;
             // the pattern arc to the parent leaves the parent (pout), else it
             // points at it and candidates come from the image's in-row
@@ -818,14 +834,14 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
             }
             if (ok && d.bits) ok = (d.bits[(size_t)lvl * W + (v >> 6)] >> (v & 63)) & 1ull;
             if (ok) ok = !used_test(L.used, v);
-            const unsigned pl = P->plabel[lvl];
+            const unsigned pl = L.plab[lvl];
             if (ok && pl != LABEL_ANY) ok = r.label == pl;
-            if (ok) ok = r.deg >= P->pdeg[lvl];
+            if (ok) ok = r.deg >= L.pdeg[lvl];
             if ((!GEN || !flags) && d.adj) {
                 // one adjacency-row word per back edge, four rows per round with
                 // their loads issued together (every lane's address is in range:
                 // v is a node id, 0 for an idle lane)
-                unsigned long long bm = P->back[lvl];
+                unsigned long long bm = L.pback[lvl];
                 const size_t wv = v >> 6;
                 unsigned long long hit = ~0ull;
                 while (bm) {
@@ -845,7 +861,7 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                 }
                 ok = ok && ((hit >> (v & 63)) & 1ull);
             } else if (!GEN || !flags) {
-                unsigned long long bm = P->back[lvl];
+                unsigned long long bm = L.pback[lvl];
                 while (bm) {
                     unsigned j = (unsigned)__builtin_ctzll(bm);
                     bm &= bm - 1;
@@ -859,12 +875,12 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                 const bool dir = flags & PLAN_DIRECTED;
                 if (ok) ok = r.pad >= P->pindeg[lvl];
                 if (ok && has_parent && lm) {
-                    const unsigned pp = (unsigned)P->parent[lvl];
+                    const unsigned pp = (unsigned)L.pp[lvl];
                     const unsigned tl = in_row ? (d.ielab ? d.ielab[lb + idx] : 0u) : (d.elab ? d.elab[lb + idx] : 0u);
                     ok = tl == (pout ? lm[pp * k + lvl] : lm[lvl * k + pp]);
                 }
                 if (ok && dir && has_parent && ((P->pboth >> lvl) & 1ull)) {
-                    const unsigned pp = (unsigned)P->parent[lvl];
+                    const unsigned pp = (unsigned)L.pp[lvl];
                     ok = arc_to(d, r.begin, r.deg, L.M[pp], lm != nullptr, lm ? lm[lvl * k + pp] : 0u);
                 }
                 for (unsigned long long bm = P->bout[lvl]; bm && ok; bm &= bm - 1) {   // M[j] -> v
@@ -1099,7 +1115,7 @@ unsigned unit_words(const LaunchCfg &cfg) {
     if (cfg.dense) return 3 * even(cfg.kmax) + 2 * cfg.kmax * cfg.wmax + 2 * cfg.wmax;
     unsigned E = cfg.kmax + cfg.lanes;
     unsigned UW = (cfg.nmax + 31) / 32;
-    return 8 * cfg.kmax + 3 * E + UW;
+    return even(13 * cfg.kmax + 3 * E + UW);   // even: every unit's area starts 8-byte aligned
 }
 
 // Largest block (256, 128 or 64 threads) whose units fit in 64 KiB of LDS.
