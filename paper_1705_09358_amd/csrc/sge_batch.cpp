@@ -40,7 +40,21 @@ sge_status sge_batch_run(sge_ctx *c, uint32_t njobs, const sge_job *jobs, sge_re
     int policy = c->batch_policy;
     const int saved_lanes = c->lanes, saved_donate = c->donate, saved_per_cu = c->per_cu;
     if (policy == 0) {
-        auto it = c->batch_tune.find(njobs);   // repeated runs of one workload reuse the choice
+        // repeated runs of one batch (the same jobs) reuse the choice
+        uint64_t key = 1469598103934665603ull;   // FNV-1a over the job list
+        auto mix = [&](uint64_t v) {
+            for (int b = 0; b < 8; b++) {
+                key ^= (v >> (8 * b)) & 0xFFu;
+                key *= 1099511628211ull;
+            }
+        };
+        mix(njobs);
+        for (uint32_t i = 0; i < njobs; i++) {
+            mix(jobs[i].target);
+            mix(jobs[i].pattern);
+            mix(((uint64_t)(uint32_t)jobs[i].mode << 1) | (jobs[i].labelled ? 1u : 0u));
+        }
+        auto it = c->batch_tune.find(key);
         if (it == c->batch_tune.end()) {
             // autotune on this batch, one knob at a time from the default shape
             // (root chunks, automatic width, default donation period, all
@@ -86,7 +100,8 @@ sge_status sge_batch_run(sge_ctx *c, uint32_t njobs, const sge_job *jobs, sge_re
             if (st == SGE_OK) st = trial(BatchTune{1, cur.lanes, cur.donate, cur.per_cu});
             if (st == SGE_OK && saved_donate == 1) st = trial(BatchTune{cur.policy, cur.lanes, 16, cur.per_cu});
             if (st != SGE_OK) return st;
-            it = c->batch_tune.emplace(njobs, cur).first;
+            if (c->batch_tune.size() >= 256) c->batch_tune.clear();
+            it = c->batch_tune.emplace(key, cur).first;
         }
         policy = it->second.policy;
         c->lanes = it->second.lanes;

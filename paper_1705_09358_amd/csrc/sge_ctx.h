@@ -78,8 +78,8 @@ struct sge_ctx {
     uint32_t root_chunk = 0;
     int batch_policy = 0;
     int plan_where = -1;   // -1 automatic, 0 host, 1 device
-    // batch autotuner's choice by batch size; cleared when tuning changes
-    std::map<uint32_t, sge::BatchTune> batch_tune;
+    // batch autotuner's choice by job list (hash); cleared when tuning changes
+    std::map<uint64_t, sge::BatchTune> batch_tune;
     int num_cus = 0;
     size_t lds_per_cu = 0;
     std::map<uint32_t, std::unique_ptr<sge::Target>> targets;
