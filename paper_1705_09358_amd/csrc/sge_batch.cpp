@@ -1,7 +1,8 @@
 // Batching: many (pattern, target) jobs of uneven size in one persistent
 // launch captured in a HIP graph, with an autotuner that picks between one
-// search unit per job and root chunks of every job shared by all units, and
-// the unit width (lanes per unit).
+// search unit per job and root chunks of every job shared by all units, the
+// unit width (lanes per unit), the resident blocks per CU and the donation
+// period.
 #include <algorithm>
 #include <chrono>
 
@@ -60,9 +61,11 @@ sge_status sge_batch_run(sge_ctx *c, uint32_t njobs, const sge_job *jobs, sge_re
             // (root chunks, automatic width, default donation period, all
             // resident blocks): resident blocks per CU, then the unit width,
             // then one unit per job, then a shorter donation period.  A knob
-            // the caller set is kept.  Short launches are timed twice (the
-            // better counts); exploring stops once a trial runs longer than
-            // TUNE_MAX_TRIAL_MS, and long launches keep the best shape so far.
+            // the caller set is kept.  A short launch is run once more and then
+            // timed three times (the median counts: launch times of the same
+            // shape vary by several percent); exploring stops once a trial runs
+            // longer than TUNE_MAX_TRIAL_MS, and long launches keep the best
+            // shape so far.
             constexpr double TUNE_MAX_TRIAL_MS = 100.0;
             double best = 1e300;
             BatchTune cur{2, saved_lanes, saved_donate, saved_per_cu};
@@ -74,9 +77,10 @@ sge_status sge_batch_run(sge_ctx *c, uint32_t njobs, const sge_job *jobs, sge_re
                 c->per_cu = t.per_cu;
                 sge_status st = run_instances(c, specs, out, mp, ms, true, t.policy);
                 if (st == SGE_OK && ms <= TUNE_MAX_TRIAL_MS) {
-                    double ms2 = 0;
-                    st = run_instances(c, specs, out, mp, ms2, true, t.policy);
-                    ms = std::min(ms, ms2);
+                    double r[3] = {0, 0, 0};
+                    for (int i = 0; i < 3 && st == SGE_OK; i++) st = run_instances(c, specs, out, mp, r[i], true, t.policy);
+                    std::sort(r, r + 3);
+                    ms = r[1];
                 }
                 c->lanes = saved_lanes;
                 c->donate = saved_donate;
