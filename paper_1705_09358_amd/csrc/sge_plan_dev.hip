@@ -37,8 +37,23 @@ constexpr int PLAN_THREADS_SMALL_BATCH = 1024;
 constexpr int PLAN_THREADS_LARGE_BATCH = 256;
 constexpr uint32_t PLAN_LARGE_BATCH = 256;
 
+// Device memory in the global address space: the pointers a plan request
+// holds are loaded from memory, so the compiler would treat them as generic
+// and emit flat accesses, whose completion counter is shared with LDS.
+template <class T>
+using gp = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gp<T> glob(T *p) {
+    return (gp<T>)p;
+}
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ NodeRec ld_node(gp<const NodeRec> p) {
+    const u32x4 x = *(gp<const u32x4>)p;
+    return NodeRec{x.x, x.y, x.z, x.w};
+}
+
 // dense id of a raw label among the target's increasing label keys
-__device__ uint32_t label_id(const uint32_t *keys, uint32_t nl, uint32_t raw) {
+__device__ uint32_t label_id(gp<const uint32_t> keys, uint32_t nl, uint32_t raw) {
     uint32_t lo = 0, hi = nl;
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
@@ -89,20 +104,23 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
     __shared__ int s_empty;
 
     const PlanIn R = reqs[blockIdx.x];
-    const DevPattern *pat = R.pat;
+    const gp<const DevPattern> pat = glob(R.pat);
+    const gp<InstDesc> desc = glob(R.desc);
+    const gp<uint64_t> pos_bits = glob(R.pos_bits);
+    const gp<uint32_t> lists = glob(R.lists);
     const uint32_t k = pat->k, n = R.n, W = R.W;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const bool use_dom = R.mode != SGE_RI;
     const bool use_si = R.mode == SGE_RIDS_SI || R.mode == SGE_RIDS_SI_FC;
-    const NodeRec *node = R.desc->node;
-    const uint32_t *col = R.desc->col;
-    uint64_t *D = R.dom;
-    DevPlan *pl = R.plan;
+    const gp<const NodeRec> node = glob(desc->node);
+    const gp<const uint32_t> col = glob(desc->col);
+    const gp<uint64_t> D = glob(R.dom);
+    const gp<DevPlan> pl = glob(R.plan);
 
     if ((uint32_t)tid < k) {
         s_nb[tid] = pat->nb[tid];
         s_deg[tid] = pat->deg[tid];
-        s_lab[tid] = R.labelled ? label_id(R.label_keys, R.nlabels, pat->label[tid]) : LABEL_ANY;
+        s_lab[tid] = R.labelled ? label_id(glob(R.label_keys), R.nlabels, pat->label[tid]) : LABEL_ANY;
     }
     if (tid == 0) s_empty = 0;
     __syncthreads();
@@ -118,7 +136,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
         const bool valid = v < n;
         uint32_t vl = LABEL_NONE, vd = 0;
         if (valid) {
-            const NodeRec r = node[v];
+            const NodeRec r = ld_node(node + v);
             vl = r.label;
             vd = r.deg;
         }
@@ -139,11 +157,11 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
     // batch are built side by side (LDS, or device scratch for very wide
     // rows), then every pattern neighbour of a batch member is revised
     // against the supports of its neighbours in the batch.
-    if (use_dom) {
-        const bool in_lds = W <= lds_words;
-        unsigned long long *Sb = in_lds ? s_support : reinterpret_cast<unsigned long long *>(R.support);
-        const uint32_t B = in_lds ? max(1u, min(k, lds_words / max(W, 1u))) : 1u;
-        const uint64_t *adj = R.desc->adj;
+    // the support sets live in LDS or, for very wide rows, in device memory;
+    // the rounds are instantiated for each, so every access has its own
+    // address space
+    auto arc_consistency = [&](auto Sb, const uint32_t B) {
+        const gp<const uint64_t> adj = glob(desc->adj);
         unsigned long long dirty = 0;
         for (uint32_t u = 0; u < k; u++)
             if (s_nb[u]) dirty |= 1ull << u;
@@ -170,7 +188,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
                 for (uint32_t it = wave; it < nbat * W; it += PLAN_WAVES) {
                     const uint32_t j = it / W, i = it - j * W;
                     const uint64_t word = D[(size_t)s_bw[j] * W + i];
-                    unsigned long long *Sj = Sb + (size_t)j * W;
+                    const auto Sj = Sb + (size_t)j * W;
                     if (R.rows) {
                         // adjacency rows, ORed word by word (lane t: word t)
                         for (uint32_t t0 = 0; t0 < W; t0 += 64) {
@@ -190,23 +208,23 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
                                            adj[(size_t)x2 * W + t] | adj[(size_t)x3 * W + t];
                                 }
                             }
-                            if (acc) atomicOr(&Sj[t], acc);
+                            if (acc) __hip_atomic_fetch_or(&Sj[t], acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                         }
                     } else if ((word >> lane) & 1ull) {
                         // the member's neighbour list, four entries per round
-                        const NodeRec r = node[i * 64 + lane];
+                        const NodeRec r = ld_node(node + i * 64 + lane);
                         uint32_t e = r.begin;
                         const uint32_t end = r.begin + r.deg;
                         for (; e + 4 <= end; e += 4) {
                             const uint32_t y0 = col[e], y1 = col[e + 1], y2 = col[e + 2], y3 = col[e + 3];
-                            atomicOr(&Sj[y0 >> 6], 1ull << (y0 & 63));
-                            atomicOr(&Sj[y1 >> 6], 1ull << (y1 & 63));
-                            atomicOr(&Sj[y2 >> 6], 1ull << (y2 & 63));
-                            atomicOr(&Sj[y3 >> 6], 1ull << (y3 & 63));
+                            __hip_atomic_fetch_or(&Sj[y0 >> 6], 1ull << (y0 & 63), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                            __hip_atomic_fetch_or(&Sj[y1 >> 6], 1ull << (y1 & 63), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                            __hip_atomic_fetch_or(&Sj[y2 >> 6], 1ull << (y2 & 63), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                            __hip_atomic_fetch_or(&Sj[y3 >> 6], 1ull << (y3 & 63), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                         }
                         for (; e < end; e++) {
                             const uint32_t y = col[e];
-                            atomicOr(&Sj[y >> 6], 1ull << (y & 63));
+                            __hip_atomic_fetch_or(&Sj[y >> 6], 1ull << (y & 63), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                         }
                     }
                 }
@@ -233,6 +251,12 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
             dirty = s_next;
             __syncthreads();
         }
+    };
+    if (use_dom) {
+        if (W <= lds_words)
+            arc_consistency(s_support, max(1u, min(k, lds_words / max(W, 1u))));
+        else
+            arc_consistency(glob(reinterpret_cast<unsigned long long *>(R.support)), 1u);
     }
 
     // domain sizes; an empty domain leaves nothing to search
@@ -272,7 +296,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
                     }
                 }
                 if (t != 0xFFFFFFFFu && (uint32_t)lane < k && (uint32_t)lane != u) {
-                    uint64_t *pw = &D[(size_t)lane * W + (t >> 6)];
+                    const gp<uint64_t> pw = &D[(size_t)lane * W + (t >> 6)];
                     const uint64_t bit = 1ull << (t & 63);
                     const uint64_t x = *pw;
                     if (x & bit) {
@@ -341,7 +365,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
         pl->flags = 0;   // undirected, edge labels not compared
         if (empty) {
             pl->list_len[0] = 0;
-            R.desc->nroot = 0;
+            desc->nroot = 0;
         }
     }
     if (empty) return;
@@ -369,13 +393,13 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
     __syncthreads();
 
     // per-position bitsets: the domain (RI-DS) or the label/degree set (RI)
-    if (R.pos_bits) {
+    if (pos_bits) {
         const uint32_t kw = k * W;
         for (uint32_t idx = tid; idx < kw; idx += PLAN_THREADS) {
             const uint32_t i = idx / W, t = idx - i * W;
             uint64_t x = D[(size_t)s_order[i] * W + t];
             if (i == 0) x &= range_mask(t, R.root_lo, R.root_hi);
-            R.pos_bits[idx] = x;
+            pos_bits[idx] = x;
         }
     }
     // candidate lists of the parentless positions, in increasing node order
@@ -383,7 +407,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
         uint32_t off = 0;
         for (uint32_t i = 0; i < k; i++) {
             if (s_par[i] >= 0) continue;
-            const uint64_t *row = &D[(size_t)s_order[i] * W];
+            const gp<const uint64_t> row = &D[(size_t)s_order[i] * W];
             const uint32_t start = off;
             for (uint32_t i0 = 0; i0 < W; i0 += 64) {
                 const uint32_t t = i0 + lane;
@@ -397,7 +421,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
                 }
                 uint32_t o = off + s - c;
                 for (unsigned long long y = x; y; y &= y - 1, o++)
-                    if (o < R.list_cap) R.lists[o] = t * 64 + (uint32_t)__builtin_ctzll(y);
+                    if (o < R.list_cap) lists[o] = t * 64 + (uint32_t)__builtin_ctzll(y);
                 off += __shfl(s, 63);
             }
             // lists fit by construction (list_cap); should they not, keep
@@ -406,7 +430,7 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
             if (lane == 0) {
                 pl->list_off[i] = start;
                 pl->list_len[i] = len;
-                if (i == 0) R.desc->nroot = len;
+                if (i == 0) desc->nroot = len;
             }
         }
     }
