@@ -279,7 +279,7 @@ struct DevWork {
 hipError_t launch_plan(const PlanIn *reqs, uint32_t m, uint32_t wmax, uint32_t kmax, InstDesc *desc, unsigned *chunk_prefix,
                        int policy, uint32_t root_chunk, uint64_t units, hipStream_t s);
 // LDS words of the plan kernel's support buffer (larger W uses PlanIn::support).
-constexpr uint32_t PLAN_LDS_WORDS = 4096;
+constexpr uint32_t PLAN_LDS_WORDS = 2048;
 
 // Launch one persistent search over `ninst` planned instances.  The grid is
 // the resident maximum (or cfg.blocks); blocks beyond what the root chunks
