@@ -356,7 +356,8 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
         return __shfl(f, gbase) != 0;
     };
     // open the frame of position `pos` (lists follow the mapped parent)
-    auto open_frame = [&](unsigned pos, unsigned lo, unsigned hi) {
+    // returns the frame's end and list start (also kept in LDS)
+    auto open_frame = [&](unsigned pos, unsigned lo, unsigned hi) -> uint2 {
         int p = L.pp[pos];
         unsigned start, len;
         if (p >= 0) {
@@ -380,6 +381,7 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
         L.lb[pos] = start;
         L.eb[pos] = etop;
         L.dn[pos] = 0;
+        return make_uint2(e, start);
     };
     auto mark = [&](unsigned v) {
         if constexpr (DENSE) atomicOr(&D.used[v >> 6], 1ull << (v & 63));
@@ -799,7 +801,9 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                 drop_task(base);
                 continue;
             }
-            // map the top accepted candidate and open the next frame
+            // map the top accepted candidate and open the next frame (whose
+            // bounds the evaluation below takes from registers, not LDS)
+            unsigned c0, e, lb;
             if (etop > L.eb[lvl] + L.dn[lvl]) {
                 etop--;
                 unsigned v = L.ev[etop];
@@ -808,10 +812,16 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                 L.MD[lvl] = L.edg[etop];
                 if (gl == 0) mark(v);
                 lvl++;
-                open_frame(lvl, 0, FULL_RANGE);
+                const uint2 fr = open_frame(lvl, 0, FULL_RANGE);
+                c0 = 0;
+                e = fr.x;
+                lb = fr.y;
+            } else {
+                c0 = L.cur[lvl];
+                e = L.end[lvl];
+                lb = L.lb[lvl];
             }
             // evaluate up to G candidates of the current frame
-            const unsigned c0 = L.cur[lvl], e = L.end[lvl], lb = L.lb[lvl];
             const unsigned idx = c0 + gl;
             bool ok = idx < e;
             const bool has_parent = L.pp[lvl] >= 0;
