@@ -115,6 +115,13 @@ sge_status upload_target(sge_ctx *c, Target &t) {
             return hip_fail(c, e, "upload adjacency bitsets");
         t.dev_bytes += adj.size() * 8;
     }
+    // neighbour-degree table (the plan kernel's first arc-consistency round)
+    if (!g.directed && !g.has_elab() && !t.nbr_deg.empty()) {
+        if ((e = hipMalloc(&t.d_nbr_deg, t.nbr_deg.size())) != hipSuccess) return hip_fail(c, e, "hipMalloc(table)");
+        if ((e = hipMemcpy(t.d_nbr_deg, t.nbr_deg.data(), t.nbr_deg.size(), hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(c, e, "upload neighbour-degree table");
+        t.dev_bytes += t.nbr_deg.size();
+    }
     const size_t nk = std::max<size_t>(t.label_keys.size(), 1);
     if ((e = hipMalloc(&t.d_label_keys, nk * 4)) != hipSuccess) return hip_fail(c, e, "hipMalloc(label keys)");
     if (!t.label_keys.empty() &&
@@ -133,6 +140,8 @@ void free_target(Target &t) {
     for (uint32_t *q : {t.d_irp, t.d_icol, t.d_elab, t.d_ielab})
         if (q) (void)hipFree(q);
     if (t.d_wcol) (void)hipFree(t.d_wcol);
+    if (t.d_nbr_deg) (void)hipFree(t.d_nbr_deg);
+    t.d_nbr_deg = nullptr;
     t.d_irp = t.d_icol = t.d_elab = t.d_ielab = nullptr;
     t.d_wcol = nullptr;
     t.d_col = nullptr;

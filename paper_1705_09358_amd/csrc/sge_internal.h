@@ -79,6 +79,7 @@ struct Target {
     WideEntry *d_wcol = nullptr;                 // undirected: per CSR entry {neighbour, its row start, degree, label}
     uint32_t *d_irp = nullptr, *d_icol = nullptr;   // directed: in-edges
     uint32_t *d_elab = nullptr, *d_ielab = nullptr; // edge labels (out, in), or null
+    uint8_t *d_nbr_deg = nullptr;                // nbr_deg on the device (undirected), or null
     uint64_t dev_bytes = 0;
 };
 
@@ -185,6 +186,8 @@ struct PlanIn {
     uint32_t mode, labelled, n, W;
     uint32_t root_lo, root_hi;
     uint32_t list_cap;            // entries `lists` holds: ncomp*n + k (a singleton domain adds one)
+    const uint8_t *nbr_deg;       // the target's neighbour-degree table (n x nbr_cols), or null
+    uint32_t nbr_cols;
     uint32_t rows;                // build support sets from adjacency rows (dense targets), not lists
     InstDesc *desc;               // the instance's search descriptor (col, node read; nroot written)
     DevPlan *plan;                // written

@@ -6,7 +6,9 @@
 //  * Domains (Section 4.1): D(u) starts as the target nodes passing the label
 //    and degree rules for pattern node u, built a word (64 nodes) at a time
 //    with one ballot per pattern node.
-//  * Arc-consistency (Section 4.1) to the greatest fixpoint, in support form:
+//  * Arc-consistency (Section 4.1) to the greatest fixpoint.  The first round
+//    (all domains still label-and-degree sets) reads the target's
+//    neighbour-degree table; later rounds work in support form:
 //    v stays in D(u) iff for each pattern neighbour w of u some target
 //    neighbour of v lies in D(w), i.e. v lies in the support set S(w), the
 //    union of the target rows of D(w).  S(w) is scattered into LDS with atomic
@@ -160,11 +162,8 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
     // the support sets live in LDS or, for very wide rows, in device memory;
     // the rounds are instantiated for each, so every access has its own
     // address space
-    auto arc_consistency = [&](auto Sb, const uint32_t B) {
+    auto arc_consistency = [&](auto Sb, const uint32_t B, unsigned long long dirty) {
         const gp<const uint64_t> adj = glob(desc->adj);
-        unsigned long long dirty = 0;
-        for (uint32_t u = 0; u < k; u++)
-            if (s_nb[u]) dirty |= 1ull << u;
         while (dirty) {
             if (tid == 0) s_next = 0;
             unsigned long long rest = dirty;
@@ -253,10 +252,53 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
         }
     };
     if (use_dom) {
+        unsigned long long dirty = 0;   // the nodes to revise the neighbours of
+        bool table = R.nbr_deg != nullptr;
+        for (uint32_t u = 0; u < k; u++) {
+            if (s_nb[u]) dirty |= 1ull << u;
+            table &= s_lab[u] != LABEL_NONE;   // (an absent label empties a domain anyway)
+        }
+        if (table) {
+            // the first round, against the label-and-degree domains: v has a
+            // neighbour in D(w) iff it has a neighbour of w's label whose
+            // degree is at least w's, which the target's neighbour-degree table
+            // answers; the rounds below then revise only around the domains
+            // this round changed (the host planner does the same)
+            const gp<const uint8_t> tab = glob(R.nbr_deg);
+            const uint32_t C = R.nbr_cols;
+            if (tid == 0) s_next = 0;
+            __syncthreads();
+            for (uint32_t it = wave; it < k * W; it += PLAN_WAVES) {
+                const uint32_t u = it / W, i = it - u * W;
+                const unsigned long long nbu = s_nb[u];
+                if (!nbu) continue;
+                const uint64_t word = D[(size_t)u * W + i];
+                bool keep = (word >> lane) & 1ull;
+                if (keep) {   // a member: node i * 64 + lane < n
+                    const gp<const uint8_t> row = tab + (size_t)(i * 64 + lane) * C;
+                    for (unsigned long long m = nbu; m; m &= m - 1) {
+                        const uint32_t w = (uint32_t)__builtin_ctzll(m);
+                        const uint32_t cw = s_lab[w] == LABEL_ANY ? C - 1 : s_lab[w];
+                        if (row[cw] < s_deg[w]) {
+                            keep = false;
+                            break;
+                        }
+                    }
+                }
+                const unsigned long long nw = __ballot(keep);
+                if (nw != word && lane == 0) {
+                    D[(size_t)u * W + i] = nw;
+                    atomicOr(&s_next, 1ull << u);
+                }
+            }
+            __syncthreads();
+            dirty = s_next;
+            __syncthreads();
+        }
         if (W <= lds_words)
-            arc_consistency(s_support, max(1u, min(k, lds_words / max(W, 1u))));
+            arc_consistency(s_support, max(1u, min(k, lds_words / max(W, 1u))), dirty);
         else
-            arc_consistency(glob(reinterpret_cast<unsigned long long *>(R.support)), 1u);
+            arc_consistency(glob(reinterpret_cast<unsigned long long *>(R.support)), 1u, dirty);
     }
 
     // domain sizes; an empty domain leaves nothing to search
