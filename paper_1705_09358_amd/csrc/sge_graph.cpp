@@ -108,13 +108,14 @@ void index_target(Target &t) {
     if ((uint64_t)g.n * t.nbr_cols <= NBR_DEG_MAX_BYTES) {
         const uint32_t C = t.nbr_cols;
         t.nbr_deg.assign((size_t)g.n * C, 0);
+        uint8_t *any = &t.nbr_deg[(size_t)(C - 1) * g.n];
         for (uint32_t v = 0; v < g.n; v++) {
-            uint8_t *row = &t.nbr_deg[(size_t)v * C];
             for (uint32_t e = g.rp[v]; e < g.rp[v + 1]; e++) {
                 const uint32_t x = g.col[e];
                 const uint8_t dx = (uint8_t)std::min<uint32_t>(g.rp[x + 1] - g.rp[x], 255);
-                row[t.dlab[x]] = std::max(row[t.dlab[x]], dx);
-                row[C - 1] = std::max(row[C - 1], dx);
+                uint8_t &byl = t.nbr_deg[(size_t)t.dlab[x] * g.n + v];
+                byl = std::max(byl, dx);
+                any[v] = std::max(any[v], dx);
             }
         }
     }

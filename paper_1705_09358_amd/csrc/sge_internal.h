@@ -66,8 +66,10 @@ struct Target {
     std::vector<std::vector<uint32_t>> by_label; // dense id -> nodes
     uint32_t W = 0;                              // 64-bit words per bitset row
     uint32_t max_deg = 0;
-    // nbr_deg[v * nbr_cols + L]: largest degree (saturated at 255) among the
+    // nbr_deg[L * n + v]: largest degree (saturated at 255) among the
     // neighbours of v with dense label L; column nbr_cols - 1 ignores labels.
+    // Stored by column, so a pass over the members of a domain for one
+    // pattern neighbour reads one column in increasing node order.
     // Empty when n * nbr_cols would exceed NBR_DEG_MAX_BYTES.
     std::vector<uint8_t> nbr_deg;
     uint32_t nbr_cols = 0;

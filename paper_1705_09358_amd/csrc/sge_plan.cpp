@@ -104,23 +104,23 @@ void build_plan(const Target &t, const HostGraph &p, int mode, bool labelled, ui
             // first round against the label-and-degree domains: a target node
             // has a neighbour in D(w) iff it has a neighbour of w's label whose
             // degree is at least w's, which the target's table answers
+            // (one pass over D(u) per pattern neighbour w, reading w's column)
             const uint32_t C = t.nbr_cols;
-            uint32_t col[KMAX];
-            for (uint32_t w = 0; w < k; w++) col[w] = lab[w] == LABEL_ANY ? C - 1 : lab[w];
             for (uint32_t u = 0; u < k; u++) {
                 if (!nb[u]) continue;
                 uint64_t *d = &D[(size_t)u * W];
-                for (uint32_t i = 0; i < W; i++) {
-                    for (uint64_t bits = d[i]; bits; bits &= bits - 1) {
-                        const uint32_t v = i * 64 + (uint32_t)__builtin_ctzll(bits);
-                        const uint8_t *row = &t.nbr_deg[(size_t)v * C];
-                        for (uint64_t m = nb[u]; m; m &= m - 1) {
-                            const uint32_t w = (uint32_t)__builtin_ctzll(m);
-                            if (row[col[w]] < deg[w]) {
-                                d[i] &= ~(1ull << (v & 63));
-                                dirty |= 1ull << u;
-                                break;
-                            }
+                for (uint64_t m = nb[u]; m; m &= m - 1) {
+                    const uint32_t w = (uint32_t)__builtin_ctzll(m);
+                    const uint8_t *cl = &t.nbr_deg[(size_t)(lab[w] == LABEL_ANY ? C - 1 : lab[w]) * n];
+                    for (uint32_t i = 0; i < W; i++) {
+                        uint64_t keep = d[i];
+                        for (uint64_t bits = d[i]; bits; bits &= bits - 1) {
+                            const uint32_t b = (uint32_t)__builtin_ctzll(bits);
+                            if (cl[i * 64 + b] < deg[w]) keep &= ~(1ull << b);
+                        }
+                        if (keep != d[i]) {
+                            d[i] = keep;
+                            dirty |= 1ull << u;
                         }
                     }
                 }
