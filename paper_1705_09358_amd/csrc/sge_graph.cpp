@@ -105,15 +105,16 @@ void index_target(Target &t) {
     // and degree >= d (pattern degrees are below 64, so 255 saturates safely)
     t.nbr_deg.clear();
     t.nbr_cols = (uint32_t)t.label_keys.size() + 1;
-    if ((uint64_t)g.n * t.nbr_cols <= NBR_DEG_MAX_BYTES) {
+    t.nbr_stride = t.W * 64;   // columns padded to whole 64-node words (zeros)
+    if ((uint64_t)t.nbr_stride * t.nbr_cols <= NBR_DEG_MAX_BYTES) {
         const uint32_t C = t.nbr_cols;
-        t.nbr_deg.assign((size_t)g.n * C, 0);
-        uint8_t *any = &t.nbr_deg[(size_t)(C - 1) * g.n];
+        t.nbr_deg.assign((size_t)t.nbr_stride * C, 0);
+        uint8_t *any = &t.nbr_deg[(size_t)(C - 1) * t.nbr_stride];
         for (uint32_t v = 0; v < g.n; v++) {
             for (uint32_t e = g.rp[v]; e < g.rp[v + 1]; e++) {
                 const uint32_t x = g.col[e];
                 const uint8_t dx = (uint8_t)std::min<uint32_t>(g.rp[x + 1] - g.rp[x], 255);
-                uint8_t &byl = t.nbr_deg[(size_t)t.dlab[x] * g.n + v];
+                uint8_t &byl = t.nbr_deg[(size_t)t.dlab[x] * t.nbr_stride + v];
                 byl = std::max(byl, dx);
                 any[v] = std::max(any[v], dx);
             }

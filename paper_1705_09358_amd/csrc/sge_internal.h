@@ -66,13 +66,14 @@ struct Target {
     std::vector<std::vector<uint32_t>> by_label; // dense id -> nodes
     uint32_t W = 0;                              // 64-bit words per bitset row
     uint32_t max_deg = 0;
-    // nbr_deg[L * n + v]: largest degree (saturated at 255) among the
-    // neighbours of v with dense label L; column nbr_cols - 1 ignores labels.
-    // Stored by column, so a pass over the members of a domain for one
-    // pattern neighbour reads one column in increasing node order.
+    // nbr_deg[L * nbr_stride + v]: largest degree (saturated at 255) among
+    // the neighbours of v with dense label L; column nbr_cols - 1 ignores
+    // labels.  Stored by column (nbr_stride = 64 W bytes, zero padded), so a
+    // domain word's 64 nodes have their entries side by side.
     // Empty when n * nbr_cols would exceed NBR_DEG_MAX_BYTES.
     std::vector<uint8_t> nbr_deg;
     uint32_t nbr_cols = 0;
+    uint32_t nbr_stride = 0;
     // device
     uint32_t *d_col = nullptr;
     NodeRec *d_node = nullptr;
@@ -188,8 +189,8 @@ struct PlanIn {
     uint32_t mode, labelled, n, W;
     uint32_t root_lo, root_hi;
     uint32_t list_cap;            // entries `lists` holds: ncomp*n + k (a singleton domain adds one)
-    const uint8_t *nbr_deg;       // the target's neighbour-degree table (n x nbr_cols), or null
-    uint32_t nbr_cols;
+    const uint8_t *nbr_deg;       // the target's neighbour-degree table (nbr_cols columns), or null
+    uint32_t nbr_cols, nbr_stride;
     uint32_t rows;                // build support sets from adjacency rows (dense targets), not lists
     InstDesc *desc;               // the instance's search descriptor (col, node read; nroot written)
     DevPlan *plan;                // written

@@ -190,6 +190,7 @@ sge_status pack_instances(sge_ctx *c, const std::vector<const InstanceSpec *> &s
         r.nlabels = (uint32_t)sp.t->label_keys.size();
         r.nbr_deg = sp.t->d_nbr_deg;
         r.nbr_cols = sp.t->nbr_cols;
+        r.nbr_stride = sp.t->nbr_stride;
         r.mode = (uint32_t)sp.mode;
         r.labelled = sp.labelled ? 1u : 0u;
         r.n = sp.t->g.n;

@@ -12,6 +12,9 @@
 // directions (Section "RI"); rule 3 compares in- and out-degree.
 #include <algorithm>
 #include <cstring>
+#if defined(__SSE2__)
+#include <emmintrin.h>
+#endif
 
 #include "sge_internal.h"
 
@@ -24,6 +27,23 @@ static inline uint32_t popcount_row(const uint64_t *r, uint32_t W) {
 }
 
 static inline bool test_bit(const uint64_t *r, uint32_t v) { return (r[v >> 6] >> (v & 63)) & 1; }
+
+// bit b set iff p[b] >= d, for the 64 bytes p[0..63]
+static inline uint64_t bytes_at_least(const uint8_t *p, uint8_t d) {
+#if defined(__SSE2__)
+    const __m128i dv = _mm_set1_epi8((char)d);
+    uint64_t m = 0;
+    for (int q = 0; q < 4; q++) {
+        const __m128i x = _mm_loadu_si128(reinterpret_cast<const __m128i *>(p + 16 * q));
+        m |= (uint64_t)(uint16_t)_mm_movemask_epi8(_mm_cmpeq_epi8(_mm_max_epu8(x, dv), x)) << (16 * q);
+    }
+    return m;
+#else
+    uint64_t m = 0;
+    for (int b = 0; b < 64; b++) m |= (uint64_t)(p[b] >= d) << b;
+    return m;
+#endif
+}
 
 void build_plan(const Target &t, const HostGraph &p, int mode, bool labelled, uint32_t root_lo, uint32_t root_hi,
                 Plan &pl, bool want_pos_bits, std::vector<uint64_t> &pos_bits) {
@@ -104,20 +124,18 @@ void build_plan(const Target &t, const HostGraph &p, int mode, bool labelled, ui
             // first round against the label-and-degree domains: a target node
             // has a neighbour in D(w) iff it has a neighbour of w's label whose
             // degree is at least w's, which the target's table answers
-            // (one pass over D(u) per pattern neighbour w, reading w's column)
+            // (one pass over D(u) per pattern neighbour w, reading w's column
+            // 64 nodes at a time; pattern degrees are below 64)
             const uint32_t C = t.nbr_cols;
             for (uint32_t u = 0; u < k; u++) {
                 if (!nb[u]) continue;
                 uint64_t *d = &D[(size_t)u * W];
                 for (uint64_t m = nb[u]; m; m &= m - 1) {
                     const uint32_t w = (uint32_t)__builtin_ctzll(m);
-                    const uint8_t *cl = &t.nbr_deg[(size_t)(lab[w] == LABEL_ANY ? C - 1 : lab[w]) * n];
+                    const uint8_t *cl = &t.nbr_deg[(size_t)(lab[w] == LABEL_ANY ? C - 1 : lab[w]) * t.nbr_stride];
                     for (uint32_t i = 0; i < W; i++) {
-                        uint64_t keep = d[i];
-                        for (uint64_t bits = d[i]; bits; bits &= bits - 1) {
-                            const uint32_t b = (uint32_t)__builtin_ctzll(bits);
-                            if (cl[i * 64 + b] < deg[w]) keep &= ~(1ull << b);
-                        }
+                        if (!d[i]) continue;
+                        const uint64_t keep = d[i] & bytes_at_least(cl + (size_t)i * 64, (uint8_t)deg[w]);
                         if (keep != d[i]) {
                             d[i] = keep;
                             dirty |= 1ull << u;

@@ -274,12 +274,12 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
                 if (!nbu) continue;
                 const uint64_t word = D[(size_t)u * W + i];
                 bool keep = (word >> lane) & 1ull;
-                if (keep) {   // a member: node i * 64 + lane < n (columns by label, n entries each)
+                if (keep) {   // a member: node i * 64 + lane < n (columns by label, 64 W entries each)
                     const gp<const uint8_t> vcol = tab + i * 64 + lane;
                     for (unsigned long long m = nbu; m; m &= m - 1) {
                         const uint32_t w = (uint32_t)__builtin_ctzll(m);
                         const uint32_t cw = s_lab[w] == LABEL_ANY ? C - 1 : s_lab[w];
-                        if (vcol[(size_t)cw * n] < s_deg[w]) {
+                        if (vcol[(size_t)cw * R.nbr_stride] < s_deg[w]) {
                             keep = false;
                             break;
                         }
