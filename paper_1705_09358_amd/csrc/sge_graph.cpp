@@ -100,6 +100,18 @@ void index_target(Target &t) {
     t.W = (g.n + 63) / 64;
     t.max_deg = 0;
     for (uint32_t v = 0; v < g.n; v++) t.max_deg = std::max(t.max_deg, g.rp[v + 1] - g.rp[v]);
+    t.label_bits.clear();
+    t.deg_ge.clear();
+    if (!g.directed && ((uint64_t)t.label_keys.size() + 64) * t.W * 8 <= LABEL_DEG_BITS_MAX_BYTES) {
+        t.label_bits.assign((size_t)t.label_keys.size() * t.W, 0);
+        t.deg_ge.assign((size_t)64 * t.W, 0);
+        for (uint32_t v = 0; v < g.n; v++) {
+            const uint64_t bit = 1ull << (v & 63);
+            t.label_bits[(size_t)t.dlab[v] * t.W + (v >> 6)] |= bit;
+            const uint32_t dv = std::min<uint32_t>(g.rp[v + 1] - g.rp[v], 63);
+            for (uint32_t d = 0; d <= dv; d++) t.deg_ge[(size_t)d * t.W + (v >> 6)] |= bit;
+        }
+    }
     // the first arc-consistency round reads, for a candidate v and a pattern
     // neighbour of label L and degree d, whether v has a neighbour of label L
     // and degree >= d (pattern degrees are below 64, so 255 saturates safely)

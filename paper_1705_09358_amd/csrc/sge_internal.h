@@ -74,6 +74,10 @@ struct Target {
     std::vector<uint8_t> nbr_deg;
     uint32_t nbr_cols = 0;
     uint32_t nbr_stride = 0;
+    // undirected targets: the nodes of each dense label (label_bits, one row
+    // of W words per label) and of degree >= d (deg_ge, rows d = 0..63), so a
+    // label-and-degree domain is one AND of two rows; empty when too large
+    std::vector<uint64_t> label_bits, deg_ge;
     // device
     uint32_t *d_col = nullptr;
     NodeRec *d_node = nullptr;
@@ -134,6 +138,7 @@ void build_plan(const Target &t, const HostGraph &p, int mode, bool labelled, ui
                 Plan &plan, bool want_pos_bitsets, std::vector<uint64_t> &pos_bits);
 
 constexpr uint64_t NBR_DEG_MAX_BYTES = 256ull << 20;
+constexpr uint64_t LABEL_DEG_BITS_MAX_BYTES = 64ull << 20;
 
 // Dense label ids of a target (fills dlab, label_keys, by_label, W, max_deg)
 // and its neighbour-degree table.

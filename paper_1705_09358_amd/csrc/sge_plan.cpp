@@ -111,7 +111,23 @@ void build_plan(const Target &t, const HostGraph &p, int mode, bool labelled, ui
     uint32_t dsize[KMAX] = {0};
     if (use_dom) {
         D.assign((size_t)k * W, 0);
-        for (uint32_t u = 0; u < k; u++) compat_nodes(u, [&](uint32_t v) { D[(size_t)u * W + (v >> 6)] |= 1ull << (v & 63); });
+        if (!directed && !t.deg_ge.empty()) {
+            // the label row AND the degree row (pattern degrees are below 64)
+            for (uint32_t u = 0; u < k; u++) {
+                if (lab[u] == LABEL_NONE) continue;
+                const uint64_t *dg = &t.deg_ge[(size_t)std::min<uint32_t>(deg[u], 63) * W];
+                uint64_t *d = &D[(size_t)u * W];
+                if (lab[u] == LABEL_ANY) {
+                    std::memcpy(d, dg, W * sizeof(uint64_t));
+                } else {
+                    const uint64_t *lb = &t.label_bits[(size_t)lab[u] * W];
+                    for (uint32_t i = 0; i < W; i++) d[i] = dg[i] & lb[i];
+                }
+            }
+        } else {
+            for (uint32_t u = 0; u < k; u++)
+                compat_nodes(u, [&](uint32_t v) { D[(size_t)u * W + (v >> 6)] |= 1ull << (v & 63); });
+        }
         // arc-consistency to the fixpoint.  A round revises D(u) against the
         // pattern neighbours w whose domains changed since D(u) was last
         // revised against them (for the others every member of D(u) still has
@@ -156,6 +172,41 @@ void build_plan(const Target &t, const HostGraph &p, int mode, bool labelled, ui
                 if (test_bit(dw, cl[e]) && (!elabelled || (el.empty() ? 0u : el[e]) == b)) return true;
             return false;
         };
+        if (!directed && !elabelled) {
+            // undirected, no edge labels compared: a round builds, for each w
+            // whose domain changed, the support set S(w) (every target
+            // neighbour of a member of D(w)) and intersects the domains of
+            // w's pattern neighbours with it
+            std::vector<uint64_t> S(W);
+            while (dirty) {
+                uint64_t next = 0;
+                for (uint64_t mw = dirty; mw; mw &= mw - 1) {
+                    const uint32_t w = (uint32_t)__builtin_ctzll(mw);
+                    std::fill(S.begin(), S.end(), 0ull);
+                    const uint64_t *dw = &D[(size_t)w * W];
+                    for (uint32_t i = 0; i < W; i++)
+                        for (uint64_t bits = dw[i]; bits; bits &= bits - 1) {
+                            const uint32_t x = i * 64 + (uint32_t)__builtin_ctzll(bits);
+                            for (uint32_t e = tg.rp[x]; e < tg.rp[x + 1]; e++) {
+                                const uint32_t y = tg.col[e];
+                                S[y >> 6] |= 1ull << (y & 63);
+                            }
+                        }
+                    for (uint64_t mu = nb[w]; mu; mu &= mu - 1) {
+                        const uint32_t u = (uint32_t)__builtin_ctzll(mu);
+                        uint64_t *d = &D[(size_t)u * W];
+                        uint64_t diff = 0;
+                        for (uint32_t i = 0; i < W; i++) {
+                            const uint64_t x = d[i] & S[i];
+                            diff |= x ^ d[i];
+                            d[i] = x;
+                        }
+                        if (diff) next |= 1ull << u;
+                    }
+                }
+                dirty = next;
+            }
+        }
         while (dirty) {
             uint64_t next = 0;
             for (uint32_t u = 0; u < k; u++) {
