@@ -169,6 +169,18 @@ sge_status pack_instances(sge_ctx *c, const std::vector<const InstanceSpec *> &s
     char *da = (char *)bufs.d_arena.p;
     InstDesc *hdesc = (InstDesc *)(hb + off_desc);
     PlanIn *hreq = (PlanIn *)(hb + pk.off_req);
+    // plan requests in decreasing order of estimated work (pattern size x
+    // target size, arc-consistency counted four times), so the workgroups
+    // of the largest plans start first and the kernel has no long tail;
+    // each request carries its own output addresses, so the order is free
+    std::vector<uint32_t> by_cost(m), slot(m);
+    for (uint32_t j = 0; j < m; j++) by_cost[j] = j;
+    auto cost = [&](uint32_t j) {
+        const InstanceSpec &sp = *specs[j];
+        return (uint64_t)sp.p->g.n * sp.t->g.n * (sp.mode != SGE_RI ? 4u : 1u);
+    };
+    std::stable_sort(by_cost.begin(), by_cost.end(), [&](uint32_t a, uint32_t b) { return cost(a) > cost(b); });
+    for (uint32_t r = 0; r < m; r++) slot[by_cost[r]] = r;
     for (uint32_t j = 0; j < m; j++) {
         const InstanceSpec &sp = *specs[j];
         const bool with_bits = dense || sp.mode != SGE_RI;
@@ -183,7 +195,7 @@ sge_status pack_instances(sge_ctx *c, const std::vector<const InstanceSpec *> &s
         d.lists = (const uint32_t *)(da + list_at[j]);
         d.rows = sp.rows;
         d.cap_rows = sp.rows ? sp.cap_rows : 0;
-        PlanIn &r = hreq[j];
+        PlanIn &r = hreq[slot[j]];
         r = PlanIn{};
         r.pat = sp.p->d_pat;
         r.label_keys = sp.t->d_label_keys;
