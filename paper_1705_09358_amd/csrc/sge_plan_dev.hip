@@ -32,12 +32,11 @@ namespace sge {
 
 namespace {
 
-// Workgroup sizes: 1024 threads when a launch plans few instances (each
-// plan's latency-bound phases then spread over 16 waves), 256 for large
-// batches (more plans resident per CU).
-constexpr int PLAN_THREADS_SMALL_BATCH = 1024;
-constexpr int PLAN_THREADS_LARGE_BATCH = 256;
-constexpr uint32_t PLAN_LARGE_BATCH = 256;
+// Workgroup size: 1024 threads, so each plan's latency-bound phases spread
+// over 16 waves.  A launch takes as long as its largest plan: with 256-thread
+// workgroups (more plans resident per CU) the 4096-plan batch took 2.96 ms,
+// its largest plan alone 2.9 ms; with 1024 threads 2.04 ms.
+constexpr int PLAN_THREADS = 1024;
 
 // Device memory in the global address space: the pointers a plan request
 // holds are loaded from memory, so the compiler would treat them as generic
@@ -538,12 +537,7 @@ hipError_t launch_plan(const PlanIn *reqs, uint32_t m, uint32_t wmax, uint32_t k
     // instance's rows times the largest pattern, when that is smaller)
     const uint32_t words =
         (uint32_t)std::min<uint64_t>((uint64_t)std::max<uint32_t>(wmax, 1) * std::max<uint32_t>(kmax, 1), PLAN_LDS_WORDS);
-    if (m >= PLAN_LARGE_BATCH)
-        hipLaunchKernelGGL(plan_kernel<PLAN_THREADS_LARGE_BATCH>, dim3(m), dim3(PLAN_THREADS_LARGE_BATCH),
-                           (size_t)words * 8, s, reqs, words);
-    else
-        hipLaunchKernelGGL(plan_kernel<PLAN_THREADS_SMALL_BATCH>, dim3(m), dim3(PLAN_THREADS_SMALL_BATCH),
-                           (size_t)words * 8, s, reqs, words);
+    hipLaunchKernelGGL(plan_kernel<PLAN_THREADS>, dim3(m), dim3(PLAN_THREADS), (size_t)words * 8, s, reqs, words);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(FIN_THREADS), 0, s, desc, chunk_prefix, m, policy, root_chunk,
