@@ -59,33 +59,63 @@ sge_status sge_batch_run(sge_ctx *c, uint32_t njobs, const sge_job *jobs, sge_re
         if (it == c->batch_tune.end()) {
             // autotune on this batch, one knob at a time from the default shape
             // (root chunks, automatic width, default donation period, all
-            // resident blocks): resident blocks per CU, then the unit width,
-            // then one unit per job, then a shorter donation period.  A knob
+            // resident blocks): resident blocks per CU, then the unit width
+            // and the donation period together, then one unit per job.  A knob
             // the caller set is kept.  A short launch is run once more and then
-            // timed three times (the median counts: launch times of the same
-            // shape vary by several percent); exploring stops once a trial runs
-            // longer than TUNE_MAX_TRIAL_MS, and long launches keep the best
-            // shape so far.
+            // timed three times (the median counts); a shape already timed (the
+            // automatic width is one of the explicit ones) is not timed again.
+            // Launch times of one shape spread by several percent, so the best
+            // of several medians is biased low: the two fastest shapes are
+            // then timed again in alternation, five launches each, and the
+            // lower median decides.  Exploring stops once a trial runs longer
+            // than TUNE_MAX_TRIAL_MS, and long launches keep the best shape so
+            // far without the final comparison.
             constexpr double TUNE_MAX_TRIAL_MS = 100.0;
-            double best = 1e300;
-            BatchTune cur{2, saved_lanes, saved_donate, saved_per_cu};
-            bool stop = false;
-            auto trial = [&](const BatchTune &t) -> sge_status {
-                if (stop) return SGE_OK;
+            constexpr int FINAL_RUNS = 5;
+            struct Tried {
+                BatchTune t;
+                double ms;
+            };
+            std::vector<Tried> tried;
+            auto same = [](const BatchTune &a, const BatchTune &b) {
+                return a.policy == b.policy && a.lanes == b.lanes && a.donate == b.donate && a.per_cu == b.per_cu;
+            };
+            auto timed_before = [&](const BatchTune &t) {
+                for (const Tried &x : tried)
+                    if (same(x.t, t)) return true;
+                return false;
+            };
+            auto set_shape = [&](const BatchTune &t) {
                 c->lanes = t.lanes;
                 c->donate = t.donate;
                 c->per_cu = t.per_cu;
+            };
+            auto restore_shape = [&]() {
+                c->lanes = saved_lanes;
+                c->donate = saved_donate;
+                c->per_cu = saved_per_cu;
+            };
+            double best = 1e300;
+            BatchTune cur{2, saved_lanes, saved_donate, saved_per_cu};
+            bool stop = false;
+            auto trial = [&](BatchTune t) -> sge_status {
+                if (stop || (t.lanes && timed_before(t))) return SGE_OK;
+                set_shape(t);
                 sge_status st = run_instances(c, specs, out, mp, ms, true, t.policy);
+                if (t.lanes == 0) t.lanes = c->last_lanes;   // the width the automatic choice resolved to
+                if (st == SGE_OK && timed_before(t)) {
+                    restore_shape();
+                    return SGE_OK;
+                }
                 if (st == SGE_OK && ms <= TUNE_MAX_TRIAL_MS) {
                     double r[3] = {0, 0, 0};
                     for (int i = 0; i < 3 && st == SGE_OK; i++) st = run_instances(c, specs, out, mp, r[i], true, t.policy);
                     std::sort(r, r + 3);
                     ms = r[1];
                 }
-                c->lanes = saved_lanes;
-                c->donate = saved_donate;
-                c->per_cu = saved_per_cu;
+                restore_shape();
                 if (st != SGE_OK) return st;
+                tried.push_back({t, ms});
                 if (ms < best) {
                     best = ms;
                     cur = t;
@@ -98,11 +128,32 @@ sge_status sge_batch_run(sge_ctx *c, uint32_t njobs, const sge_job *jobs, sge_re
                 for (int b : {1, 2})
                     if (st == SGE_OK) st = trial(BatchTune{cur.policy, cur.lanes, cur.donate, b});
             const BatchTune after_blocks = cur;
-            if (saved_lanes == 0)
-                for (int l : {32, 64})
-                    if (st == SGE_OK) st = trial(BatchTune{after_blocks.policy, l, after_blocks.donate, after_blocks.per_cu});
+            // the unit width and the donation period interact (narrow units
+            // gain more from a shorter period), so they are tried together
+            const std::vector<int> widths = saved_lanes ? std::vector<int>{saved_lanes} : std::vector<int>{32, 64};
+            const std::vector<int> periods = saved_donate == 1 ? std::vector<int>{1, 16} : std::vector<int>{saved_donate};
+            for (int l : widths)
+                for (int dn : periods)
+                    if (st == SGE_OK) st = trial(BatchTune{after_blocks.policy, l, dn, after_blocks.per_cu});
             if (st == SGE_OK) st = trial(BatchTune{1, cur.lanes, cur.donate, cur.per_cu});
-            if (st == SGE_OK && saved_donate == 1) st = trial(BatchTune{cur.policy, cur.lanes, 16, cur.per_cu});
+            if (st == SGE_OK && !stop && tried.size() >= 2) {
+                std::sort(tried.begin(), tried.end(), [](const Tried &a, const Tried &b) { return a.ms < b.ms; });
+                const BatchTune A = tried[0].t, B = tried[1].t;
+                double ra[FINAL_RUNS], rb[FINAL_RUNS];
+                for (int i = 0; i < FINAL_RUNS && st == SGE_OK; i++) {
+                    set_shape(A);
+                    st = run_instances(c, specs, out, mp, ra[i], true, A.policy);
+                    if (st != SGE_OK) break;
+                    set_shape(B);
+                    st = run_instances(c, specs, out, mp, rb[i], true, B.policy);
+                }
+                restore_shape();
+                if (st == SGE_OK) {
+                    std::sort(ra, ra + FINAL_RUNS);
+                    std::sort(rb, rb + FINAL_RUNS);
+                    cur = rb[FINAL_RUNS / 2] < ra[FINAL_RUNS / 2] ? B : A;
+                }
+            }
             if (st != SGE_OK) return st;
             if (c->batch_tune.size() >= 256) c->batch_tune.clear();
             it = c->batch_tune.emplace(key, cur).first;

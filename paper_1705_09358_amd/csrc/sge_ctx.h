@@ -90,6 +90,7 @@ struct sge_ctx {
     double last_ms[3] = {0, 0, 0};   // last launch: kernel, until the last task finished, until done was set
     double last_busy_ms = 0;         // last launch: unit-milliseconds spent holding tasks
     uint32_t last_units = 0;         // last launch: units that entered the search loop
+    int last_lanes = 0;              // last launch: lanes per search unit
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::unique_ptr<sge::Server, sge::ServerDeleter> server;
     std::mutex serve_mu;

@@ -486,6 +486,7 @@ sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std
     c->last_ms[2] = pk.ms_done;
     c->last_busy_ms = pk.busy_ms;
     c->last_units = pk.units_run;
+    c->last_lanes = pk.cfg.lanes;
     if (pk.bad_task) return fail(c, SGE_E_DEVICE, "the work queue delivered an invalid task; counters are unreliable");
     if (op[0]->timed_out) c->err = "search stopped at the time limit; counters are partial";
     return SGE_OK;
