@@ -12,8 +12,11 @@ match counts are checked against the oracle's stored values.
 Also reported: the plain single-instance path (one sge_count per pattern) on
 the same patterns, the same batch in each of the four search modes (the
 variant study), the C1 / C4 / dense C3 workloads, the directed edge-labelled
-workload (c2d), the serving run (p50/p99 latency), the kernel's algorithmic-byte rate against the HBM peak, and the
-oracle's own rate on this host (a baseline, not the target).
+workload (c2d), the serving run (p50/p99 latency), the kernel's algorithmic-byte rate against the HBM peak, and
+three CPU baselines on this host (baselines, not the target): the oracle
+single-threaded on one pinned core (with the processor model), the paper's
+parallel scheduler on up to 16 threads, and a pool of up to 16
+single-threaded oracle processes over one pass of C4.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--extra c1,c4,c3,c2d]
                     [--c3-patterns 8] [--serve-seconds 10] [--no-variants]
@@ -259,7 +262,55 @@ def measured_traffic():
     return float(m.group(1)) if m and m.group(2) == h else None
 
 
+def host_cpu():
+    """The host's processor model and the cores this process may use."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(cpu_model=model, host_cores=len(os.sched_getaffinity(0)))
+
+
+def measured_l2(kernel_ms):
+    """L2 hit rate and request rate of the search kernel on this workload, from
+    the committed counter summary, only while the kernel source is the one
+    that was measured (else None)."""
+    import hashlib
+    import re
+    path = os.path.join(REPO, "profiles", "search_kernel_l2_contact3000.md")
+    src = os.path.join(REPO, "paper_1705_09358_amd", "csrc", "sge_search.hip")
+    try:
+        m = re.search(r"l2_hit_rate=([0-9.]+) l2_requests_per_launch=([0-9.eE+]+) kernel_source_sha256=([0-9a-f]+)",
+                      open(path).read())
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if not m or m.group(3) != h:
+        return None
+    req = float(m.group(2))
+    return dict(hit_rate=float(m.group(1)), requests_per_launch=req,
+                requests_per_s=req / (kernel_ms / 1000.0), source="profiles/search_kernel_l2_contact3000.md")
+
+
 def cpu_baseline(insts, budget_s=12.0, variant_sample=34):
+    """The oracle, single-threaded, with the calling thread pinned to one core
+    (restored afterwards, before the multi-threaded legs)."""
+    allowed = os.sched_getaffinity(0)
+    core = min(allowed)
+    os.sched_setaffinity(0, {core})
+    try:
+        r = _cpu_baseline(insts, budget_s, variant_sample)
+    finally:
+        os.sched_setaffinity(0, allowed)
+    r["pinned_core"] = core
+    return r
+
+
+def _cpu_baseline(insts, budget_s, variant_sample):
     import oracle
     oracle.lib()
     # the variant study's oracle leg: every third pattern in each mode
@@ -290,6 +341,37 @@ def cpu_baseline(insts, budget_s=12.0, variant_sample=34):
                 matches_per_s=matches / el,
                 sample=f"{n} pattern searches ({passes} pass(es) over the workload), single thread, {el:.1f} s CPU",
                 variants=dict(sample=f"{len(sample)} of the 100 patterns (every third), each mode", **variants))
+
+
+def _pool_init(root):
+    sys.path.insert(0, root)
+    import oracle
+    oracle.lib()
+
+
+def _pool_run(inst):
+    import oracle
+    r = oracle.run(inst.pattern, inst.target, inst.mode, inst.labelled)
+    return r["states"], r["matches"]
+
+
+def cpu_pool(insts, procs=16):
+    """A pool of single-threaded oracle processes, one instance per task, over
+    one pass of a many-instance workload (wall time from the first task to the
+    last result; the pool is started and warm before the clock starts)."""
+    import multiprocessing as mp
+    procs = max(1, min(procs, len(os.sched_getaffinity(0))))
+    with mp.get_context("spawn").Pool(procs, initializer=_pool_init, initargs=(REPO,)) as pool:
+        pool.map(_pool_run, insts[:procs], chunksize=1)   # warm: every worker has loaded the oracle
+        t0 = time.perf_counter()
+        res = pool.map(_pool_run, insts, chunksize=1)
+        el = time.perf_counter() - t0
+    states = sum(r[0] for r in res)
+    matches = sum(r[1] for r in res)
+    return dict(value=states / el, unit="states/s", cores=procs, kind="oracle pool",
+                matches_per_s=matches / el, states=states, seconds=el,
+                sample=f"one pass over the {len(insts)} instances, one instance per task, {procs} single-threaded "
+                       f"oracle processes, wall time")
 
 
 def cpu_parallel(insts, budget_s=6.0, group=4):
@@ -365,6 +447,7 @@ def main():
             log("c2: variant study (four modes)")
             variants = run_variants(ctx, torch, b["jobs"], max(3, a.steps // 4))
         extras = {}
+        c4_insts = None
         for cfg in [x for x in a.extra.split(",") if x]:
             if cfg == "c3":
                 ctx3 = sge.Context(0, stream=stream)
@@ -385,6 +468,8 @@ def main():
                 extras[cfg]["plain_states_per_s"] = p2["states_per_s"]
                 extras[cfg]["vs_plain"] = e["states_per_s"] / p2["states_per_s"]
             ctx2.close()
+            if cfg == "c4":
+                c4_insts = i2
         ctx.close()
     serve = run_serve(torch, a.serve_seconds, 200.0) if a.serve_seconds > 0 else None
     alg_bytes = man["total_alg_bytes"]
@@ -415,6 +500,7 @@ def main():
         "vs_plain": None if plain is None else b["states_per_s"] / plain["states_per_s"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic()},
+        "l2": measured_l2(b["kernel_ms"]),
         "p99_ms": None if serve is None else serve["p99_ms"],
         "serve": serve,
         "variants": variants,
@@ -423,8 +509,12 @@ def main():
     if not a.no_cpu:
         log("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(insts)
+        res["cpu_baseline"].update(host_cpu())
         log("cpu baseline (the paper's parallel scheduler)")
         res["cpu_parallel"] = cpu_parallel(insts)
+        if c4_insts is not None:
+            log("cpu baseline: oracle process pool over c4")
+            res["cpu_pool_c4"] = cpu_pool(c4_insts)
     print(json.dumps(res))
 
 
