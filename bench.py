@@ -406,7 +406,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--c3-patterns", type=int, default=4)
     ap.add_argument("--copy-probe", type=int, default=0,
-                    help="only copy a buffer of this many MiB five times (calibrates the HBM byte counters)")
+                    help="only copy a buffer of this many MiB (calibrates the HBM byte counters; prints the copy rate)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--no-variants", action="store_true", help="skip the four-mode variant study")
     a = ap.parse_args()
@@ -421,13 +421,27 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
     if a.copy_probe:
+        # a plain device copy: calibrates the HBM byte counters (five copies)
+        # and measures the streaming rate (read + write bytes / copy time,
+        # median of 20 timed copies after the five)
         n = a.copy_probe << 18        # float32 elements
         src = torch.ones(n, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(5):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_MiB": a.copy_probe, "copies": 5}))
+        ms = []
+        for _ in range(20):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            dst.copy_(src)
+            e1.record()
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        ms.sort()
+        med = ms[len(ms) // 2]
+        print(json.dumps({"copy_probe_MiB": a.copy_probe, "copies": 25, "ms_per_copy": med,
+                          "GBps_read_plus_write": 2 * n * 4 / (med / 1000.0) / 1e9}))
         return
     stream = torch.cuda.Stream()
     man = load_manifest("c2")
