@@ -317,7 +317,7 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
     }
     const unsigned home = blockIdx.x % QUEUE_GROUPS;
     QGroup *HG = &S->grp[home];
-    if (lane == 0) fadd(&S->units, 64u / G);
+    if (threadIdx.x == 0) fadd(&S->units, blockDim.x / G);   // every unit of the block enters the loop
     const bool checker = blockIdx.x == 0 && threadIdx.x < 64;   // the wave that detects termination
 
     // unit state (identical in the G lanes of a unit)
@@ -1080,10 +1080,55 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
             }
         }
     }
-    flush();
-    if (gl == 0) fadd64(&S->t_busy, busy_ticks);
-    if (lane == 0) {
-        if (last_finish) stamp_max(&S->t_work, last_finish);
+    // Leaving: the units of the block combine what they still hold, so that
+    // a shared word receives one atomic per block rather than one per unit
+    // (thousands of units leave within microseconds of each other, mostly
+    // holding the same last instance, and atomics on one word serialise).
+    // Every wave of the block reaches this point (the loop is left only by
+    // `break`), and the units' LDS areas are free: each unit's area (at least
+    // 16 words) takes its exit record.
+    __syncthreads();
+    unsigned long long *rec = reinterpret_cast<unsigned long long *>(lds + (size_t)unit * a.unit_words);
+    if (gl == 0) {
+        rec[0] = cinst;
+        rec[1] = c_states;
+        rec[2] = c_matches;
+        rec[3] = c_cands;
+        rec[4] = c_steals;
+        rec[5] = c_steps;
+        rec[6] = busy_ticks;
+        rec[7] = last_finish;
+    }
+    __syncthreads();
+    const unsigned nunits = blockDim.x / G;
+    auto rec_of = [&](unsigned u) {
+        return reinterpret_cast<const unsigned long long *>(lds + (size_t)u * a.unit_words);
+    };
+    if (gl == 0 && cinst != NO_TASK) {
+        // the first unit holding an instance adds every later unit's counts for it
+        bool first = true;
+        for (unsigned u = 0; u < (unsigned)unit && first; u++) first = rec_of(u)[0] != cinst;
+        if (first) {
+            for (unsigned u = unit + 1; u < nunits; u++) {
+                const unsigned long long *r = rec_of(u);
+                if (r[0] != cinst) continue;
+                c_states += r[1];
+                c_matches += r[2];
+                c_cands += r[3];
+                c_steals += r[4];
+                c_steps += r[5];
+            }
+            flush();
+        }
+    }
+    if (threadIdx.x == 0) {
+        unsigned long long busy = 0, fin = 0;
+        for (unsigned u = 0; u < nunits; u++) {
+            busy += rec_of(u)[6];
+            fin = max(fin, rec_of(u)[7]);
+        }
+        fadd64(&S->t_busy, busy);
+        if (fin) stamp_max(&S->t_work, fin);
         stamp_max(&S->t_end, now_ticks());
     }
 }
@@ -1122,10 +1167,12 @@ hipError_t launch_g(SearchArgs args, int blocks, int per_cu_cap, int threads, si
 }
 
 unsigned unit_words(const LaunchCfg &cfg) {
-    if (cfg.dense) return 3 * even(cfg.kmax) + 2 * cfg.kmax * cfg.wmax + 2 * cfg.wmax;
+    // even: every unit's area starts 8-byte aligned; at least 16 words: the
+    // area takes the unit's exit record (eight 64-bit values)
+    if (cfg.dense) return std::max(16u, 3 * even(cfg.kmax) + 2 * cfg.kmax * cfg.wmax + 2 * cfg.wmax);
     unsigned E = cfg.kmax + cfg.lanes;
     unsigned UW = (cfg.nmax + 31) / 32;
-    return even(13 * cfg.kmax + 3 * E + UW);   // even: every unit's area starts 8-byte aligned
+    return std::max(16u, even(13 * cfg.kmax + 3 * E + UW));
 }
 
 // Largest block (256, 128 or 64 threads) whose units fit in 64 KiB of LDS.
