@@ -77,13 +77,6 @@ __device__ __forceinline__ unsigned long long wave_max(unsigned long long x) {
     return x;
 }
 
-// value of lane l (uniform l) of a 64-bit per-lane value
-__device__ __forceinline__ unsigned long long readlane64(unsigned long long v, uint32_t l) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, (int)l);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)l);
-    return ((unsigned long long)hi << 32) | lo;
-}
-
 // bits of word t (nodes 64t .. 64t+63) that lie in [lo, hi)
 __device__ __forceinline__ unsigned long long range_mask(uint32_t t, uint32_t lo, uint32_t hi) {
     const unsigned long long base = (unsigned long long)t * 64;
@@ -126,10 +119,10 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
     if (tid == 0) s_empty = 0;
     __syncthreads();
 
-    // pattern node data by lane (lane u: node u), read back with readlane
+    // pattern node data by lane (lane u: node u)
     const bool mine = (uint32_t)lane < k;
     const unsigned long long mynb = mine ? s_nb[lane] : 0ull;
-    const uint32_t mylab = mine ? s_lab[lane] : 0u, mydeg = mine ? s_deg[lane] : 0u;
+    const uint32_t mydeg = mine ? s_deg[lane] : 0u;
 
     // label and degree domains; lane l of a wave decides node 64 i + l
     for (uint32_t i = wave; i < W; i += PLAN_WAVES) {
@@ -142,9 +135,10 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
             vd = r.deg;
         }
         unsigned long long row = 0;
+        // the pattern node's label and degree are uniform LDS reads (broadcasts)
+#pragma unroll 4
         for (uint32_t u = 0; u < k; u++) {
-            const uint32_t lu = (uint32_t)__builtin_amdgcn_readlane((int)mylab, (int)u);
-            const uint32_t du = (uint32_t)__builtin_amdgcn_readlane((int)mydeg, (int)u);
+            const uint32_t lu = s_lab[u], du = s_deg[u];
             const bool p = valid && (lu == LABEL_ANY || vl == lu) && vd >= du;
             const unsigned long long b = __ballot(p);
             if ((uint32_t)lane == u) row = b;
@@ -370,12 +364,25 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
         }
         while (len < k) {
             // w_n(u) counts the placed w sharing an unplaced neighbour x with u:
-            // the placed members of the union of N(x) over unplaced x in N(u)
+            // the placed members of the union of N(x) over unplaced x in N(u).
+            // N(x) comes from LDS at a uniform address (one broadcast read),
+            // four unplaced x at a time so that the reads overlap; a repeated
+            // x at the end of the set adds nothing to the union
             unsigned long long two_hop = 0;
-            for (unsigned long long m = all & ~placed; m; m &= m - 1) {
-                const uint32_t x = (uint32_t)__builtin_ctzll(m);
-                const unsigned long long nbx = readlane64(mynb, x);
-                if ((mynb >> x) & 1ull) two_hop |= nbx;
+            for (unsigned long long m = all & ~placed; m;) {
+                const uint32_t x0 = (uint32_t)__builtin_ctzll(m);
+                m &= m - 1;
+                const uint32_t x1 = m ? (uint32_t)__builtin_ctzll(m) : x0;
+                m &= m ? m - 1 : 0ull;
+                const uint32_t x2 = m ? (uint32_t)__builtin_ctzll(m) : x0;
+                m &= m ? m - 1 : 0ull;
+                const uint32_t x3 = m ? (uint32_t)__builtin_ctzll(m) : x0;
+                m &= m ? m - 1 : 0ull;
+                const unsigned long long n0 = s_nb[x0], n1 = s_nb[x1], n2 = s_nb[x2], n3 = s_nb[x3];
+                two_hop |= n0 & (0ull - ((mynb >> x0) & 1ull));
+                two_hop |= n1 & (0ull - ((mynb >> x1) & 1ull));
+                two_hop |= n2 & (0ull - ((mynb >> x2) & 1ull));
+                two_hop |= n3 & (0ull - ((mynb >> x3) & 1ull));
             }
             unsigned long long key = 0;
             if (mine && !((placed >> lane) & 1ull)) {
@@ -387,8 +394,11 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
                       ((unsigned long long)mydeg << 38) | ((unsigned long long)(use_si ? ~mysz : 0u) << 6) |
                       (unsigned long long)(63 - lane);
             }
-            key = wave_max(key);
-            const uint32_t u = 63u - (uint32_t)(key & 63ull);
+            // the keys are distinct (their lowest bits are the lane), so one
+            // lane holds the maximum; its ballot names it as a wave-uniform
+            // value, which keeps `placed` and the loop above scalar
+            const unsigned long long best = wave_max(key);
+            const uint32_t u = (uint32_t)__builtin_ctzll(__ballot(key == best));
             if (lane == 0) s_order[len] = u;
             len++;
             placed |= 1ull << u;
