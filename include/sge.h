@@ -176,10 +176,17 @@ sge_status sge_batch_run(sge_ctx *ctx, uint32_t njobs, const sge_job *jobs, sge_
 sge_status sge_set_batch_policy(sge_ctx *ctx, int policy);
 
 /* ----------------------------------------------------------------- serving */
-/* Start the resident server: a persistent kernel that takes queries from a
- * ring as they arrive.  slots = maximum queries in flight; arena_bytes =
- * device memory for per-query plans and domains (admission is by this
- * memory and by free slots). */
+/* Start the server: continuous batching of queries on the context's
+ * resident targets and patterns.  Admitted queries are planned by host
+ * threads (or by the plan kernel at the head of their launch when the plan
+ * location is 1) and packed, whatever is ready, into one persistent search
+ * launch on the first idle of four launch lanes (HIP streams with their own
+ * scheduler state), so queries that arrive while others run start at once
+ * beside them.  slots = maximum queries in flight; arena_bytes = device
+ * memory for per-query plans and domains (admission is by this memory and by
+ * free slots; a query larger than the whole arena is SGE_E_NOMEM at submit).
+ * SGE_E_INVAL if the server already runs or slots or arena_bytes is 0;
+ * SGE_E_DEVICE if its streams cannot be created. */
 sge_status sge_serve_start(sge_ctx *ctx, uint32_t slots, uint64_t arena_bytes);
 /* Submit one query (job->mode / labelled apply).  SGE_E_BUSY when no slot
  * or memory is free now.  *ticket identifies the query. */

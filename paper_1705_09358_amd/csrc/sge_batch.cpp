@@ -57,9 +57,9 @@ sge_status sge_batch_run(sge_ctx *c, uint32_t njobs, const sge_job *jobs, sge_re
         }
         auto it = c->batch_tune.find(key);
         if (it == c->batch_tune.end()) {
-            // autotune on this batch, one knob at a time from the default shape
-            // (root chunks, automatic width, default donation period, all
-            // resident blocks): resident blocks per CU, then the unit width
+            // autotune on this batch, starting from the default shape (root
+            // chunks, automatic width, default donation period, all resident
+            // blocks): resident blocks per CU, then the unit width
             // and the donation period together, then one unit per job.  A knob
             // the caller set is kept.  A short launch is run once more and then
             // timed three times (the median counts); a shape already timed (the
