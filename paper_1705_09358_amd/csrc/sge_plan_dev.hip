@@ -136,7 +136,6 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
         }
         unsigned long long row = 0;
         // the pattern node's label and degree are uniform LDS reads (broadcasts)
-#pragma unroll 4
         for (uint32_t u = 0; u < k; u++) {
             const uint32_t lu = s_lab[u], du = s_deg[u];
             const bool p = valid && (lu == LABEL_ANY || vl == lu) && vd >= du;
