@@ -234,6 +234,7 @@ void sge_destroy(sge_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     for (auto &kv : c->targets) free_target(*kv.second);
     for (auto &kv : c->patterns) free_pattern(*kv.second);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     c->bufs.release();
     c->d_rows.release();
     if (c->ev0) (void)hipEventDestroy(c->ev0);

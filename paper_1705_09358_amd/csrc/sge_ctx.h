@@ -92,6 +92,10 @@ struct sge_ctx {
     uint32_t last_units = 0;         // last launch: units that entered the search loop
     int last_lanes = 0;              // last launch: lanes per search unit
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // the last batch launch's executable graph and the key of everything it
+    // captured (sizes, launch shape, buffer addresses, settings)
+    hipGraphExec_t gexec = nullptr;
+    uint64_t gexec_key = 0;
     std::unique_ptr<sge::Server, sge::ServerDeleter> server;
     std::mutex serve_mu;
 };

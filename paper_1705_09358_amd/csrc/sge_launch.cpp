@@ -376,6 +376,31 @@ void read_pack(const sge_ctx *c, Pack &pk, const LaunchBufs &bufs, const std::ve
     }
 }
 
+// Everything a captured batch graph depends on besides the contents of the
+// descriptor buffer: the stream, the pack's sizes and launch shape, the
+// buffer addresses and the context settings the kernels receive.
+static uint64_t graph_key(const sge_ctx *c, const Pack &pk, const LaunchBufs &b, hipStream_t s) {
+    uint64_t h = 1469598103934665603ull;   // FNV-1a over 64-bit words
+    auto mix = [&](uint64_t v) {
+        for (int i = 0; i < 8; i++) {
+            h ^= (v >> (8 * i)) & 0xFFu;
+            h *= 1099511628211ull;
+        }
+    };
+    const LaunchCfg &g = pk.cfg;
+    for (uint64_t v : {(uint64_t)(uintptr_t)s, (uint64_t)pk.device_plan, (uint64_t)pk.m, (uint64_t)pk.upload,
+                       (uint64_t)pk.off_req, (uint64_t)pk.ctr_bytes, (uint64_t)pk.policy, (uint64_t)pk.units,
+                       (uint64_t)g.lanes, (uint64_t)g.dense, (uint64_t)g.donate, (uint64_t)g.kmax, (uint64_t)g.nmax,
+                       (uint64_t)g.wmax, (uint64_t)g.blocks, (uint64_t)g.per_cu, (uint64_t)g.used_bitset,
+                       (uint64_t)g.general, (uint64_t)(uintptr_t)b.d_blob.p, (uint64_t)(uintptr_t)b.h_blob.p,
+                       (uint64_t)(uintptr_t)b.h_ctr.p, (uint64_t)(uintptr_t)b.work.sched,
+                       (uint64_t)(uintptr_t)b.work.queue, (uint64_t)(uintptr_t)b.work.ctr,
+                       (uint64_t)(uintptr_t)b.work.inst, (uint64_t)(uintptr_t)b.work.chunk_prefix,
+                       (uint64_t)c->root_chunk, (uint64_t)c->cap, (uint64_t)c->time_limit_ms, (uint64_t)c->num_cus})
+        mix(v);
+    return h;
+}
+
 sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std::vector<InstanceOut> &out,
                          double &ms_prep, double &ms_search, bool graph, int policy) {
     auto t0 = clk::now();
@@ -455,25 +480,41 @@ sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std
     ms_prep = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
     hipError_t e;
     if (graph) {
-        // one graph: plan upload, scheduler reset, the persistent search, read-back
-        hipGraph_t g = nullptr;
-        hipGraphExec_t ge = nullptr;
-        if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-            return hip_fail(c, e, "hipStreamBeginCapture");
-        hipError_t er = enqueue_pack(c, pk, c->bufs, s);
-        e = hipStreamEndCapture(s, &g);
-        if (er != hipSuccess || e != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return hip_fail(c, er != hipSuccess ? er : e, "capture search graph");
+        // one graph: plan upload, scheduler reset, the persistent search,
+        // read-back.  The executable graph is kept and launched again while
+        // everything it captured is unchanged: the launch shape, the sizes, the
+        // buffer addresses and the settings passed to the kernels.  Its upload
+        // node copies the pinned descriptor buffer as the host has just
+        // refilled it, so each launch plans and searches the current jobs.
+        const uint64_t key = graph_key(c, pk, c->bufs, s);
+        if (!c->gexec || c->gexec_key != key) {
+            if (c->gexec) {
+                (void)hipGraphExecDestroy(c->gexec);   // the stream is idle: every launch was waited for
+                c->gexec = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ge = nullptr;
+            if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                return hip_fail(c, e, "hipStreamBeginCapture");
+            hipError_t er = enqueue_pack(c, pk, c->bufs, s);
+            e = hipStreamEndCapture(s, &g);
+            if (er != hipSuccess || e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return hip_fail(c, er != hipSuccess ? er : e, "capture search graph");
+            }
+            e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+            c->gexec = ge;
+            c->gexec_key = key;
         }
-        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
-        // the executable graph owns the launch's kernel arguments: it is destroyed
-        // only after the stream has drained
-        e = hipGraphLaunch(ge, s);
+        e = hipGraphLaunch(c->gexec, s);
         hipError_t es = hipStreamSynchronize(s);
-        (void)hipGraphExecDestroy(ge);
+        if (e != hipSuccess || es != hipSuccess) {
+            // an executable graph whose launch failed is not reused
+            (void)hipGraphExecDestroy(c->gexec);
+            c->gexec = nullptr;
+        }
         if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
         if (es != hipSuccess) return hip_fail(c, es, "search");
     } else {

@@ -157,6 +157,55 @@ def test_batch_state_cap(ctx):
             assert r.states > cap
 
 
+def test_batch_graph_reuse(ctx):
+    """The batch graph is launched again while the launch is unchanged: every
+    repeat (with eager single searches between them) must match the oracle,
+    a changed state cap must take effect at once and be lifted again, and a
+    different job list of the same size must give its own results."""
+    man = manifest("c2")
+    rows = man["instances"][:10]
+    other = man["instances"][10:20]
+    insts = [synth.c2_instance(r["j"], r["attempt"]) for r in rows]
+    insts2 = [synth.c2_instance(r["j"], r["attempt"]) for r in other]
+    jobs = load_jobs(ctx, insts)
+    jobs2 = load_jobs(ctx, insts2)
+    want = [(w["matches"], w["states"]) for w in rows]
+    want2 = [(w["matches"], w["states"]) for w in other]
+    ctx.set_batch_policy(2)
+    ctx.set_plan_location(1)
+    ctx.set_mode(sge.RI)          # the single searches below: as the jobs (RI, labelled)
+    ctx.set_labelled(True)
+    try:
+        for rep in range(3):
+            _note(f"batch graph reuse: repeat {rep}")
+            st, res = ctx.batch_run(jobs)
+            assert st == sge.OK and [(r.matches, r.states) for r in res] == want
+            single = ctx.count(jobs[rep][0], jobs[rep][1])   # eager work between the launches
+            assert (single.matches, single.states) == want[rep]
+        cap = sorted(w["states"] for w in rows)[5]
+        ctx.set_state_cap(cap)
+        st, res = ctx.batch_run(jobs, allow=(sge.OK, sge.E_ABORTED))
+        assert st == sge.E_ABORTED
+        for r, w in zip(res, rows):
+            if w["states"] <= cap:
+                assert (r.matches, r.states) == (w["matches"], w["states"])
+            else:
+                assert r.states > cap
+        ctx.set_state_cap(0)
+        st, res = ctx.batch_run(jobs)
+        assert st == sge.OK and [(r.matches, r.states) for r in res] == want
+        st, res = ctx.batch_run(jobs2)
+        assert st == sge.OK and [(r.matches, r.states) for r in res] == want2
+        st, res = ctx.batch_run(jobs)
+        assert st == sge.OK and [(r.matches, r.states) for r in res] == want
+    finally:
+        ctx.set_state_cap(0)
+        ctx.set_batch_policy(0)
+        ctx.set_plan_location(-1)
+        unload(ctx, jobs)
+        unload(ctx, jobs2)
+
+
 _UNITS = {}
 
 
