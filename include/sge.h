@@ -166,8 +166,10 @@ typedef struct {
 } sge_job;
 
 /* Search all jobs in one persistent launch (captured, with the upload of the
- * job descriptors, the plan kernel and the read-back, in one HIP graph per
- * call).  results[njobs] receives each job's counters; the state cap of
+ * job descriptors, the plan kernel and the read-back, in one HIP graph, which
+ * the context keeps and launches again while the launch shape, sizes,
+ * buffers and settings are unchanged).  results[njobs] receives each job's
+ * counters; the state cap of
  * the context applies per job.  Returns SGE_E_ABORTED if any job was capped
  * (its counters are partial); the others are complete. */
 sge_status sge_batch_run(sge_ctx *ctx, uint32_t njobs, const sge_job *jobs, sge_result *results);
