@@ -42,12 +42,10 @@ sge_status sge_batch_run(sge_ctx *c, uint32_t njobs, const sge_job *jobs, sge_re
     const int saved_lanes = c->lanes, saved_donate = c->donate, saved_per_cu = c->per_cu;
     if (policy == 0) {
         // repeated runs of one batch (the same jobs) reuse the choice
-        uint64_t key = 1469598103934665603ull;   // FNV-1a over the job list
+        uint64_t key = 1469598103934665603ull;   // a multiplicative hash of the job list, word by word
         auto mix = [&](uint64_t v) {
-            for (int b = 0; b < 8; b++) {
-                key ^= (v >> (8 * b)) & 0xFFu;
-                key *= 1099511628211ull;
-            }
+            key = (key ^ v) * 0x9E3779B97F4A7C15ull;
+            key ^= key >> 29;
         };
         mix(njobs);
         for (uint32_t i = 0; i < njobs; i++) {

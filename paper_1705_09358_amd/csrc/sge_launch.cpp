@@ -174,12 +174,13 @@ sge_status pack_instances(sge_ctx *c, const std::vector<const InstanceSpec *> &s
     // of the largest plans start first and the kernel has no long tail;
     // each request carries its own output addresses, so the order is free
     std::vector<uint32_t> by_cost(m), slot(m);
-    for (uint32_t j = 0; j < m; j++) by_cost[j] = j;
-    auto cost = [&](uint32_t j) {
+    std::vector<uint64_t> cost(m);   // computed once: the sort then reads one array
+    for (uint32_t j = 0; j < m; j++) {
         const InstanceSpec &sp = *specs[j];
-        return (uint64_t)sp.p->g.n * sp.t->g.n * (sp.mode != SGE_RI ? 4u : 1u);
-    };
-    std::stable_sort(by_cost.begin(), by_cost.end(), [&](uint32_t a, uint32_t b) { return cost(a) > cost(b); });
+        by_cost[j] = j;
+        cost[j] = (uint64_t)sp.p->g.n * sp.t->g.n * (sp.mode != SGE_RI ? 4u : 1u);
+    }
+    std::stable_sort(by_cost.begin(), by_cost.end(), [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
     for (uint32_t r = 0; r < m; r++) slot[by_cost[r]] = r;
     for (uint32_t j = 0; j < m; j++) {
         const InstanceSpec &sp = *specs[j];
