@@ -33,9 +33,11 @@ namespace sge {
 namespace {
 
 // Workgroup size: 1024 threads, so each plan's latency-bound phases spread
-// over 16 waves.  A launch takes as long as its largest plan: with 256-thread
-// workgroups (more plans resident per CU) the 4096-plan batch took 2.96 ms,
-// its largest plan alone 2.9 ms; with 1024 threads 2.04 ms.
+// over 16 waves.  With 256-thread workgroups (more plans resident per CU) a
+// 4096-plan batch took as long as its largest plan, 2.96 ms of which that
+// plan alone took 2.9 ms; with 1024 threads the largest plan takes about
+// 1 ms and the batch about 2 ms, bound by the one workgroup per CU that
+// resides at a time.
 constexpr int PLAN_THREADS = 1024;
 
 // Device memory in the global address space: the pointers a plan request
