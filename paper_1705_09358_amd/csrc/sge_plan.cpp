@@ -142,16 +142,40 @@ void build_plan(const Target &t, const HostGraph &p, int mode, bool labelled, ui
             // degree is at least w's, which the target's table answers
             // (one pass over D(u) per pattern neighbour w, reading w's column
             // 64 nodes at a time; pattern degrees are below 64)
+            // Pattern nodes sharing a (label column, degree) key share the
+            // row "has a neighbour of that label with at least that degree":
+            // each word of a key's row is computed once, when a domain of a
+            // pattern neighbour first needs it (words a domain no longer
+            // holds are skipped, as before), and then reused.
             const uint32_t C = t.nbr_cols;
+            uint32_t key_of[KMAX], nkeys = 0;
+            uint64_t keys[KMAX];
+            for (uint32_t w = 0; w < k; w++) {
+                const uint64_t key = ((uint64_t)(lab[w] == LABEL_ANY ? C - 1 : lab[w]) << 8) | std::min<uint32_t>(deg[w], 255);
+                uint32_t j = 0;
+                while (j < nkeys && keys[j] != key) j++;
+                if (j == nkeys) keys[nkeys++] = key;
+                key_of[w] = j;
+            }
+            const uint32_t WB = (W + 63) / 64;   // words of the per-key "computed" bitmaps
+            std::vector<uint64_t> rows((size_t)nkeys * W), done((size_t)nkeys * WB, 0);
             for (uint32_t u = 0; u < k; u++) {
                 if (!nb[u]) continue;
                 uint64_t *d = &D[(size_t)u * W];
                 for (uint64_t m = nb[u]; m; m &= m - 1) {
                     const uint32_t w = (uint32_t)__builtin_ctzll(m);
-                    const uint8_t *cl = &t.nbr_deg[(size_t)(lab[w] == LABEL_ANY ? C - 1 : lab[w]) * t.nbr_stride];
+                    const uint32_t j = key_of[w];
+                    uint64_t *row = &rows[(size_t)j * W];
+                    uint64_t *dn = &done[(size_t)j * WB];
+                    const uint8_t *cl = &t.nbr_deg[(size_t)(keys[j] >> 8) * t.nbr_stride];
+                    const uint8_t dmin = (uint8_t)(keys[j] & 0xFF);
                     for (uint32_t i = 0; i < W; i++) {
                         if (!d[i]) continue;
-                        const uint64_t keep = d[i] & bytes_at_least(cl + (size_t)i * 64, (uint8_t)deg[w]);
+                        if (!((dn[i >> 6] >> (i & 63)) & 1)) {
+                            row[i] = bytes_at_least(cl + (size_t)i * 64, dmin);
+                            dn[i >> 6] |= 1ull << (i & 63);
+                        }
+                        const uint64_t keep = d[i] & row[i];
                         if (keep != d[i]) {
                             d[i] = keep;
                             dirty |= 1ull << u;
