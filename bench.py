@@ -263,16 +263,20 @@ def measured_traffic():
 
 
 def host_cpu():
-    """The host's processor model and the cores this process may use."""
-    model = None
+    """The host's processor model, its current clock as the kernel reports it
+    (first core, MHz) and the cores this process may use."""
+    model = mhz = None
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
+            if model is None and line.startswith("model name"):
                 model = line.split(":", 1)[1].strip()
+            elif mhz is None and line.startswith("cpu MHz"):
+                mhz = float(line.split(":", 1)[1])
+            if model is not None and mhz is not None:
                 break
-    except OSError:
+    except (OSError, ValueError):
         pass
-    return dict(cpu_model=model, host_cores=len(os.sched_getaffinity(0)))
+    return dict(cpu_model=model, cpu_mhz=mhz, host_cores=len(os.sched_getaffinity(0)))
 
 
 def measured_l2(kernel_ms):

@@ -40,6 +40,7 @@ def test_host_cpu_description():
     h = bench.host_cpu()
     assert h["host_cores"] >= 1
     assert h["cpu_model"] is None or isinstance(h["cpu_model"], str)
+    assert h["cpu_mhz"] is None or h["cpu_mhz"] > 0
 
 
 def test_oracle_pool_reproduces_stored_counts():
