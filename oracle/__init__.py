@@ -75,11 +75,13 @@ def _graph_args(g):
 
 def run(pattern, target, mode: int, labelled: bool, state_cap: int = 0, rows: bool = False,
         cap_rows: int = 1 << 20, root_range=(0, 0xFFFFFFFF)) -> dict:
-    """Enumerate; returns {status, matches, states, candidates, alg_bytes, rows?}.
-    root_range restricts the first node of the order to target nodes in [lo, hi)."""
+    """Enumerate; returns {status, matches, states, candidates, alg_bytes,
+    dense_bytes, rows?}.  The byte counts are those of a count-only search (an
+    enumeration also writes 4k bytes per match).  root_range restricts the
+    first node of the order to target nodes in [lo, hi)."""
     keep_p, pa = _graph_args(pattern)
     keep_t, ta = _graph_args(target)
-    cnt = np.zeros(4, dtype=np.uint64)
+    cnt = np.zeros(5, dtype=np.uint64)
     buf = np.zeros((cap_rows if rows else 0, max(pattern.n, 1)), dtype=np.uint32)
     rc = lib().oracle_run_ex(pattern.n, *pa, target.n, *ta, int(mode), int(bool(labelled)), int(state_cap),
                              int(root_range[0]), int(root_range[1]),
@@ -87,7 +89,7 @@ def run(pattern, target, mode: int, labelled: bool, state_cap: int = 0, rows: bo
     if rc < 0:
         raise ValueError(f"oracle rejected the input (code {rc})")
     out = dict(status=rc, matches=int(cnt[0]), states=int(cnt[1]), candidates=int(cnt[2]),
-               alg_bytes=int(cnt[3]))
+               alg_bytes=int(cnt[3]), dense_bytes=int(cnt[4]))
     if rows:
         nr = min(out["matches"], cap_rows)
         out["rows"] = buf[:nr, :pattern.n].copy()

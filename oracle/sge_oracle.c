@@ -60,8 +60,11 @@
  *   - Edge labels are compared exactly when node labels are (labelled).
  *
  * Counters: `states` = accepted (position, target) pairs (consistent prefix
- * assignments); `candidates` = pairs considered; `alg_bytes` = bytes the method
- * must read per the per-unit model below; `matches` = complete mappings.
+ * assignments); `candidates` = pairs considered; `alg_bytes` = bytes a search
+ * must read per the sparse per-unit model below; `dense_bytes` = the same for
+ * a search on adjacency bitsets; `matches` = complete mappings.  Neither byte
+ * count includes the rows an enumeration writes (4k bytes per match), so both
+ * are the figures of a count-only search.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -171,7 +174,8 @@ typedef struct {
     int32_t parent[64];   /* position -> earlier position, or -1 */
     uint32_t M[64];       /* position -> target node */
     unsigned char *used;  /* n */
-    uint64_t matches, states, candidates, alg_bytes;
+    uint64_t matches, states, candidates, alg_bytes, dense_bytes;
+    uint64_t W;           /* 64-bit words of one target adjacency bitset row */
     uint32_t *rows;
     uint64_t cap_rows;
     uint32_t root_lo, root_hi;  /* first position restricted to target nodes in [lo, hi) */
@@ -314,25 +318,36 @@ static void make_order(oracle_t *o) {
 }
 
 /*
- * Algorithmic bytes, sparse model: 8 B for the bounds of each neighbour list
+ * Algorithmic bytes.  Sparse model: 8 B for the bounds of each neighbour list
  * read plus 4 B per id in it; per candidate 5 B (RI: label byte and degree
- * word) or 8 B (RI-DS: one domain word); 8 B per back-edge probe performed;
- * 4k B per row written.  For a parentless position the candidate ids are
- * implicit (RI) or 4 B each from the domain list (RI-DS).
+ * word) or 8 B (RI-DS: one domain word); 8 B per back-edge probe performed (the
+ * probes of a candidate stop at the first that fails).  For a parentless
+ * position the candidate ids are implicit (RI) or 4 B each from the domain list
+ * (RI-DS).  Dense model (a search whose target rows are bitsets of W words):
+ * each expansion of a position reads W words of the domain (or label and
+ * degree) row, W of the parent image's adjacency row when there is a parent,
+ * and W of each earlier neighbour's row other than the parent.
  */
+static uint32_t back_count(const oracle_t *o, uint32_t i) {
+    uint32_t c = 0;
+    for (uint32_t j = 0; j < i; j++)
+        if ((int32_t)j != o->parent[i] && pattern_adj(o, o->order[i], o->order[j])) c++;
+    return c;
+}
+
 static void search(oracle_t *o, uint32_t i) {
     if (o->aborted) return;
     if (i == o->k) {
         if (o->rows && o->matches < o->cap_rows) {
             uint32_t *r = o->rows + o->matches * o->k;
             for (uint32_t j = 0; j < o->k; j++) r[o->order[j]] = o->M[j];
-            o->alg_bytes += 4ull * o->k;
         }
         o->matches++;
         return;
     }
     uint32_t u = o->order[i];
     int use_dom = o->mode != OR_RI;
+    o->dense_bytes += 8ull * o->W * (1u + (o->parent[i] >= 0) + back_count(o, i));
     uint32_t lo, hi;
     const uint32_t *list = NULL, *labs = NULL;
     uint32_t pu = 0, pv = 0, plab = 0;
@@ -439,6 +454,7 @@ static int oracle_setup(oracle_t *o, uint32_t k, const uint32_t *prp, const uint
     o->directed = pdir || tdir;
     o->k = k;
     o->n = n;
+    o->W = ((uint64_t)n + 63) / 64;
     o->mode = mode;
     o->labelled = labelled;
     o->used = (unsigned char *)calloc(n ? n : 1, 1);
@@ -479,7 +495,8 @@ int oracle_plan_ex(uint32_t k, const uint32_t *prp, const uint32_t *pcol, const 
 }
 
 /*
- * Full run.  counters[0..3] = matches, states, candidates, alg_bytes.  Rows
+ * Full run.  counters[0..4] = matches, states, candidates, alg_bytes,
+ * dense_bytes.  Rows
  * (pattern-id order) are written for the first cap_rows matches when rows is
  * given.  The first pattern node of the order is restricted to target nodes in
  * [root_lo, root_hi) (a shard of the search; 0 and UINT32_MAX for all).
@@ -506,6 +523,7 @@ int oracle_run_ex(uint32_t k, const uint32_t *prp, const uint32_t *pcol, const u
     counters[1] = o.states;
     counters[2] = o.candidates;
     counters[3] = o.alg_bytes;
+    counters[4] = o.dense_bytes;
     rc = o.aborted ? OR_ABORTED : OR_OK;
     oracle_free(&o);
     return rc;

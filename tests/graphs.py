@@ -250,3 +250,67 @@ def brute_ac_domains(P: Graph, T: Graph, labelled: bool) -> np.ndarray:
                     D[u, v] = False
                     changed = True
     return D
+
+
+def brute_bytes(P: Graph, T: Graph, labelled: bool, mode: int, order, parent, domains) -> tuple[int, int]:
+    """Algorithmic bytes of a count-only search by the per-unit model, summed
+    over the consistent prefixes found by brute force (undirected graphs
+    without edge labels).  Every consistent prefix of positions 0..i-1 (the
+    empty prefix for i = 0) is expanded once at position i < k.
+
+    Sparse model, per expansion: with a parent, 8 bytes of list bounds and 4
+    per id in the parent image's neighbour list; without one, nothing (RI: all
+    target ids) or 4 bytes per member of the domain (RI-DS).  Per candidate, 5
+    bytes (RI) or 8 (RI-DS); a candidate that passes the unary checks and is
+    unused has its back-edges probed at 8 bytes each, earliest position first,
+    up to and including the first one that fails.  Dense model, per expansion:
+    8W bytes for the domain row, 8W for the parent row (when there is a
+    parent) and 8W per back-edge row.  Returns (sparse, dense)."""
+    AT = adjacency(T)
+    AP = adjacency(P)
+    tdeg = T.degrees()
+    pdeg = P.degrees()
+    k, n = P.n, T.n
+    use_dom = mode != 0
+    W = (n + 63) // 64
+    order = [int(u) for u in order]
+
+    def unary(u, v):
+        if labelled and P.labels[u] != T.labels[v]:
+            return False
+        if pdeg[u] > tdeg[v]:
+            return False
+        return not use_dom or bool(domains[u, v])
+
+    def consistent(m):
+        us = order[:len(m)]
+        if not all(unary(us[i], m[i]) for i in range(len(m))):
+            return False
+        return all(AT[m[i], m[j]] for i in range(len(m)) for j in range(i) if AP[us[i], us[j]])
+
+    sparse = dense = 0
+    for i in range(k):
+        u = order[i]
+        par = int(parent[i])
+        back = [j for j in range(i) if j != par and AP[order[j], u]]
+        for m in itertools.permutations(range(n), i):
+            if not consistent(m):
+                continue
+            dense += 8 * W * (1 + (par >= 0) + len(back))
+            if par >= 0:
+                cands = np.flatnonzero(AT[m[par]])
+                sparse += 8 + 4 * len(cands)
+            elif use_dom:
+                cands = np.flatnonzero(domains[u])
+                sparse += 4 * len(cands)
+            else:
+                cands = range(n)
+            for v in cands:
+                sparse += 8 if use_dom else 5
+                if v in m or not unary(u, v):
+                    continue
+                for j in back:
+                    sparse += 8
+                    if not AT[m[j], v]:
+                        break
+    return sparse, dense

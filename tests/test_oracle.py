@@ -339,3 +339,104 @@ def test_root_shards_partition_the_search(orc):
     order0 = orc.plan(inst.pattern, inst.target, 0, True)["order"][0]
     for p, (lo, hi) in zip(parts, [(0, 1000), (1000, 1001), (1001, 3000)]):
         assert all(lo <= r[order0] < hi for r in p["rows"])
+
+
+# ------------------------------------------------- algorithmic bytes (roofline numerator)
+# The byte model (bytes a search must read, per unit of work): sparse, per
+# expansion with a parent 8 + 4 deg(parent image); per candidate 5 B (RI) or
+# 8 B (RI-DS); per parentless RI-DS candidate 4 B more (the domain list); 8 B
+# per back-edge probe up to the first failure.  Dense, per expansion 8W bytes
+# per row read: domain, parent (if any), each back-edge.  Neither counts rows.
+
+@pytest.mark.parametrize("seed", range(60))
+def test_bytes_brute_force_tiny(orc, seed):
+    """The oracle's byte counters equal the model summed over the consistent
+    prefixes that a brute force finds (the DFS itself is not used)."""
+    g = np.random.default_rng(10_000 + seed)
+    n = int(g.integers(3, 8))
+    k = int(g.integers(2, min(5, n) + 1))
+    nlab = int(g.integers(1, 3))
+    T = G.random_graph(g, n, float(g.uniform(0.3, 0.9)), nlab)
+    P = G.random_graph(g, k, float(g.uniform(0.4, 1.0)), nlab)
+    labelled = bool(g.integers(0, 2))
+    for mode in MODES:
+        pl = orc.plan(P, T, mode, labelled)
+        r = orc.run(P, T, mode, labelled)
+        if pl["empty"]:
+            assert r["alg_bytes"] == 0 and r["dense_bytes"] == 0
+            continue
+        want = G.brute_bytes(P, T, labelled, mode, pl["order"], pl["parent"], pl["domains"])
+        assert (r["alg_bytes"], r["dense_bytes"]) == want, (seed, mode)
+
+
+@pytest.mark.parametrize("n,k", [(6, 1), (6, 3), (7, 4), (6, 6), (9, 5), (70, 3)])
+@pytest.mark.parametrize("mode", MODES)
+def test_bytes_clique_in_clique_closed_form(orc, n, k, mode):
+    """K_k in K_n, unlabelled.  The order is 0..k-1 with every parent at
+    position 0 and back(i) = {1..i-1}.  Position 0 reads no list: its n
+    candidates cost 5 B each in RI, 4 + 8 B in RI-DS.  Position i >= 1 is
+    expanded once per injective i-prefix (P(n, i) of them): 8 + 4(n-1) bytes
+    of the parent's list, n-1 candidates, of which n-i are unused and probe all
+    i-1 back-edges successfully."""
+    r = orc.run(G.complete(k), G.complete(n), mode, False)
+    per_cand = 5 if mode == 0 else 8
+    root = 5 * n if mode == 0 else 12 * n
+    want = root + sum(math.perm(n, i) * (8 + 4 * (n - 1) + per_cand * (n - 1) + 8 * (i - 1) * (n - i))
+                      for i in range(1, k))
+    W = (n + 63) // 64
+    want_dense = 8 * W * (1 + sum(math.perm(n, i) * (i + 1) for i in range(1, k)))
+    assert r["alg_bytes"] == want
+    assert r["dense_bytes"] == want_dense
+
+
+def _k4_bytes(T):
+    """Closed form of the byte counters for K_4 in a target T (RI, unlabelled),
+    from the adjacency matrix.  The order is 0,1,2,3, every parent at position
+    0, back(2) = {1}, back(3) = {1, 2}.  s = nodes of degree >= 3 (rule 3),
+    B = A restricted to them.  A state (v0, v1) probes v1's row once for each
+    other qualifying neighbour v2 of v0 ((B1)_v0 - 1 of them); a state
+    (v0, v1, v2) probes v1's row for each qualifying neighbour v3 of v0 other
+    than v1 and v2, and v2's row only when that first probe succeeds
+    ((B^2)_{v0 v1} - 1 of them: v2 itself is a common neighbour)."""
+    A = G.adjacency(T).astype(np.int64)
+    n = T.n
+    d = A.sum(1)
+    s = (d >= 3).astype(np.int64)
+    B = A * np.outer(s, s)
+    B2 = B @ B
+    r1 = B.sum(1)
+    f = 8 + 9 * d                                      # list bounds + 4 B/id + 5 B/candidate
+    pos0 = 5 * n
+    pos1 = int((s * f).sum())
+    pos2 = int((B * (f + 8 * (r1 - 1))[:, None]).sum())
+    tri = B * B2                                       # (v0, v1) -> number of v2 closing a triangle
+    pos3 = int((tri * (f[:, None] + 8 * ((r1 - 2)[:, None] + B2 - 1))).sum())
+    W = (n + 63) // 64
+    states0, states1, states2 = int(s.sum()), int(B.sum()), int(tri.sum())
+    dense = 8 * W * (1 + 2 * states0 + 3 * states1 + 4 * states2)
+    return pos0 + pos1 + pos2 + pos3, dense
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_bytes_k4_closed_form(orc, seed):
+    g = np.random.default_rng(seed)
+    T = G.random_graph(g, 40, 0.3, 1)
+    r = orc.run(G.complete(4), T, 0, False)
+    assert (r["alg_bytes"], r["dense_bytes"]) == _k4_bytes(T)
+
+
+def test_bytes_k4_closed_form_c1_target(orc):
+    T = synth.c1_instance(0).target
+    r = orc.run(G.complete(4), T, 0, False)
+    assert (r["alg_bytes"], r["dense_bytes"]) == _k4_bytes(T)
+
+
+def test_bytes_exclude_rows(orc):
+    """The byte counters are those of a count-only search: asking for the rows
+    (4k bytes written per match) changes neither."""
+    inst = synth.c1_instance(3)
+    for mode in (0, 3):
+        a = orc.run(inst.pattern, inst.target, mode, True)
+        b = orc.run(inst.pattern, inst.target, mode, True, rows=True)
+        assert b["matches"] > 0
+        assert (a["alg_bytes"], a["dense_bytes"]) == (b["alg_bytes"], b["dense_bytes"])
