@@ -70,6 +70,24 @@ enum { SGE_RI = 0, SGE_RIDS = 1, SGE_RIDS_SI = 2, SGE_RIDS_SI_FC = 3 };
  *              partial mappings summed over their lengths -- independent of
  *              the traversal order and the parallel schedule;
  *  candidates  pairs examined (implementation-dependent, for reporting);
+ *  alg_bytes   the algorithmic bytes of the search: what the method itself
+ *              must read, by a per-unit model of the traversal, the
+ *              numerator of the memory roofline (0 when counting is off,
+ *              sge_set_count_bytes).  It depends on the instance and the
+ *              kernel variant, not on the schedule.  CSR search: per
+ *              expansion of a position with a parent, 8 bytes (list bounds)
+ *              plus 4 per id in the parent image's neighbour list; per
+ *              candidate 5 bytes (RI: label and degree) or 8 (RI-DS: a
+ *              domain word); per back-edge probe 8 bytes, earliest position
+ *              first, up to the first that fails (general graphs: an arc in
+ *              each direction per earlier position, plus 4 bytes for the
+ *              label of the arc a candidate came over and 8 for the reverse
+ *              arc to the parent); a position without a parent costs 5 bytes
+ *              per target node of its range (RI) or 12 per domain member
+ *              (RI-DS) per expansion.  Dense-bitset search: per expansion
+ *              8*ceil(n/64) bytes per row read (the domain row, the parent
+ *              image's row, every back-edge row).  Rows written by
+ *              sge_enumerate (4k bytes per match) are not included;
  *  steals      tasks moved between search units through the work queue;
  *  steps       search-unit steps of the launch (a step maps one candidate
  *              and/or evaluates one group of candidates), for profiling;
@@ -78,7 +96,7 @@ enum { SGE_RI = 0, SGE_RIDS = 1, SGE_RIDS_SI = 2, SGE_RIDS_SI_FC = 3 };
  *              last wave exit, device clock); for a batch or serve launch it
  *              is the whole launch's. */
 typedef struct {
-    uint64_t matches, states, candidates, steals, steps;
+    uint64_t matches, states, candidates, alg_bytes, steals, steps;
     double ms_prep, ms_search;
 } sge_result;
 
@@ -95,6 +113,15 @@ const char *sge_last_error(const sge_ctx *ctx);
  * wave exited (the kernel), ms[1] until the last task finished, ms[2] until
  * termination was detected. */
 sge_status sge_last_launch_timing(const sge_ctx *ctx, double *ms);
+/* The search kernel of the context's last count, enumerate or batch launch
+ * timed by HIP events recorded on the context's stream right before and right
+ * after it (event nodes of the batch graph): *ms receives the elapsed time,
+ * 0 before any launch or when the last call launched nothing. */
+sge_status sge_last_kernel_ms(const sge_ctx *ctx, double *ms);
+/* on = 1 (default): search launches count each instance's alg_bytes;
+ * on = 0: they do not (a few instructions fewer per candidate), and
+ * sge_result.alg_bytes is 0. */
+sge_status sge_set_count_bytes(sge_ctx *ctx, int on);
 /* Occupancy of the same launch (the parallel search of Section 3 as run on
  * the device): *busy_unit_ms receives the sum over search units of the time
  * each held a task, *units the number of units that entered the search loop

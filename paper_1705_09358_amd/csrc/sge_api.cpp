@@ -250,6 +250,18 @@ sge_status sge_last_launch_timing(const sge_ctx *c, double *ms) {
     return SGE_OK;
 }
 
+sge_status sge_last_kernel_ms(const sge_ctx *c, double *ms) {
+    if (!c || !ms) return SGE_E_INVAL;
+    *ms = c->last_event_ms;
+    return SGE_OK;
+}
+
+sge_status sge_set_count_bytes(sge_ctx *c, int on) {
+    if (!c) return SGE_E_INVAL;
+    c->count_bytes = on ? 1 : 0;
+    return SGE_OK;
+}
+
 sge_status sge_last_launch_occupancy(const sge_ctx *c, double *busy_unit_ms, uint32_t *units) {
     if (!c || !busy_unit_ms || !units) return SGE_E_INVAL;
     *busy_unit_ms = c->last_busy_ms;
@@ -423,6 +435,7 @@ static sge_status single(sge_ctx *c, uint32_t target, uint32_t pattern, uint32_t
     res->matches = out[0].matches;
     res->states = out[0].states;
     res->candidates = out[0].candidates;
+    res->alg_bytes = out[0].bytes;
     res->steals = out[0].steals;
     res->steps = out[0].steps;
     res->ms_prep = mp;

@@ -171,6 +171,7 @@ sge_status sge_batch_run(sge_ctx *c, uint32_t njobs, const sge_job *jobs, sge_re
         results[i].matches = out[i].matches;
         results[i].states = out[i].states;
         results[i].candidates = out[i].candidates;
+        results[i].alg_bytes = out[i].bytes;
         results[i].steals = out[i].steals;
         results[i].steps = out[i].steps;
         results[i].ms_prep = mp;

@@ -40,7 +40,7 @@ struct InstanceSpec {
 struct InstanceOut {
     sge_status status = SGE_OK;
     bool timed_out = false;
-    uint64_t matches = 0, states = 0, candidates = 0, steals = 0, steps = 0;
+    uint64_t matches = 0, states = 0, candidates = 0, steals = 0, steps = 0, bytes = 0;
 };
 
 // Buffers of one launch stream.
@@ -78,6 +78,7 @@ struct sge_ctx {
     uint32_t root_chunk = 0;
     int batch_policy = 0;
     int plan_where = -1;   // -1 automatic, 0 host, 1 device
+    int count_bytes = 1;   // search launches count each instance's algorithmic bytes
     // batch autotuner's choice by job list (hash); cleared when tuning changes
     std::map<uint64_t, sge::BatchTune> batch_tune;
     int num_cus = 0;
@@ -91,7 +92,8 @@ struct sge_ctx {
     double last_busy_ms = 0;         // last launch: unit-milliseconds spent holding tasks
     uint32_t last_units = 0;         // last launch: units that entered the search loop
     int last_lanes = 0;              // last launch: lanes per search unit
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // around the search kernel of count, enumerate and batch launches
+    double last_event_ms = 0;                  // last launch: the search kernel between ev0 and ev1
     // the last batch launch's executable graph and the key of everything it
     // captured (sizes, launch shape, buffer addresses, settings)
     hipGraphExec_t gexec = nullptr;
@@ -154,8 +156,11 @@ constexpr size_t PLAN_DEVICE_MIN_INSTANCES = 64;
 bool plan_on_device(const sge_ctx *c, const std::vector<const InstanceSpec *> &specs);
 // A search with a directed graph, or edge labels that are compared.
 bool general_instance(const InstanceSpec &s);
-// Upload, plan, reset, search and read back on `s` (asynchronous).
-hipError_t enqueue_pack(sge_ctx *c, const Pack &pk, LaunchBufs &bufs, hipStream_t s);
+// Upload, plan, reset, search and read back on `s` (asynchronous).  With
+// events, e0 and e1 are recorded right before and after the search kernel
+// (as event nodes when the stream is being captured).
+hipError_t enqueue_pack(sge_ctx *c, const Pack &pk, LaunchBufs &bufs, hipStream_t s, hipEvent_t e0 = nullptr,
+                        hipEvent_t e1 = nullptr, bool capturing = false);
 // Upload and plan only (the plan of instance 0 is then read back by the caller).
 hipError_t enqueue_plan_only(const Pack &pk, LaunchBufs &bufs, uint32_t root_chunk, hipStream_t s);
 // After the stream has drained: per-instance results and the kernel time.

@@ -205,9 +205,10 @@ struct PlanIn {
     uint64_t *support;            // W words of scratch when W exceeds the plan kernel's LDS
 };
 
-// Per-instance device counters.
+// Per-instance device counters.  pad0: set when the instance's states
+// exceeded the cap; bytes: algorithmic bytes of the search (when counted).
 struct InstCounters {
-    unsigned long long matches, states, candidates, steals, row_next, pad0, steps, pad2;
+    unsigned long long matches, states, candidates, steals, row_next, pad0, steps, bytes;
 };
 
 constexpr uint32_t QUEUE_GROUPS = 8;                          // work-queue groups
@@ -270,6 +271,8 @@ struct LaunchCfg {
     int per_cu = 0;           // with blocks = 0: at most this many resident blocks per CU (0 = all that fit)
     int used_bitset = 1;
     int general = 0;          // some plan is directed or compares edge labels (CSR kernel with those checks)
+    int count_bytes = 1;      // count each instance's algorithmic bytes
+    uint32_t root_lo = 0, root_hi = 0xFFFFFFFFu;   // the first position's target-id range
 };
 
 // Device-side work state of a context (allocated once, reused per launch).

@@ -123,6 +123,9 @@ static void launch_config(const sge_ctx *c, const std::vector<const InstanceSpec
     }
     cfg.donate = c->donate;
     cfg.per_cu = c->per_cu;
+    cfg.count_bytes = c->count_bytes;
+    cfg.root_lo = c->root_lo;
+    cfg.root_hi = c->root_hi;
     // approximate number of search units (for the root chunk size): up to
     // four blocks of four waves per CU
     pk.units = (uint64_t)c->num_cus * (c->per_cu > 0 ? std::min(c->per_cu, 4) : 4) * 4 * (64 / cfg.lanes);
@@ -329,14 +332,22 @@ hipError_t enqueue_plan_only(const Pack &pk, LaunchBufs &bufs, uint32_t root_chu
                        bufs.work.inst, bufs.work.chunk_prefix, pk.policy, root_chunk, pk.units, s);
 }
 
-hipError_t enqueue_pack(sge_ctx *c, const Pack &pk, LaunchBufs &bufs, hipStream_t s) {
+hipError_t enqueue_pack(sge_ctx *c, const Pack &pk, LaunchBufs &bufs, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                        bool capturing) {
     hipError_t r;
     if (pk.device_plan) r = enqueue_plan_only(pk, bufs, c->root_chunk, s);
     else r = hipMemcpyAsync(bufs.d_blob.p, bufs.h_blob.p, pk.upload, hipMemcpyHostToDevice, s);
     if (r != hipSuccess) return r;
     if ((r = launch_reset(bufs.work, pk.m, s)) != hipSuccess) return r;
+    // inside a capture an event record becomes a node of the graph only with
+    // the external flag
+    auto record = [&](hipEvent_t ev) {
+        return capturing ? hipEventRecordWithFlags(ev, s, hipEventRecordExternal) : hipEventRecord(ev, s);
+    };
+    if (e0 && (r = record(e0)) != hipSuccess) return r;
     if ((r = launch_search(pk.cfg, bufs.work, pk.m, c->cap, c->time_limit_ms, s, c->num_cus)) != hipSuccess)
         return r;
+    if (e1 && (r = record(e1)) != hipSuccess) return r;
     if ((r = hipMemcpyAsync(bufs.h_ctr.p, bufs.work.ctr, pk.m * sizeof(InstCounters), hipMemcpyDeviceToHost, s)) !=
         hipSuccess)
         return r;
@@ -363,6 +374,7 @@ void read_pack(const sge_ctx *c, Pack &pk, const LaunchBufs &bufs, const std::ve
         o.candidates = hc[j].candidates;
         o.steals = hc[j].steals;
         o.steps = hc[j].steps;
+        o.bytes = hc[j].bytes;
         o.status = SGE_OK;
         if (pk.bad_task) {
             o.status = SGE_E_DEVICE;
@@ -393,7 +405,8 @@ static uint64_t graph_key(const sge_ctx *c, const Pack &pk, const LaunchBufs &b,
                        (uint64_t)pk.off_req, (uint64_t)pk.ctr_bytes, (uint64_t)pk.policy, (uint64_t)pk.units,
                        (uint64_t)g.lanes, (uint64_t)g.dense, (uint64_t)g.donate, (uint64_t)g.kmax, (uint64_t)g.nmax,
                        (uint64_t)g.wmax, (uint64_t)g.blocks, (uint64_t)g.per_cu, (uint64_t)g.used_bitset,
-                       (uint64_t)g.general, (uint64_t)(uintptr_t)b.d_blob.p, (uint64_t)(uintptr_t)b.h_blob.p,
+                       (uint64_t)g.general, (uint64_t)g.count_bytes, (uint64_t)g.root_lo, (uint64_t)g.root_hi,
+                       (uint64_t)(uintptr_t)b.d_blob.p, (uint64_t)(uintptr_t)b.h_blob.p,
                        (uint64_t)(uintptr_t)b.h_ctr.p, (uint64_t)(uintptr_t)b.work.sched,
                        (uint64_t)(uintptr_t)b.work.queue, (uint64_t)(uintptr_t)b.work.ctr,
                        (uint64_t)(uintptr_t)b.work.inst, (uint64_t)(uintptr_t)b.work.chunk_prefix,
@@ -418,6 +431,7 @@ sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std
         op.push_back(&out[i]);
     }
     ms_search = 0;
+    c->last_event_ms = 0;
     if (sp.empty()) {
         ms_prep = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
         return SGE_OK;
@@ -497,7 +511,7 @@ sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std
             hipGraphExec_t ge = nullptr;
             if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
                 return hip_fail(c, e, "hipStreamBeginCapture");
-            hipError_t er = enqueue_pack(c, pk, c->bufs, s);
+            hipError_t er = enqueue_pack(c, pk, c->bufs, s, c->ev0, c->ev1, true);
             e = hipStreamEndCapture(s, &g);
             if (er != hipSuccess || e != hipSuccess) {
                 if (g) (void)hipGraphDestroy(g);
@@ -519,10 +533,14 @@ sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std
         if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
         if (es != hipSuccess) return hip_fail(c, es, "search");
     } else {
-        if ((e = enqueue_pack(c, pk, c->bufs, s)) != hipSuccess) return hip_fail(c, e, "search launch");
+        if ((e = enqueue_pack(c, pk, c->bufs, s, c->ev0, c->ev1, false)) != hipSuccess)
+            return hip_fail(c, e, "search launch");
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "search");
     }
     read_pack(c, pk, c->bufs, sp, op, ms_search);
+    float ev_ms = 0;
+    c->last_event_ms =
+        c->ev0 && c->ev1 && hipEventElapsedTime(&ev_ms, c->ev0, c->ev1) == hipSuccess ? (double)ev_ms : 0.0;
     c->last_ms[0] = ms_search;
     c->last_ms[1] = pk.ms_work;
     c->last_ms[2] = pk.ms_done;

@@ -66,6 +66,8 @@ struct SearchArgs {
     unsigned long long limit_ticks;   // time limit in s_memrealtime ticks (100 MHz); 0 = none
     unsigned min_blocks;              // blocks kept whatever the number of root chunks
     unsigned units_per_block;
+    unsigned count_bytes;             // count the algorithmic bytes of the search (InstCounters::bytes)
+    unsigned root_lo, root_hi;        // the first position's target-id range
 };
 
 constexpr unsigned FULL_RANGE = 0xFFFFFFFFu;
@@ -142,6 +144,11 @@ __device__ __forceinline__ unsigned long long group_mask(unsigned long long ball
 
 template <int G>
 __device__ __forceinline__ unsigned group_sum(unsigned x) {
+    for (int o = G / 2; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+template <int G>
+__device__ __forceinline__ unsigned long long group_sum64(unsigned long long x) {
     for (int o = G / 2; o > 0; o >>= 1) x += __shfl_xor(x, o);
     return x;
 }
@@ -311,6 +318,26 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
     const unsigned long long want = (4ull * nchunks + a.units_per_block - 1) / a.units_per_block;
     if (blockIdx.x >= max((unsigned long long)min(gridDim.x, a.min_blocks), want)) return;
     if (threadIdx.x == 0) stamp_min(&S->t_start, now_ticks());
+    if (a.count_bytes && blockIdx.x == 0) {
+        // the first position's expansion, once per searched instance: dense,
+        // its domain row; CSR, 5 bytes per target id of the root range (RI:
+        // label and degree of every node) or 4 + 8 bytes per domain member
+        // (RI-DS: the list and the domain word)
+        for (unsigned j = threadIdx.x; j < a.ninst; j += blockDim.x) {
+            const gp<const DevPlan> pj = glob(glob(a.inst)[j].plan);
+            if (pj->empty) continue;
+            unsigned long long b;
+            if constexpr (DENSE) {
+                b = 8ull * pj->W;
+            } else if (pj->use_dom) {
+                b = 12ull * pj->list_len[0];
+            } else {
+                const unsigned n = pj->n;
+                b = 5ull * (min(a.root_hi, n) - min(a.root_lo, n));
+            }
+            if (b) fadd64(&a.ctr[j].bytes, b);
+        }
+    }
     if (nchunks == 0) {   // no root candidate anywhere: nothing to search
         if (lane == 0) stamp_max(&S->t_end, now_ticks());
         return;
@@ -325,6 +352,9 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
     GDesc d{};
     gp<const DevPlan> P = nullptr;
     unsigned long long c_states = 0, c_matches = 0, c_cands = 0, c_steals = 0, c_steps = 0;
+    // algorithmic bytes (counted when a.count_bytes): c_bytes per unit (the
+    // same in its lanes), lane_bytes per lane, summed over the unit at a flush
+    unsigned long long c_bytes = 0, lane_bytes = 0;
     bool roots_done = false;
     unsigned since_donate = 0;     // steps since this unit's task began or it last gave work away
     unsigned iter = 0, backoff = 0, polls = 0;
@@ -335,9 +365,15 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
     // every wave ends by the deadline, whatever the state of the search
     const unsigned long long deadline = a.limit_ticks ? now_ticks() + a.limit_ticks : ~0ull;
 
-    auto flush = [&]() {
+    // `fold`: every lane of the unit is here, so the per-lane bytes can be summed
+    auto flush = [&](bool fold) {
+        if (fold && a.count_bytes) {
+            c_bytes += group_sum64<G>(lane_bytes);
+            lane_bytes = 0;
+        }
         if (cinst != NO_TASK && gl == 0) {
             InstCounters *c = a.ctr + cinst;
+            if (c_bytes) fadd64(&c->bytes, c_bytes);
             if (c_matches) fadd64(&c->matches, c_matches);
             if (c_cands) fadd64(&c->candidates, c_cands);
             if (c_steals) fadd64(&c->steals, c_steals);
@@ -348,7 +384,7 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                     __hip_atomic_store(&c->pad0, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        c_states = c_matches = c_cands = c_steals = c_steps = 0;
+        c_states = c_matches = c_cands = c_steals = c_steps = c_bytes = 0;
     };
     auto inst_aborted = [&](unsigned i) -> bool {
         unsigned long long f = 0;
@@ -460,6 +496,9 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
         if (count) {
             c_states += cnt;
             if (last) c_matches += cnt;
+            // one row of W words each: the position's domain (or label and
+            // degree) set, the parent image's adjacency row, every back-edge row
+            if (a.count_bytes) c_bytes += 8ull * W * (1u + (p >= 0 ? 1u : 0u) + (unsigned)__popcll(bmask));
         }
         D.fc[pos] = last ? 0u : cnt;
         D.hw[pos] = W;
@@ -649,7 +688,7 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                     }
                     // start the task
                     if (ti != cinst) {
-                        flush();
+                        flush(true);
                         cinst = ti;
                         d = gdesc(glob(a.inst) + ti);
                         P = d.plan;
@@ -768,7 +807,7 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                 if (gl == 0) unmark(D.M[lvl]);
             }
             if (task_done) {
-                if (c_states >= 4096) flush();
+                if (c_states >= 4096) flush(true);
                 drop_task(base);
                 continue;
             }
@@ -797,7 +836,7 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                 if (gl == 0) unmark(L.M[lvl]);
             }
             if (task_done) {
-                if (c_states >= 4096) flush();
+                if (c_states >= 4096) flush(true);
                 drop_task(base);
                 continue;
             }
@@ -813,6 +852,14 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                 if (gl == 0) mark(v);
                 lvl++;
                 const uint2 fr = open_frame(lvl, 0, FULL_RANGE);
+                if (a.count_bytes) {
+                    // an expansion: the bounds of the parent image's list (its ids
+                    // are counted per candidate below); without a parent, the
+                    // whole candidate set: 5 bytes per target node (RI) or 4 + 8
+                    // per domain member (RI-DS)
+                    c_bytes += L.pp[lvl] >= 0 ? 8ull
+                               : d.bits ? 12ull * P->list_len[lvl] : 5ull * P->n;
+                }
                 c0 = 0;
                 e = fr.x;
                 lb = fr.y;
@@ -832,6 +879,8 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
             const bool in_row = GEN && has_parent && (flags & PLAN_DIRECTED) && !pout && d.irp != nullptr;
             unsigned v = 0;
             NodeRec r{0, 0, 0, 0};
+            unsigned probes = 0;      // back-edge probes of this lane's candidate, up to the first failure
+            unsigned gen_extra = 0;   // general graphs: bytes of the parent-arc checks
             if (ok) {
                 if (!GEN && has_parent && d.wcol) {
                     const WideEntry we = ld_wide(d.wcol + lb + idx);   // id, row start, degree, label in one load
@@ -854,7 +903,9 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                 unsigned long long bm = L.pback[lvl];
                 const size_t wv = v >> 6;
                 unsigned long long hit = ~0ull;
+                bool alive = ok;   // this candidate's probes have not failed yet
                 while (bm) {
+                    const unsigned ng = min((unsigned)__popcll(bm), 4u);   // distinct rows this round
                     const unsigned j0 = (unsigned)__builtin_ctzll(bm);
                     bm &= bm - 1;
                     const unsigned j1 = bm ? (unsigned)__builtin_ctzll(bm) : j0;
@@ -868,6 +919,16 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                     const unsigned long long a2 = d.adj[(size_t)L.M[j2] * W + wv];
                     const unsigned long long a3 = d.adj[(size_t)L.M[j3] * W + wv];
                     hit &= a0 & a1 & a2 & a3;
+                    if (a.count_bytes) {
+                        // probes in position order up to the first that fails
+                        const unsigned sh = v & 63;
+                        const unsigned res = (unsigned)((a0 >> sh) & 1ull) | ((unsigned)((a1 >> sh) & 1ull) << 1) |
+                                             ((unsigned)((a2 >> sh) & 1ull) << 2) |
+                                             ((unsigned)((a3 >> sh) & 1ull) << 3) | (0xFu << ng);
+                        const unsigned f = (unsigned)__builtin_ctz(~res);   // first failure, >= ng: none
+                        probes += alive ? min(f + 1, ng) : 0u;
+                        alive = alive && f >= ng;
+                    }
                 }
                 ok = ok && ((hit >> (v & 63)) & 1ull);
             } else if (!GEN || !flags) {
@@ -875,7 +936,10 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                 while (bm) {
                     unsigned j = (unsigned)__builtin_ctzll(bm);
                     bm &= bm - 1;
-                    if (ok) ok = adjacent(d, W, L.M[j], L.MB[j], L.MD[j], v);
+                    if (ok) {
+                        probes++;
+                        ok = adjacent(d, W, L.M[j], L.MB[j], L.MD[j], v);
+                    }
                 }
             } else if constexpr (GEN) {
                 // general graphs: in-degree (r.pad), the label of the arc the
@@ -887,26 +951,39 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                 if (ok && has_parent && lm) {
                     const unsigned pp = (unsigned)L.pp[lvl];
                     const unsigned tl = in_row ? (d.ielab ? d.ielab[lb + idx] : 0u) : (d.elab ? d.elab[lb + idx] : 0u);
+                    gen_extra += 4;   // the label of the arc the candidate came over
                     ok = tl == (pout ? lm[pp * k + lvl] : lm[lvl * k + pp]);
                 }
                 if (ok && dir && has_parent && ((P->pboth >> lvl) & 1ull)) {
                     const unsigned pp = (unsigned)L.pp[lvl];
+                    gen_extra += 8;   // the reverse arc to the parent
                     ok = arc_to(d, r.begin, r.deg, L.M[pp], lm != nullptr, lm ? lm[lvl * k + pp] : 0u);
                 }
-                for (unsigned long long bm = P->bout[lvl]; bm && ok; bm &= bm - 1) {   // M[j] -> v
+                // earlier positions in order; for each, the arc into v, then
+                // (directed) the arc out of v, up to the first that fails
+                const unsigned long long bo = P->bout[lvl], bi = dir ? P->bin[lvl] : 0ull;
+                for (unsigned long long bm = bo | bi; bm && ok; bm &= bm - 1) {
                     const unsigned j = (unsigned)__builtin_ctzll(bm);
-                    ok = arc_to(d, L.MB[j], L.MD[j], v, lm != nullptr, lm ? lm[j * k + lvl] : 0u);
-                }
-                if (dir)
-                    for (unsigned long long bm = P->bin[lvl]; bm && ok; bm &= bm - 1) {   // v -> M[j]
-                        const unsigned j = (unsigned)__builtin_ctzll(bm);
+                    if ((bo >> j) & 1ull) {   // M[j] -> v
+                        probes++;
+                        ok = arc_to(d, L.MB[j], L.MD[j], v, lm != nullptr, lm ? lm[j * k + lvl] : 0u);
+                    }
+                    if (ok && ((bi >> j) & 1ull)) {   // v -> M[j]
+                        probes++;
                         ok = arc_to(d, r.begin, r.deg, L.M[j], lm != nullptr, lm ? lm[lvl * k + j] : 0u);
                     }
+                }
             }
             c_cands += min((unsigned)G, e - c0);
             unsigned long long acc = group_mask<G>(__ballot(ok), gbase);
             unsigned cnt = (unsigned)__popcll(acc);
+            // bytes of the candidates this step is done with (those past the
+            // frame's new cursor are evaluated again later): with a parent, the
+            // list id, 5 (RI) or 8 (RI-DS) bytes of checks, the parent-arc
+            // checks and 8 per back-edge probe
+            const unsigned cand_bytes = has_parent ? 4u + (d.bits ? 8u : 5u) + gen_extra + 8u * probes : 0u;
             if (lvl + 1 == k) {
+                if (a.count_bytes && idx < e) lane_bytes += cand_bytes;
                 c_states += cnt;
                 c_matches += cnt;
                 if (d.rows && ok) {
@@ -939,12 +1016,13 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                 etop += take;
                 c_states += take;
                 L.cur[lvl] = ncur;
+                if (a.count_bytes && idx < e && idx < ncur) lane_bytes += cand_bytes;
             }
         }
 
         // counters: flush now and then so a state cap takes effect
         if (c_states >= 8192) {
-            flush();
+            flush(true);
             if (a.state_cap && inst_aborted(inst)) {
                 drop_task(lvl);
                 continue;
@@ -1087,6 +1165,10 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
     // Every wave of the block reaches this point (the loop is left only by
     // `break`), and the units' LDS areas are free: each unit's area (at least
     // 16 words) takes its exit record.
+    if (a.count_bytes) {   // every lane is here: fold the per-lane bytes into the unit's
+        c_bytes += group_sum64<G>(lane_bytes);
+        lane_bytes = 0;
+    }
     __syncthreads();
     unsigned long long *rec = reinterpret_cast<unsigned long long *>(lds + (size_t)unit * a.unit_words);
     if (gl == 0) {
@@ -1098,6 +1180,7 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
         rec[5] = c_steps;
         rec[6] = busy_ticks;
         rec[7] = last_finish;
+        rec[8] = c_bytes;
     }
     __syncthreads();
     const unsigned nunits = blockDim.x / G;
@@ -1117,8 +1200,9 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                 c_cands += r[3];
                 c_steals += r[4];
                 c_steps += r[5];
+                c_bytes += r[8];
             }
-            flush();
+            flush(false);
         }
     }
     if (threadIdx.x == 0) {
@@ -1143,7 +1227,7 @@ __global__ void reset_kernel(Sched *s, InstCounters *c, unsigned ninst, QTask *q
         if (threadIdx.x < QUEUE_GROUPS) s->grp[threadIdx.x].free = QUEUE_GROUP_SLOTS;
         if (threadIdx.x == 0) s->t_start = ~0ull;
     }
-    for (unsigned j = i; j < ninst; j += stride) c[j] = InstCounters{0, 0, 0, 0, 0, 0, 0, 0};
+    for (unsigned j = i; j < ninst; j += stride) c[j] = InstCounters{};
     for (unsigned j = i; j < QUEUE_SLOTS; j += stride) q[j].seq = 2 * (j % QUEUE_GROUP_SLOTS);
 }
 
@@ -1167,12 +1251,12 @@ hipError_t launch_g(SearchArgs args, int blocks, int per_cu_cap, int threads, si
 }
 
 unsigned unit_words(const LaunchCfg &cfg) {
-    // even: every unit's area starts 8-byte aligned; at least 16 words: the
-    // area takes the unit's exit record (eight 64-bit values)
-    if (cfg.dense) return std::max(16u, 3 * even(cfg.kmax) + 2 * cfg.kmax * cfg.wmax + 2 * cfg.wmax);
+    // even: every unit's area starts 8-byte aligned; at least 18 words: the
+    // area takes the unit's exit record (nine 64-bit values)
+    if (cfg.dense) return std::max(18u, 3 * even(cfg.kmax) + 2 * cfg.kmax * cfg.wmax + 2 * cfg.wmax);
     unsigned E = cfg.kmax + cfg.lanes;
     unsigned UW = (cfg.nmax + 31) / 32;
-    return std::max(16u, even(13 * cfg.kmax + 3 * E + UW));
+    return std::max(18u, even(13 * cfg.kmax + 3 * E + UW));
 }
 
 // Largest block (256, 128 or 64 threads) whose units fit in 64 KiB of LDS.
@@ -1198,6 +1282,9 @@ hipError_t launch_reset(DevWork &w, uint32_t ninst, hipStream_t s) {
 hipError_t launch_search(const LaunchCfg &cfg, DevWork &w, uint32_t ninst, uint64_t state_cap,
                          uint64_t time_limit_ms, hipStream_t s, int num_cus) {
     SearchArgs a{};
+    a.count_bytes = cfg.count_bytes ? 1u : 0u;
+    a.root_lo = cfg.root_lo;
+    a.root_hi = cfg.root_hi;
     a.inst = w.inst;
     a.chunk_prefix = w.chunk_prefix;
     a.ctr = w.ctr;

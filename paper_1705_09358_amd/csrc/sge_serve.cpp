@@ -290,6 +290,7 @@ sge_status sge_serve_poll(sge_ctx *c, uint64_t ticket, sge_result *res) {
     res->matches = q->out.matches;
     res->states = q->out.states;
     res->candidates = q->out.candidates;
+    res->alg_bytes = q->out.bytes;
     res->steals = q->out.steals;
     res->steps = q->out.steps;
     res->ms_prep = q->ms_prep;

@@ -28,13 +28,14 @@ EXPORTS = [
     "sge_count", "sge_enumerate", "sge_batch_run", "sge_set_batch_policy", "sge_serve_start", "sge_serve_submit",
     "sge_serve_poll", "sge_serve_stop", "sge_plan_host", "sge_plan_device", "sge_set_plan_location", "sge_set_tuning",
     "sge_set_time_limit", "sge_last_launch_timing", "sge_last_launch_occupancy", "sge_set_blocks_per_cu",
+    "sge_last_kernel_ms", "sge_set_count_bytes",
 ]
 
 
 class c_result(ctypes.Structure):
     _fields_ = [("matches", ctypes.c_uint64), ("states", ctypes.c_uint64), ("candidates", ctypes.c_uint64),
-                ("steals", ctypes.c_uint64), ("steps", ctypes.c_uint64), ("ms_prep", ctypes.c_double),
-                ("ms_search", ctypes.c_double)]
+                ("alg_bytes", ctypes.c_uint64), ("steals", ctypes.c_uint64), ("steps", ctypes.c_uint64),
+                ("ms_prep", ctypes.c_double), ("ms_search", ctypes.c_double)]
 
 
 class c_job(ctypes.Structure):
@@ -48,6 +49,7 @@ class Result:
     matches: int
     states: int
     candidates: int
+    alg_bytes: int
     steals: int
     steps: int
     ms_prep: float
@@ -55,14 +57,15 @@ class Result:
 
     @staticmethod
     def of(st: int, r: c_result) -> "Result":
-        return Result(st, r.matches, r.states, r.candidates, r.steals, r.steps, r.ms_prep, r.ms_search)
+        return Result(st, r.matches, r.states, r.candidates, r.alg_bytes, r.steals, r.steps, r.ms_prep,
+                      r.ms_search)
 
 
 # numpy layouts of sge_job and sge_result, for batches marshalled without
 # per-job Python objects
 JOB_DTYPE = np.dtype([("target", "<u4"), ("pattern", "<u4"), ("mode", "<i4"), ("labelled", "<i4")])
-RESULT_DTYPE = np.dtype([("matches", "<u8"), ("states", "<u8"), ("candidates", "<u8"), ("steals", "<u8"),
-                         ("steps", "<u8"), ("ms_prep", "<f8"), ("ms_search", "<f8")])
+RESULT_DTYPE = np.dtype([("matches", "<u8"), ("states", "<u8"), ("candidates", "<u8"), ("alg_bytes", "<u8"),
+                         ("steals", "<u8"), ("steps", "<u8"), ("ms_prep", "<f8"), ("ms_search", "<f8")])
 assert JOB_DTYPE.itemsize == ctypes.sizeof(c_job) and RESULT_DTYPE.itemsize == ctypes.sizeof(c_result)
 
 
@@ -86,8 +89,8 @@ class BatchResults:
 
     def __getitem__(self, i: int) -> "Result":
         r = self.array[i]
-        return Result(self.status, int(r["matches"]), int(r["states"]), int(r["candidates"]), int(r["steals"]),
-                      int(r["steps"]), float(r["ms_prep"]), float(r["ms_search"]))
+        return Result(self.status, int(r["matches"]), int(r["states"]), int(r["candidates"]), int(r["alg_bytes"]),
+                      int(r["steals"]), int(r["steps"]), float(r["ms_prep"]), float(r["ms_search"]))
 
     def __iter__(self):
         return (self[i] for i in range(len(self)))
@@ -147,6 +150,8 @@ def lib() -> ctypes.CDLL:
             "sge_last_launch_timing": (I32, [P, P]),
             "sge_last_launch_occupancy": (I32, [P, P, P]),
             "sge_set_blocks_per_cu": (I32, [P, I32]),
+            "sge_last_kernel_ms": (I32, [P, ctypes.POINTER(ctypes.c_double)]),
+            "sge_set_count_bytes": (I32, [P, I32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -235,6 +240,16 @@ class Context:
         out = (ctypes.c_double * 3)()
         self._check(self._L.sge_last_launch_timing(self._h, ctypes.addressof(out)), "sge_last_launch_timing")
         return tuple(out)
+
+    def last_kernel_ms(self) -> float:
+        """HIP-event time (ms) of the last launch's search kernel."""
+        ms = ctypes.c_double()
+        self._check(self._L.sge_last_kernel_ms(self._h, ctypes.byref(ms)), "sge_last_kernel_ms")
+        return ms.value
+
+    def set_count_bytes(self, on: bool):
+        """Count each search's algorithmic bytes (Result.alg_bytes); on by default."""
+        self._check(self._L.sge_set_count_bytes(self._h, int(bool(on))), "sge_set_count_bytes")
 
     def last_launch_occupancy(self):
         """(sum over units of the ms each held a task, units that entered the

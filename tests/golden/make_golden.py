@@ -180,7 +180,7 @@ def main():
             else:
                 json.dump(out, f, indent=0)
         print(f"{cfg}: {len(rows)} instances, states {out['total_states']}, matches {out['total_matches']}, "
-              f"redrawn {sum(r['attempt'] > 0 for r in rows)}, "
+              f"redrawn {sum(r.get('attempt', 0) > 0 for r in rows)}, "
               f"aborted {sum(r.get('status') == 'aborted' for r in rows)}, {time.time() - t0:.1f}s", flush=True)
 
 

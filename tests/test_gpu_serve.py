@@ -14,6 +14,7 @@ from paper_1705_09358_amd import sge, synth
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+C5_SAMPLE = 48   # the first queries of the serving workload's arrival stream
 
 
 def _note(msg):
@@ -91,11 +92,12 @@ def test_serve_c5_sample_alone_and_mix(ctx, where):
     RI-DS-SI-FC, state cap 1e7) against the oracle, in the mix and alone,
     planned on the host (-1) or on the device (1)."""
     man = manifest("c5")
+    sample = man["instances"][:C5_SAMPLE]
     _note("serve c5: loading 50 resident targets")
     targets = [synth.c5_target(t) for t in range(synth.C5_TARGETS)]
     th = [ctx.load_target(T) for T in targets]
     jobs, pats = [], []
-    for r in man["instances"]:
+    for r in sample:
         t, P, _ = synth.c5_query(r["j"], targets)
         assert t == r["target"]
         pats.append(P)
@@ -111,7 +113,7 @@ def test_serve_c5_sample_alone_and_mix(ctx, where):
             ctx.serve_stop()
         ctx.set_mode(sge.RIDS_SI_FC)
         ctx.set_labelled(True)
-        for (t, p, _, _), r, w in zip(jobs, mix, man["instances"]):
+        for (t, p, _, _), r, w in zip(jobs, mix, sample):
             if w["status"] == "ok":
                 assert r.status == sge.OK, w["j"]
                 assert (r.matches, r.states) == (w["matches"], w["states"]), w["j"]
