@@ -131,10 +131,17 @@ sge_status sge_set_count_bytes(sge_ctx *ctx, int on);
 sge_status sge_last_launch_occupancy(const sge_ctx *ctx, double *busy_unit_ms, uint32_t *units);
 
 /* Load a target graph and keep it resident in device memory (CSR, per-node
- * records and, when the graph is small enough, a dense adjacency bitset).
+ * records and, for n <= 65536, dense adjacency bitset rows).  Target size is
+ * bounded only by device memory: with rows a back-edge is one 64-bit word
+ * test, without them a binary search in the CSR row; a used-node bitset
+ * per search unit is kept in LDS while it fits beside four waves of units,
+ * and beyond that a candidate is compared with the mapped prefix instead.
  * labels: n uint32 or NULL (all nodes equivalent).  *handle receives the id. */
 sge_status sge_load_target(sge_ctx *ctx, uint32_t n, const uint32_t *row_ptr, const uint32_t *col,
                            const uint32_t *labels, uint32_t *handle);
+/* Unloading a target or pattern that server queries in flight still use
+ * (submitted and not yet complete) is refused with SGE_E_BUSY; it succeeds
+ * once they have completed (they need not have been polled). */
 sge_status sge_unload_target(sge_ctx *ctx, uint32_t handle);
 
 /* Load a pattern graph (k <= 64 nodes, same CSR conventions). */
@@ -268,7 +275,10 @@ sge_status sge_set_plan_location(sge_ctx *ctx, int where);
  * 0 = automatic), root chunk size (0 = automatic), work donation (0 = off,
  * 1 = on with the default period, N > 1 = a unit gives work away at most
  * once per N of its steps), dense-bitset search (-1 = automatic, 0 = off,
- * 1 = on). */
+ * 1 = on wherever it can run: undirected graphs without compared edge
+ * labels, every target with adjacency rows -- n <= 65536 -- and a search
+ * unit's k rows of ceil(n/64) words within 64 KiB of LDS; elsewhere the CSR
+ * search runs, and a general graph is SGE_E_INVAL). */
 sge_status sge_set_tuning(sge_ctx *ctx, int lanes_per_unit, uint32_t root_chunk, int donate, int dense);
 
 /* Resident search blocks per compute unit (each block is four wavefronts of

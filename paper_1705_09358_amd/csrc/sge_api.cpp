@@ -226,6 +226,7 @@ sge_status sge_create(int device, void *hip_stream, sge_ctx **out) {
 }
 
 void sge_serve_shutdown_internal(sge_ctx *c);
+bool sge_serve_holds(sge_ctx *c, const Target *t, const Pattern *p);
 
 void sge_destroy(sge_ctx *c) {
     if (!c) return;
@@ -297,6 +298,8 @@ sge_status sge_unload_target(sge_ctx *c, uint32_t handle) {
     if (!c) return SGE_E_INVAL;
     auto it = c->targets.find(handle);
     if (it == c->targets.end()) return fail(c, SGE_E_HANDLE, "unknown target handle");
+    if (sge_serve_holds(c, it->second.get(), nullptr))
+        return fail(c, SGE_E_BUSY, "the target is in use by server queries in flight");
     (void)hipStreamSynchronize(c->stream);
     free_target(*it->second);
     c->targets.erase(it);
@@ -332,6 +335,8 @@ sge_status sge_unload_pattern(sge_ctx *c, uint32_t handle) {
     if (!c) return SGE_E_INVAL;
     auto it = c->patterns.find(handle);
     if (it == c->patterns.end()) return fail(c, SGE_E_HANDLE, "unknown pattern handle");
+    if (sge_serve_holds(c, nullptr, it->second.get()))
+        return fail(c, SGE_E_BUSY, "the pattern is in use by server queries in flight");
     (void)hipStreamSynchronize(c->stream);
     free_pattern(*it->second);
     c->patterns.erase(it);

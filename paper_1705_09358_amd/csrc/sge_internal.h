@@ -88,6 +88,7 @@ struct Target {
     uint32_t *d_elab = nullptr, *d_ielab = nullptr; // edge labels (out, in), or null
     uint8_t *d_nbr_deg = nullptr;                // nbr_deg on the device (undirected), or null
     uint64_t dev_bytes = 0;
+    uint32_t serve_refs = 0;                     // server queries in flight on it (under the server's lock)
 };
 
 // A pattern as the plan kernel reads it (resident on the device).
@@ -103,6 +104,7 @@ struct Pattern {
     HostGraph g;
     uint32_t ncomp = 0;
     DevPattern *d_pat = nullptr;
+    uint32_t serve_refs = 0;                     // server queries in flight on it (under the server's lock)
 };
 
 // Plan flags: directions or edge labels take part in the search.
@@ -269,7 +271,7 @@ struct LaunchCfg {
     uint32_t kmax = 0, nmax = 0, wmax = 0;
     int blocks = 0;           // 0 = fill the device
     int per_cu = 0;           // with blocks = 0: at most this many resident blocks per CU (0 = all that fit)
-    int used_bitset = 1;
+    int used_bitset = 1;      // CSR: a used-node bitset per unit in LDS (else the prefix is compared)
     int general = 0;          // some plan is directed or compares edge labels (CSR kernel with those checks)
     int count_bytes = 1;      // count each instance's algorithmic bytes
     uint32_t root_lo = 0, root_hi = 0xFFFFFFFFu;   // the first position's target-id range
@@ -302,6 +304,9 @@ hipError_t launch_search(const LaunchCfg &cfg, DevWork &w, uint32_t ninst, uint6
                          uint64_t time_limit_ms, hipStream_t s, int num_cus);
 // Shared memory a block of the search kernel needs.
 size_t search_lds_bytes(const LaunchCfg &cfg);
+// Threads per block of the search kernel (256, 128 or 64; 0: one unit's LDS
+// does not fit in 64 KiB).
+int search_block_threads(const LaunchCfg &cfg);
 // Clear the scheduling words of a launch (a fill kernel; usable in a captured graph).
 hipError_t launch_reset(DevWork &w, uint32_t ninst, hipStream_t s);
 

@@ -46,6 +46,18 @@ bool choose_dense(const sge_ctx *c, const std::vector<InstanceSpec> &specs) {
         words += s.t->W;
     }
     if (!all_adj) return false;
+    // every search unit holds k rows of W words in LDS: the launch must fit
+    LaunchCfg probe;
+    probe.dense = 1;
+    for (const InstanceSpec &s : specs) {
+        probe.kmax = std::max(probe.kmax, s.p->g.n);
+        probe.nmax = std::max(probe.nmax, s.t->g.n);
+        probe.wmax = std::max(probe.wmax, s.t->W);
+    }
+    probe.lanes = c->lanes ? c->lanes : 8;
+    if (!c->lanes)
+        while (probe.lanes < 64 && (uint32_t)probe.lanes < probe.wmax) probe.lanes *= 2;
+    if (search_block_threads(probe) == 0) return false;
     return c->dense == 1 || deg >= 2.0 * words;
 }
 
@@ -123,6 +135,11 @@ static void launch_config(const sge_ctx *c, const std::vector<const InstanceSpec
     }
     cfg.donate = c->donate;
     cfg.per_cu = c->per_cu;
+    // a used-node bitset per search unit (n bits of LDS) while a block of
+    // four waves still fits; larger targets compare candidates with the
+    // mapped prefix instead (at most 63 entries), which fits any n
+    cfg.used_bitset = 1;
+    if (!dense && search_block_threads(cfg) < 256) cfg.used_bitset = 0;
     cfg.count_bytes = c->count_bytes;
     cfg.root_lo = c->root_lo;
     cfg.root_hi = c->root_hi;

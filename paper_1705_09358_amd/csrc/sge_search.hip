@@ -419,13 +419,14 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
         L.dn[pos] = 0;
         return make_uint2(e, start);
     };
+    // the used-node set (CSR without a bitset: the mapped prefix itself)
     auto mark = [&](unsigned v) {
         if constexpr (DENSE) atomicOr(&D.used[v >> 6], 1ull << (v & 63));
-        else atomicOr(&L.used[v >> 5], 1u << (v & 31));
+        else if (a.UW) atomicOr(&L.used[v >> 5], 1u << (v & 31));
     };
     auto unmark = [&](unsigned v) {
         if constexpr (DENSE) atomicAnd(&D.used[v >> 6], ~(1ull << (v & 63)));
-        else atomicAnd(&L.used[v >> 5], ~(1u << (v & 31)));
+        else if (a.UW) atomicAnd(&L.used[v >> 5], ~(1u << (v & 31)));
     };
     // dense: take the lowest member of frame f (group-uniform result)
     auto pick_lowest = [&](unsigned f) -> unsigned {
@@ -892,7 +893,15 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                 }
             }
             if (ok && d.bits) ok = (d.bits[(size_t)lvl * W + (v >> 6)] >> (v & 63)) & 1ull;
-            if (ok) ok = !used_test(L.used, v);
+            if (ok) {
+                if (a.UW) {
+                    ok = !used_test(L.used, v);
+                } else {
+                    // targets too large for a used bitset in LDS: v against the
+                    // mapped prefix (the same address in every lane: a broadcast)
+                    for (unsigned j = 0; j < lvl; j++) ok = ok && L.M[j] != v;
+                }
+            }
             const unsigned pl = L.plab[lvl];
             if (ok && pl != LABEL_ANY) ok = r.label == pl;
             if (ok) ok = r.deg >= L.pdeg[lvl];
@@ -1255,7 +1264,7 @@ unsigned unit_words(const LaunchCfg &cfg) {
     // area takes the unit's exit record (nine 64-bit values)
     if (cfg.dense) return std::max(18u, 3 * even(cfg.kmax) + 2 * cfg.kmax * cfg.wmax + 2 * cfg.wmax);
     unsigned E = cfg.kmax + cfg.lanes;
-    unsigned UW = (cfg.nmax + 31) / 32;
+    unsigned UW = cfg.used_bitset ? (cfg.nmax + 31) / 32 : 0;
     return std::max(18u, even(13 * cfg.kmax + 3 * E + UW));
 }
 
@@ -1268,6 +1277,8 @@ int block_threads(const LaunchCfg &cfg) {
 }
 
 }  // namespace
+
+int search_block_threads(const LaunchCfg &cfg) { return block_threads(cfg); }
 
 size_t search_lds_bytes(const LaunchCfg &cfg) {
     int t = block_threads(cfg);
@@ -1293,7 +1304,7 @@ hipError_t launch_search(const LaunchCfg &cfg, DevWork &w, uint32_t ninst, uint6
     a.ninst = ninst;
     a.kmax = cfg.kmax;
     a.E = cfg.kmax + cfg.lanes;
-    a.UW = (cfg.nmax + 31) / 32;
+    a.UW = cfg.used_bitset ? (cfg.nmax + 31) / 32 : 0;
     a.W = cfg.dense ? cfg.wmax : 0;
     a.unit_words = unit_words(cfg);
     a.donate = cfg.donate != 0;

@@ -67,6 +67,9 @@ struct Server {
         q->done = true;
         bytes_in_use -= q->bytes;
         in_flight--;
+        // the query no longer touches its target and pattern
+        const_cast<Target *>(q->spec.t)->serve_refs--;
+        const_cast<Pattern *>(q->spec.p)->serve_refs--;
     }
     void prep_loop();
     void dispatch_loop();
@@ -188,6 +191,14 @@ void Server::dispatch_loop() {
 
 extern "C" {
 
+// Whether a server query in flight holds the target or pattern (unloading it
+// must wait until the query completes).
+__attribute__((visibility("hidden"))) bool sge_serve_holds(sge_ctx *c, const Target *t, const Pattern *p) {
+    if (!c || !c->server) return false;
+    std::lock_guard<std::mutex> lk(c->server->mu);
+    return (t && t->serve_refs) || (p && p->serve_refs);
+}
+
 __attribute__((visibility("hidden"))) void sge_serve_shutdown_internal(sge_ctx *c) {
     if (!c || !c->server) return;
     Server *sv = c->server.get();
@@ -264,6 +275,8 @@ sge_status sge_serve_submit(sge_ctx *c, const sge_job *job, uint64_t *ticket) {
     *ticket = q->ticket;
     sv->in_flight++;
     sv->bytes_in_use += q->bytes;
+    it->second->serve_refs++;
+    ip->second->serve_refs++;
     if (q->spec.p->g.n == 0) {   // the empty pattern has one (empty) match
         q->out.matches = 1;
         sv->release(q.get());

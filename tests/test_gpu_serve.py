@@ -175,3 +175,37 @@ def test_serve_admission(ctx):
         ctx.unload_pattern(h)
     for h in (t3, t1):
         ctx.unload_target(h)
+
+
+def test_unload_refused_while_queries_use_the_graphs(ctx):
+    """A target or pattern that a query in flight uses cannot be unloaded
+    (SGE_E_BUSY); once the query has completed the unload succeeds, and the
+    query's result is the oracle's.  The query is a full dense search (about
+    7e8 states, a fraction of a second on the device), so it is still running
+    when the unloads are tried right after the submit."""
+    man = json.load(open(os.path.join(GOLDEN, "c3full.json")))
+    w = man["instances"][0]
+    inst = synth.c3_instance(w["j"], 0)
+    th, ph = ctx.load_target(inst.target), ctx.load_pattern(inst.pattern)
+    other = ctx.load_pattern(synth.c3_instance(1, 0).pattern)
+    ctx.set_state_cap(0)
+    ctx.serve_start(8, 1 << 30)
+    try:
+        tk = ctx.serve_submit(th, ph, sge.RIDS_SI_FC, True)
+        assert tk is not None
+        for fn, h in ((ctx.unload_target, th), (ctx.unload_pattern, ph)):
+            with pytest.raises(sge.SgeError) as e:
+                fn(h)
+            assert e.value.code == sge.E_BUSY
+        ctx.unload_pattern(other)          # not used by any query: unloads at once
+        t_end = time.time() + 60
+        r = None
+        while r is None and time.time() < t_end:
+            r = ctx.serve_poll(tk)
+            time.sleep(0.001)
+        assert r is not None and r.status == sge.OK
+        assert (r.matches, r.states, r.alg_bytes) == (w["matches"], w["states"], w["dense_bytes"])
+    finally:
+        ctx.serve_stop()
+    ctx.unload_pattern(ph)
+    ctx.unload_target(th)
