@@ -106,6 +106,8 @@ def run_batch_workload(ctx, torch, insts, man, steps, warmup, label):
     tot_states = int(want_states.sum()) * steps
     tot_matches = int(want_matches.sum()) * steps
     kernel_ms = sum(ev_ms) / len(ev_ms)
+    if kernel_ms <= 0:
+        raise SystemExit(f"{label}: the search kernel's events recorded nothing ({ctx.last_error()})")
     return dict(ms_per_step=1000 * el / steps, states_per_s=tot_states / el, matches_per_s=tot_matches / el,
                 kernel_ms=kernel_ms, kernel_ms_device_clock=sum(dev_ms) / len(dev_ms),
                 prep_ms=float(res.ms_prep[0]), jobs=jobs, tgt=tgt, model=model, alg_bytes=alg_bytes,

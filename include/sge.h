@@ -122,6 +122,11 @@ sge_status sge_last_kernel_ms(const sge_ctx *ctx, double *ms);
  * on = 0: they do not (a few instructions fewer per candidate), and
  * sge_result.alg_bytes is 0. */
 sge_status sge_set_count_bytes(sge_ctx *ctx, int on);
+/* on = 1: every search step also verifies that the lanes of each search unit
+ * hold the same copy of the unit's state (its task, level, stack top and the
+ * current frame); a disagreement makes the call return SGE_E_DEVICE (the
+ * search itself runs to its end).  Off by default: a check for testing. */
+sge_status sge_set_checks(sge_ctx *ctx, int on);
 /* Occupancy of the same launch (the parallel search of Section 3 as run on
  * the device): *busy_unit_ms receives the sum over search units of the time
  * each held a task, *units the number of units that entered the search loop

@@ -221,6 +221,9 @@ sge_status sge_create(int device, void *hip_stream, sge_ctx **out) {
     if (c->num_cus <= 0) c->num_cus = 1;
     (void)hipEventCreate(&c->ev0);
     (void)hipEventCreate(&c->ev1);
+    if (hipStreamCreateWithFlags(&c->plan_s2, hipStreamNonBlocking) != hipSuccess) c->plan_s2 = nullptr;
+    (void)hipEventCreateWithFlags(&c->plan_fork, hipEventDisableTiming);
+    (void)hipEventCreateWithFlags(&c->plan_join, hipEventDisableTiming);
     *out = c;
     return SGE_OK;
 }
@@ -236,10 +239,15 @@ void sge_destroy(sge_ctx *c) {
     for (auto &kv : c->targets) free_target(*kv.second);
     for (auto &kv : c->patterns) free_pattern(*kv.second);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->gev0) (void)hipEventDestroy(c->gev0);
+    if (c->gev1) (void)hipEventDestroy(c->gev1);
     c->bufs.release();
     c->d_rows.release();
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->plan_fork) (void)hipEventDestroy(c->plan_fork);
+    if (c->plan_join) (void)hipEventDestroy(c->plan_join);
+    if (c->plan_s2) (void)hipStreamDestroy(c->plan_s2);
     delete c;
 }
 
@@ -254,6 +262,12 @@ sge_status sge_last_launch_timing(const sge_ctx *c, double *ms) {
 sge_status sge_last_kernel_ms(const sge_ctx *c, double *ms) {
     if (!c || !ms) return SGE_E_INVAL;
     *ms = c->last_event_ms;
+    return SGE_OK;
+}
+
+sge_status sge_set_checks(sge_ctx *c, int on) {
+    if (!c) return SGE_E_INVAL;
+    c->check_uniform = on ? 1 : 0;
     return SGE_OK;
 }
 

@@ -79,6 +79,7 @@ struct sge_ctx {
     int batch_policy = 0;
     int plan_where = -1;   // -1 automatic, 0 host, 1 device
     int count_bytes = 1;   // search launches count each instance's algorithmic bytes
+    int check_uniform = 0; // search launches verify that a unit's lanes agree on its state
     // batch autotuner's choice by job list (hash); cleared when tuning changes
     std::map<uint64_t, sge::BatchTune> batch_tune;
     int num_cus = 0;
@@ -93,11 +94,20 @@ struct sge_ctx {
     uint32_t last_units = 0;         // last launch: units that entered the search loop
     int last_lanes = 0;              // last launch: lanes per search unit
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // around the search kernel of count, enumerate and batch launches
+    // a second stream and fork/join events: the small plans of a batch run
+    // beside the large ones (default priority, like the context's stream)
+    hipStream_t plan_s2 = nullptr;
+    hipEvent_t plan_fork = nullptr, plan_join = nullptr;
+    bool graph_extras = true;          // captures take the event nodes and the second plan stream
+    std::string graph_extras_error;    // why a capture refused them (then graph_extras is false)
+    const char *enqueue_step = "";     // the step enqueue_pack was at (for error messages)
     double last_event_ms = 0;                  // last launch: the search kernel between ev0 and ev1
     // the last batch launch's executable graph and the key of everything it
     // captured (sizes, launch shape, buffer addresses, settings)
     hipGraphExec_t gexec = nullptr;
     uint64_t gexec_key = 0;
+    bool gexec_timed = false;   // it holds the kernel's event nodes
+    hipEvent_t gev0 = nullptr, gev1 = nullptr;   // those event nodes' events (new ones for every capture)
     std::unique_ptr<sge::Server, sge::ServerDeleter> server;
     std::mutex serve_mu;
 };
@@ -117,6 +127,9 @@ sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std
 // The pieces of run_instances, also used by the server.
 // Whether these instances are searched by the dense-bitset kernel.
 bool choose_dense(const sge_ctx *c, const std::vector<InstanceSpec> &specs);
+bool choose_dense(const sge_ctx *c, const InstanceSpec *specs, size_t m);
+// Candidate-list entries one instance may need (parentless positions).
+uint64_t list_entries(const InstanceSpec &s);
 // Device bytes one instance holds during a launch (descriptors, plan, domains,
 // per-position bitsets, candidate lists).
 uint64_t instance_device_bytes(const InstanceSpec &s);
@@ -133,11 +146,15 @@ struct Pack {
     double busy_ms = 0;                // unit-milliseconds holding tasks (read_pack)
     uint32_t units_run = 0;            // units that entered the search loop (read_pack)
     bool bad_task = false;             // filled by read_pack: the work queue delivered an invalid task
+    bool bad_unit = false;             // filled by read_pack: a unit's lanes disagreed on its state
     size_t blob = 0, upload = 0, arena = 0, ctr_bytes = 0;
     size_t off_req = 0, off_pref = 0;  // in the blob
     std::vector<size_t> dom_at;        // in the arena: instance j's domains by pattern node
 };
 
+// The launch shape of a set of instances: sizes, kernel variant, unit
+// width, donation, used-set mode (fills pk.cfg, pk.m, pk.policy, pk.units).
+void launch_config(const sge_ctx *c, const InstanceSpec *const *specs, size_t m, bool dense, int policy, Pack &pk);
 // Lay out the descriptors and plan requests of `specs` (every one with k > 0)
 // in the pinned blob, with device addresses in bufs.d_blob / bufs.d_arena.
 sge_status pack_instances(sge_ctx *c, const std::vector<const InstanceSpec *> &specs, bool dense, int policy,
@@ -158,11 +175,14 @@ bool plan_on_device(const sge_ctx *c, const std::vector<const InstanceSpec *> &s
 bool general_instance(const InstanceSpec &s);
 // Upload, plan, reset, search and read back on `s` (asynchronous).  With
 // events, e0 and e1 are recorded right before and after the search kernel
-// (as event nodes when the stream is being captured).
+// (not while the stream is being captured: a batch graph gets event nodes
+// added after its capture).  With a split, the small plans of a large batch
+// run on a second stream beside the large ones.
 hipError_t enqueue_pack(sge_ctx *c, const Pack &pk, LaunchBufs &bufs, hipStream_t s, hipEvent_t e0 = nullptr,
-                        hipEvent_t e1 = nullptr, bool capturing = false);
+                        hipEvent_t e1 = nullptr, const PlanSplit *split = nullptr);
 // Upload and plan only (the plan of instance 0 is then read back by the caller).
-hipError_t enqueue_plan_only(const Pack &pk, LaunchBufs &bufs, uint32_t root_chunk, hipStream_t s);
+hipError_t enqueue_plan_only(const Pack &pk, LaunchBufs &bufs, uint32_t root_chunk, hipStream_t s,
+                             const PlanSplit *split = nullptr);
 // After the stream has drained: per-instance results and the kernel time.
 void read_pack(const sge_ctx *c, Pack &pk, const LaunchBufs &bufs, const std::vector<const InstanceSpec *> &specs,
                std::vector<InstanceOut *> &out, double &ms_search);

@@ -240,7 +240,8 @@ struct Sched {
     unsigned int p0[31];
     unsigned int done;         // set once every task is finished
     unsigned int abort;        // set when the launch's time limit is reached
-    unsigned int bad;          // set when a dequeued task fails validation (never expected)
+    unsigned int bad;          // 1: a dequeued task failed validation; 2: a unit's lanes disagreed
+                               // on its state (checked on request); never expected
     unsigned int units;        // units that entered the search loop
     unsigned int p1[28];
     unsigned long long t_start;  // earliest block start (s_memrealtime, 100 MHz)
@@ -274,6 +275,7 @@ struct LaunchCfg {
     int used_bitset = 1;      // CSR: a used-node bitset per unit in LDS (else the prefix is compared)
     int general = 0;          // some plan is directed or compares edge labels (CSR kernel with those checks)
     int count_bytes = 1;      // count each instance's algorithmic bytes
+    int check_uniform = 0;    // verify that a unit's lanes agree on its state every step
     uint32_t root_lo = 0, root_hi = 0xFFFFFFFFu;   // the first position's target-id range
 };
 
@@ -289,11 +291,23 @@ struct DevWork {
     size_t ctr_cap = 0;
 };
 
+// How a plan launch splits its requests (sorted by decreasing estimated
+// work): the first `big` get 1024-thread workgroups, the rest 256-thread
+// ones, launched on stream s2 beside the large ones (fork and join events
+// order them with the launch's stream; without s2 they follow on it).
+struct PlanSplit {
+    uint32_t big = 0;
+    hipStream_t s2 = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    const char **step = nullptr;   // when set: the step the launch was at (for error messages)
+};
 // Plan `m` instances (one workgroup each), then set every instance's root
 // chunks and the chunk prefix: `policy` 1 = one chunk per instance, else
 // `root_chunk` candidates per chunk, or (0) the total roots over 4 * `units`.
+// Without a split every request gets a 1024-thread workgroup.
 hipError_t launch_plan(const PlanIn *reqs, uint32_t m, uint32_t wmax, uint32_t kmax, InstDesc *desc, unsigned *chunk_prefix,
-                       int policy, uint32_t root_chunk, uint64_t units, hipStream_t s);
+                       int policy, uint32_t root_chunk, uint64_t units, hipStream_t s,
+                       const PlanSplit *split = nullptr);
 // LDS words of the plan kernel's support buffer (larger W uses PlanIn::support).
 constexpr uint32_t PLAN_LDS_WORDS = 2048;
 
@@ -307,6 +321,9 @@ size_t search_lds_bytes(const LaunchCfg &cfg);
 // Threads per block of the search kernel (256, 128 or 64; 0: one unit's LDS
 // does not fit in 64 KiB).
 int search_block_threads(const LaunchCfg &cfg);
+// The search kernel function launch_search launches for `cfg` (to find its
+// node in a captured graph).
+const void *search_kernel_fn(const LaunchCfg &cfg);
 // Clear the scheduling words of a launch (a fill kernel; usable in a captured graph).
 hipError_t launch_reset(DevWork &w, uint32_t ninst, hipStream_t s);
 

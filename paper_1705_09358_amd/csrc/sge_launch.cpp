@@ -32,28 +32,29 @@ bool general_instance(const InstanceSpec &s) {
 }
 
 bool choose_dense(const sge_ctx *c, const std::vector<InstanceSpec> &specs) {
+    return choose_dense(c, specs.data(), specs.size());
+}
+
+bool choose_dense(const sge_ctx *c, const InstanceSpec *specs, size_t m) {
     // dense-bitset search when every target has adjacency rows and is dense
     // enough that a row of W words costs no more than walking a neighbour list;
     // directed or edge-labelled searches take the CSR kernel
-    if (c->dense == 0 || specs.empty()) return false;
-    for (const InstanceSpec &s : specs)
-        if (general_instance(s)) return false;
+    if (c->dense == 0 || m == 0) return false;
     bool all_adj = true;
     double deg = 0, words = 0;
-    for (const InstanceSpec &s : specs) {
+    LaunchCfg probe;   // every search unit holds k rows of W words in LDS: the launch must fit
+    probe.dense = 1;
+    for (size_t j = 0; j < m; j++) {
+        const InstanceSpec &s = specs[j];
+        if (general_instance(s)) return false;
         all_adj &= s.t->d_adj != nullptr;
         deg += s.t->g.n ? (double)s.t->g.col.size() / s.t->g.n : 0.0;
         words += s.t->W;
-    }
-    if (!all_adj) return false;
-    // every search unit holds k rows of W words in LDS: the launch must fit
-    LaunchCfg probe;
-    probe.dense = 1;
-    for (const InstanceSpec &s : specs) {
         probe.kmax = std::max(probe.kmax, s.p->g.n);
         probe.nmax = std::max(probe.nmax, s.t->g.n);
         probe.wmax = std::max(probe.wmax, s.t->W);
     }
+    if (!all_adj) return false;
     probe.lanes = c->lanes ? c->lanes : 8;
     if (!c->lanes)
         while (probe.lanes < 64 && (uint32_t)probe.lanes < probe.wmax) probe.lanes *= 2;
@@ -64,7 +65,7 @@ bool choose_dense(const sge_ctx *c, const std::vector<InstanceSpec> &specs) {
 // Candidate-list entries of one instance: a parentless position either
 // starts a pattern component (at most n candidates) or, in the RI-DS modes,
 // holds a singleton domain placed first (one candidate).
-static uint64_t list_entries(const InstanceSpec &s) {
+uint64_t list_entries(const InstanceSpec &s) {
     return (uint64_t)std::max<uint32_t>(s.p->ncomp, 1) * s.t->g.n + s.p->g.n;
 }
 
@@ -81,10 +82,11 @@ uint64_t instance_device_bytes(const InstanceSpec &s) {
            list_entries(s) * 4 + (W > PLAN_LDS_WORDS ? W * 8 : 0);
 }
 
-static int auto_lanes(const std::vector<const InstanceSpec *> &specs) {
+static int auto_lanes(const InstanceSpec *const *specs, size_t m) {
     double deg = 0;
     uint64_t cnt = 0;
-    for (const InstanceSpec *s : specs) {
+    for (size_t j = 0; j < m; j++) {
+        const InstanceSpec *s = specs[j];
         deg += (double)s->t->g.col.size();
         cnt += s->t->g.n;
     }
@@ -112,26 +114,26 @@ static hipError_t ensure_work(DevWork &w, uint32_t m) {
 }
 
 // Launch shape shared by both packings: sizes, kernel variant, unit width.
-static void launch_config(const sge_ctx *c, const std::vector<const InstanceSpec *> &specs, bool dense, int policy,
-                          Pack &pk) {
+void launch_config(const sge_ctx *c, const InstanceSpec *const *specs, size_t m, bool dense, int policy, Pack &pk) {
     pk = Pack{};
-    pk.m = (uint32_t)specs.size();
+    pk.m = (uint32_t)m;
     pk.policy = policy;
     LaunchCfg &cfg = pk.cfg;
-    for (const InstanceSpec *sp : specs) {
+    for (size_t j = 0; j < m; j++) {
+        const InstanceSpec *sp = specs[j];
         cfg.kmax = std::max(cfg.kmax, sp->p->g.n);
         cfg.nmax = std::max(cfg.nmax, sp->t->g.n);
         cfg.wmax = std::max(cfg.wmax, sp->t->W);
+        cfg.general |= general_instance(*sp) ? 1 : 0;
     }
     cfg.dense = dense ? 1 : 0;
-    for (const InstanceSpec *sp : specs) cfg.general |= general_instance(*sp) ? 1 : 0;
     if (c->lanes) {
         cfg.lanes = c->lanes;
     } else if (dense) {
         cfg.lanes = 8;
         while (cfg.lanes < 64 && (uint32_t)cfg.lanes < cfg.wmax) cfg.lanes *= 2;
     } else {
-        cfg.lanes = auto_lanes(specs);
+        cfg.lanes = auto_lanes(specs, m);
     }
     cfg.donate = c->donate;
     cfg.per_cu = c->per_cu;
@@ -141,6 +143,7 @@ static void launch_config(const sge_ctx *c, const std::vector<const InstanceSpec
     cfg.used_bitset = 1;
     if (!dense && search_block_threads(cfg) < 256) cfg.used_bitset = 0;
     cfg.count_bytes = c->count_bytes;
+    cfg.check_uniform = c->check_uniform;
     cfg.root_lo = c->root_lo;
     cfg.root_hi = c->root_hi;
     // approximate number of search units (for the root chunk size): up to
@@ -151,7 +154,7 @@ static void launch_config(const sge_ctx *c, const std::vector<const InstanceSpec
 sge_status pack_instances(sge_ctx *c, const std::vector<const InstanceSpec *> &specs, bool dense, int policy,
                           LaunchBufs &bufs, Pack &pk) {
     const uint32_t m = (uint32_t)specs.size();
-    launch_config(c, specs, dense, policy, pk);
+    launch_config(c, specs.data(), specs.size(), dense, policy, pk);
     pk.device_plan = true;
     // blob (uploaded): descriptors | plan requests | chunk prefix (device-written)
     const size_t off_desc = 0;
@@ -251,7 +254,7 @@ sge_status pack_host_planned(sge_ctx *c, const std::vector<const InstanceSpec *>
                              const std::vector<const std::vector<uint64_t> *> &bits, bool dense, int policy,
                              LaunchBufs &bufs, Pack &pk) {
     const uint32_t m = (uint32_t)specs.size();
-    launch_config(c, specs, dense, policy, pk);
+    launch_config(c, specs.data(), specs.size(), dense, policy, pk);
     pk.device_plan = false;
     // blob (uploaded whole): descriptors | chunk prefix | plans | lists | bits
     const size_t off_desc = 0;
@@ -341,30 +344,32 @@ sge_status pack_host_planned(sge_ctx *c, const std::vector<const InstanceSpec *>
     return SGE_OK;
 }
 
-hipError_t enqueue_plan_only(const Pack &pk, LaunchBufs &bufs, uint32_t root_chunk, hipStream_t s) {
+hipError_t enqueue_plan_only(const Pack &pk, LaunchBufs &bufs, uint32_t root_chunk, hipStream_t s,
+                             const PlanSplit *split) {
     hipError_t r;
     if ((r = hipMemcpyAsync(bufs.d_blob.p, bufs.h_blob.p, pk.upload, hipMemcpyHostToDevice, s)) != hipSuccess)
         return r;
     return launch_plan((const PlanIn *)((char *)bufs.d_blob.p + pk.off_req), pk.m, pk.cfg.wmax, pk.cfg.kmax,
-                       bufs.work.inst, bufs.work.chunk_prefix, pk.policy, root_chunk, pk.units, s);
+                       bufs.work.inst, bufs.work.chunk_prefix, pk.policy, root_chunk, pk.units, s, split);
 }
 
 hipError_t enqueue_pack(sge_ctx *c, const Pack &pk, LaunchBufs &bufs, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
-                        bool capturing) {
+                        const PlanSplit *split) {
     hipError_t r;
-    if (pk.device_plan) r = enqueue_plan_only(pk, bufs, c->root_chunk, s);
+    c->enqueue_step = pk.device_plan ? "upload and plan kernels" : "upload";
+    if (pk.device_plan) r = enqueue_plan_only(pk, bufs, c->root_chunk, s, split);
     else r = hipMemcpyAsync(bufs.d_blob.p, bufs.h_blob.p, pk.upload, hipMemcpyHostToDevice, s);
     if (r != hipSuccess) return r;
+    c->enqueue_step = "reset kernel";
     if ((r = launch_reset(bufs.work, pk.m, s)) != hipSuccess) return r;
-    // inside a capture an event record becomes a node of the graph only with
-    // the external flag
-    auto record = [&](hipEvent_t ev) {
-        return capturing ? hipEventRecordWithFlags(ev, s, hipEventRecordExternal) : hipEventRecord(ev, s);
-    };
-    if (e0 && (r = record(e0)) != hipSuccess) return r;
+    c->enqueue_step = "record the kernel's start event";
+    if (e0 && (r = hipEventRecord(e0, s)) != hipSuccess) return r;
+    c->enqueue_step = "search kernel";
     if ((r = launch_search(pk.cfg, bufs.work, pk.m, c->cap, c->time_limit_ms, s, c->num_cus)) != hipSuccess)
         return r;
-    if (e1 && (r = record(e1)) != hipSuccess) return r;
+    c->enqueue_step = "record the kernel's end event";
+    if (e1 && (r = hipEventRecord(e1, s)) != hipSuccess) return r;
+    c->enqueue_step = "read-back";
     if ((r = hipMemcpyAsync(bufs.h_ctr.p, bufs.work.ctr, pk.m * sizeof(InstCounters), hipMemcpyDeviceToHost, s)) !=
         hipSuccess)
         return r;
@@ -383,7 +388,8 @@ void read_pack(const sge_ctx *c, Pack &pk, const LaunchBufs &bufs, const std::ve
     pk.ms_done = since(hs->t_done);
     pk.busy_ms = (double)hs->t_busy / 1e5;
     pk.units_run = hs->units;
-    pk.bad_task = hs->bad != 0;
+    pk.bad_task = hs->bad == 1;
+    pk.bad_unit = hs->bad == 2;
     for (uint32_t j = 0; j < pk.m; j++) {
         InstanceOut &o = *out[j];
         o.matches = hc[j].matches;
@@ -393,7 +399,7 @@ void read_pack(const sge_ctx *c, Pack &pk, const LaunchBufs &bufs, const std::ve
         o.steps = hc[j].steps;
         o.bytes = hc[j].bytes;
         o.status = SGE_OK;
-        if (pk.bad_task) {
+        if (pk.bad_task || pk.bad_unit) {
             o.status = SGE_E_DEVICE;
         } else if (hs->abort) {
             o.status = SGE_E_ABORTED;
@@ -404,6 +410,37 @@ void read_pack(const sge_ctx *c, Pack &pk, const LaunchBufs &bufs, const std::ve
             o.status = SGE_E_OVERFLOW;
         }
     }
+}
+
+// Event-record nodes around the search kernel's node of a captured graph:
+// e0 after everything the kernel waits for, the kernel after e0, e1 after
+// the kernel (the nodes after the kernel keep waiting on it directly).
+static hipError_t add_kernel_events(hipGraph_t g, const void *fn, hipEvent_t e0, hipEvent_t e1) {
+    if (!fn || !e0 || !e1) return hipErrorInvalidValue;
+    size_t n = 0;
+    hipError_t e = hipGraphGetNodes(g, nullptr, &n);
+    if (e != hipSuccess) return e;
+    std::vector<hipGraphNode_t> nodes(n);
+    if ((e = hipGraphGetNodes(g, nodes.data(), &n)) != hipSuccess) return e;
+    hipGraphNode_t kern = nullptr;
+    for (hipGraphNode_t nd : nodes) {
+        hipGraphNodeType t;
+        if (hipGraphNodeGetType(nd, &t) != hipSuccess || t != hipGraphNodeTypeKernel) continue;
+        hipKernelNodeParams kp{};
+        if (hipGraphKernelNodeGetParams(nd, &kp) == hipSuccess && kp.func == fn) {
+            kern = nd;
+            break;
+        }
+    }
+    if (!kern) return hipErrorNotFound;
+    size_t nd = 0;
+    if ((e = hipGraphNodeGetDependencies(kern, nullptr, &nd)) != hipSuccess) return e;
+    std::vector<hipGraphNode_t> deps(nd);
+    if (nd && (e = hipGraphNodeGetDependencies(kern, deps.data(), &nd)) != hipSuccess) return e;
+    hipGraphNode_t n0 = nullptr, n1 = nullptr;
+    if ((e = hipGraphAddEventRecordNode(&n0, g, deps.data(), nd, e0)) != hipSuccess) return e;
+    if ((e = hipGraphAddDependencies(g, &n0, &kern, 1)) != hipSuccess) return e;
+    return hipGraphAddEventRecordNode(&n1, g, &kern, 1, e1);
 }
 
 // Everything a captured batch graph depends on besides the contents of the
@@ -422,7 +459,8 @@ static uint64_t graph_key(const sge_ctx *c, const Pack &pk, const LaunchBufs &b,
                        (uint64_t)pk.off_req, (uint64_t)pk.ctr_bytes, (uint64_t)pk.policy, (uint64_t)pk.units,
                        (uint64_t)g.lanes, (uint64_t)g.dense, (uint64_t)g.donate, (uint64_t)g.kmax, (uint64_t)g.nmax,
                        (uint64_t)g.wmax, (uint64_t)g.blocks, (uint64_t)g.per_cu, (uint64_t)g.used_bitset,
-                       (uint64_t)g.general, (uint64_t)g.count_bytes, (uint64_t)g.root_lo, (uint64_t)g.root_hi,
+                       (uint64_t)g.general, (uint64_t)g.count_bytes, (uint64_t)g.check_uniform,
+                       (uint64_t)g.root_lo, (uint64_t)g.root_hi,
                        (uint64_t)(uintptr_t)b.d_blob.p, (uint64_t)(uintptr_t)b.h_blob.p,
                        (uint64_t)(uintptr_t)b.h_ctr.p, (uint64_t)(uintptr_t)b.work.sched,
                        (uint64_t)(uintptr_t)b.work.queue, (uint64_t)(uintptr_t)b.work.ctr,
@@ -526,19 +564,53 @@ sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std
             }
             hipGraph_t g = nullptr;
             hipGraphExec_t ge = nullptr;
-            if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-                return hip_fail(c, e, "hipStreamBeginCapture");
-            hipError_t er = enqueue_pack(c, pk, c->bufs, s, c->ev0, c->ev1, true);
-            e = hipStreamEndCapture(s, &g);
-            if (er != hipSuccess || e != hipSuccess) {
+            // with the small plans on a second stream beside the largest (one
+            // per CU) and event-record nodes right before and after the search
+            // kernel's node; should the runtime refuse either, the graph is
+            // captured again without them (the events then time nothing) and
+            // later captures leave them out
+            if (c->gev0) (void)hipEventDestroy(c->gev0);
+            if (c->gev1) (void)hipEventDestroy(c->gev1);
+            c->gev0 = c->gev1 = nullptr;
+            if (c->graph_extras &&
+                (hipEventCreate(&c->gev0) != hipSuccess || hipEventCreate(&c->gev1) != hipSuccess)) {
+                c->graph_extras = false;
+                c->graph_extras_error = "hipEventCreate";
+            }
+            hipError_t er = hipSuccess;
+            for (int attempt = c->graph_extras ? 0 : 1; attempt < 2; attempt++) {
+                (void)hipGetLastError();
+                if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                    return hip_fail(c, e, "hipStreamBeginCapture");
+                PlanSplit split;
+                split.big = (uint32_t)c->num_cus;
+                split.s2 = c->plan_s2;
+                split.fork = c->plan_fork;
+                split.join = c->plan_join;
+                split.step = &c->enqueue_step;
+                er = enqueue_pack(c, pk, c->bufs, s, nullptr, nullptr, attempt == 0 ? &split : nullptr);
+                e = hipStreamEndCapture(s, &g);
+                if (er == hipSuccess && e == hipSuccess && attempt == 0) {
+                    c->enqueue_step = "event nodes around the search kernel";
+                    er = add_kernel_events(g, search_kernel_fn(pk.cfg), c->gev0, c->gev1);
+                }
+                if (er == hipSuccess && e == hipSuccess) break;
                 if (g) (void)hipGraphDestroy(g);
-                return hip_fail(c, er != hipSuccess ? er : e, "capture search graph");
+                g = nullptr;
+                if (attempt == 1) return hip_fail(c, er != hipSuccess ? er : e, "capture search graph");
+                c->graph_extras = false;
+                c->graph_extras_error = (er != hipSuccess ? std::string("enqueue (") + c->enqueue_step + "): "
+                                                          : std::string("end capture: ")) +
+                                        hipGetErrorString(er != hipSuccess ? er : e);
+                // not an error of this call: kept as the context's message for inspection
+                c->err = "batch graph captured without the kernel's event nodes (" + c->graph_extras_error + ")";
             }
             e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
             c->gexec = ge;
             c->gexec_key = key;
+            c->gexec_timed = c->graph_extras;
         }
         e = hipGraphLaunch(c->gexec, s);
         hipError_t es = hipStreamSynchronize(s);
@@ -550,14 +622,17 @@ sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std
         if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
         if (es != hipSuccess) return hip_fail(c, es, "search");
     } else {
-        if ((e = enqueue_pack(c, pk, c->bufs, s, c->ev0, c->ev1, false)) != hipSuccess)
+        if ((e = enqueue_pack(c, pk, c->bufs, s, c->ev0, c->ev1)) != hipSuccess)
             return hip_fail(c, e, "search launch");
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "search");
     }
     read_pack(c, pk, c->bufs, sp, op, ms_search);
     float ev_ms = 0;
-    c->last_event_ms =
-        c->ev0 && c->ev1 && hipEventElapsedTime(&ev_ms, c->ev0, c->ev1) == hipSuccess ? (double)ev_ms : 0.0;
+    // this launch recorded the kernel's events: plain records, or the event
+    // nodes of the graph
+    hipEvent_t k0 = graph ? (c->gexec_timed ? c->gev0 : nullptr) : c->ev0;
+    hipEvent_t k1 = graph ? (c->gexec_timed ? c->gev1 : nullptr) : c->ev1;
+    c->last_event_ms = k0 && k1 && hipEventElapsedTime(&ev_ms, k0, k1) == hipSuccess ? (double)ev_ms : 0.0;
     c->last_ms[0] = ms_search;
     c->last_ms[1] = pk.ms_work;
     c->last_ms[2] = pk.ms_done;
@@ -565,6 +640,8 @@ sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std
     c->last_units = pk.units_run;
     c->last_lanes = pk.cfg.lanes;
     if (pk.bad_task) return fail(c, SGE_E_DEVICE, "the work queue delivered an invalid task; counters are unreliable");
+    if (pk.bad_unit)
+        return fail(c, SGE_E_DEVICE, "the lanes of a search unit disagreed on its state; counters are unreliable");
     if (op[0]->timed_out) c->err = "search stopped at the time limit; counters are partial";
     return SGE_OK;
 }

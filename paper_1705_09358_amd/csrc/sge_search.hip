@@ -67,6 +67,7 @@ struct SearchArgs {
     unsigned min_blocks;              // blocks kept whatever the number of root chunks
     unsigned units_per_block;
     unsigned count_bytes;             // count the algorithmic bytes of the search (InstCounters::bytes)
+    unsigned check_uniform;           // verify every step that per-unit values agree across the unit's lanes
     unsigned root_lo, root_hi;        // the first position's target-id range
 };
 
@@ -798,6 +799,30 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
         WAVE_SYNC();
         since_donate++;
         c_steps++;
+        if (a.check_uniform) {
+            // a unit's state is held by each of its lanes: every copy must be
+            // the same (a disagreement is reported, the search goes on)
+            bool diff = false;
+            auto same = [&](unsigned x) { diff |= x != (unsigned)__shfl((int)x, gbase); };
+            same(inst);
+            same(lvl);
+            same(base);
+            same(etop);
+            same(k);
+            if constexpr (DENSE) {
+                same(D.fc[lvl]);
+                same(D.hw[lvl]);
+                same(D.M[lvl > 0 ? lvl - 1 : 0]);
+            } else {
+                same(L.cur[lvl]);
+                same(L.end[lvl]);
+                same(L.eb[lvl]);
+                same(L.dn[lvl]);
+                same(L.lb[lvl]);
+                same(L.M[lvl > 0 ? lvl - 1 : 0]);
+            }
+            if (group_mask<G>(__ballot(diff), gbase) != 0 && gl == 0) st_rlx(&S->bad, 2u);
+        }
         if constexpr (DENSE) {
             // pop exhausted frames
             bool task_done = false;
@@ -1280,6 +1305,26 @@ int block_threads(const LaunchCfg &cfg) {
 
 int search_block_threads(const LaunchCfg &cfg) { return block_threads(cfg); }
 
+const void *search_kernel_fn(const LaunchCfg &cfg) {
+    auto pick = [&](auto k8, auto k16, auto k32, auto k64) -> const void * {
+        switch (cfg.lanes) {
+            case 8: return (const void *)k8;
+            case 16: return (const void *)k16;
+            case 32: return (const void *)k32;
+            case 64: return (const void *)k64;
+            default: return nullptr;
+        }
+    };
+    if (cfg.dense)
+        return pick(search_kernel<8, true, false>, search_kernel<16, true, false>, search_kernel<32, true, false>,
+                    search_kernel<64, true, false>);
+    if (cfg.general)
+        return pick(search_kernel<8, false, true>, search_kernel<16, false, true>, search_kernel<32, false, true>,
+                    search_kernel<64, false, true>);
+    return pick(search_kernel<8, false, false>, search_kernel<16, false, false>, search_kernel<32, false, false>,
+                search_kernel<64, false, false>);
+}
+
 size_t search_lds_bytes(const LaunchCfg &cfg) {
     int t = block_threads(cfg);
     return (size_t)unit_words(cfg) * 4 * (size_t)((t ? t : 64) / cfg.lanes);
@@ -1294,6 +1339,7 @@ hipError_t launch_search(const LaunchCfg &cfg, DevWork &w, uint32_t ninst, uint6
                          uint64_t time_limit_ms, hipStream_t s, int num_cus) {
     SearchArgs a{};
     a.count_bytes = cfg.count_bytes ? 1u : 0u;
+    a.check_uniform = cfg.check_uniform ? 1u : 0u;
     a.root_lo = cfg.root_lo;
     a.root_hi = cfg.root_hi;
     a.inst = w.inst;

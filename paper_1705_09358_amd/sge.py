@@ -28,7 +28,7 @@ EXPORTS = [
     "sge_count", "sge_enumerate", "sge_batch_run", "sge_set_batch_policy", "sge_serve_start", "sge_serve_submit",
     "sge_serve_poll", "sge_serve_stop", "sge_plan_host", "sge_plan_device", "sge_set_plan_location", "sge_set_tuning",
     "sge_set_time_limit", "sge_last_launch_timing", "sge_last_launch_occupancy", "sge_set_blocks_per_cu",
-    "sge_last_kernel_ms", "sge_set_count_bytes",
+    "sge_last_kernel_ms", "sge_set_count_bytes", "sge_set_checks",
 ]
 
 
@@ -152,6 +152,7 @@ def lib() -> ctypes.CDLL:
             "sge_set_blocks_per_cu": (I32, [P, I32]),
             "sge_last_kernel_ms": (I32, [P, ctypes.POINTER(ctypes.c_double)]),
             "sge_set_count_bytes": (I32, [P, I32]),
+            "sge_set_checks": (I32, [P, I32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -250,6 +251,10 @@ class Context:
     def set_count_bytes(self, on: bool):
         """Count each search's algorithmic bytes (Result.alg_bytes); on by default."""
         self._check(self._L.sge_set_count_bytes(self._h, int(bool(on))), "sge_set_count_bytes")
+
+    def set_checks(self, on: bool):
+        """Verify, every search step, that a unit's lanes agree on its state (for testing)."""
+        self._check(self._L.sge_set_checks(self._h, int(bool(on))), "sge_set_checks")
 
     def last_launch_occupancy(self):
         """(sum over units of the ms each held a task, units that entered the

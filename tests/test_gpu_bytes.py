@@ -188,7 +188,7 @@ def test_kernel_event_time(ctx):
             st, res = ctx.batch_run(jobs)
             ev = ctx.last_kernel_ms()
             dev = ctx.last_launch_timing()[0]
-            _note(f"batch replay {rep}: event {ev:.3f} ms, device clock {dev:.3f} ms")
+            _note(f"batch replay {rep}: event {ev:.3f} ms, device clock {dev:.3f} ms; {ctx.last_error()}")
             assert dev > 0 and 0.9 * dev <= ev <= dev + 0.5
         ctx.set_mode(0)
         ctx.set_labelled(True)
