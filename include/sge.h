@@ -191,6 +191,20 @@ sge_status sge_set_root_range(sge_ctx *ctx, uint32_t lo, uint32_t hi);
 /* Count the embeddings of `pattern` in `target`. */
 sge_status sge_count(sge_ctx *ctx, uint32_t target, uint32_t pattern, sge_result *res);
 
+/* For callers that cannot allocate device or pinned memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): as
+ * sge_count, with every buffer of the launch -- job descriptor, device plan,
+ * domains, candidate lists, scheduler words, work queue, counters -- in one
+ * static device array of 16 MiB per device (held from the library's load
+ * until the process ends), and the plan made by the plan kernel.  Calls no
+ * allocating routine.  The target and pattern must be loaded beforehand.
+ * SGE_E_INVAL when the instance needs more than the array (about
+ * 1.5 MiB + 16 k ceil(n/64) + 4 (components * n + k) bytes) or is directed
+ * or compares edge labels.  Every call on a device shares that device's
+ * array: calls that overlap on one device race (results undefined); calls in
+ * sequence are independent (the launch clears what must start at zero). */
+sge_status sge_count_noalloc(sge_ctx *ctx, uint32_t target, uint32_t pattern, sge_result *res);
+
 /* Enumerate: as sge_count, and write up to cap_rows rows of k uint32 to
  * `rows` (host or device pointer; device memory must be on the context's
  * device).  More matches than cap_rows: SGE_E_OVERFLOW with full counts. */

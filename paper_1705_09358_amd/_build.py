@@ -17,7 +17,7 @@ SYNTH_SO = os.path.join(LIBDIR, "libsynth_walk.so")
 # Host sources (plain C++) and device sources (HIP) of the search library.
 HOST_SRCS = ["sge_graph.cpp", "sge_plan.cpp", "sge_api.cpp", "sge_launch.cpp", "sge_batch.cpp", "sge_serve.cpp"]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__"]
-HIP_SRCS = ["sge_search.hip", "sge_plan_dev.hip"]
+HIP_SRCS = ["sge_search.hip", "sge_plan_dev.hip", "sge_noalloc.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -224,6 +224,9 @@ sge_status sge_create(int device, void *hip_stream, sge_ctx **out) {
     if (hipStreamCreateWithFlags(&c->plan_s2, hipStreamNonBlocking) != hipSuccess) c->plan_s2 = nullptr;
     (void)hipEventCreateWithFlags(&c->plan_fork, hipEventDisableTiming);
     (void)hipEventCreateWithFlags(&c->plan_join, hipEventDisableTiming);
+    // the allocation-free count's scratch array: its address on this device
+    // (a failure leaves that entry point reporting the error)
+    (void)noalloc_init(device);
     *out = c;
     return SGE_OK;
 }

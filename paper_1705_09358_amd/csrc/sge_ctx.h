@@ -187,6 +187,10 @@ hipError_t enqueue_plan_only(const Pack &pk, LaunchBufs &bufs, uint32_t root_chu
 void read_pack(const sge_ctx *c, Pack &pk, const LaunchBufs &bufs, const std::vector<const InstanceSpec *> &specs,
                std::vector<InstanceOut *> &out, double &ms_search);
 
+// The allocation-free count's static scratch array: record its address on
+// `device` (the current device), once per device.
+hipError_t noalloc_init(int device);
+
 // Device memory for a target's / pattern's resident data.
 sge_status upload_target(sge_ctx *c, Target &t);
 void free_target(Target &t);

@@ -28,7 +28,7 @@ EXPORTS = [
     "sge_count", "sge_enumerate", "sge_batch_run", "sge_set_batch_policy", "sge_serve_start", "sge_serve_submit",
     "sge_serve_poll", "sge_serve_stop", "sge_plan_host", "sge_plan_device", "sge_set_plan_location", "sge_set_tuning",
     "sge_set_time_limit", "sge_last_launch_timing", "sge_last_launch_occupancy", "sge_set_blocks_per_cu",
-    "sge_last_kernel_ms", "sge_set_count_bytes", "sge_set_checks",
+    "sge_last_kernel_ms", "sge_set_count_bytes", "sge_set_checks", "sge_count_noalloc",
 ]
 
 
@@ -153,6 +153,7 @@ def lib() -> ctypes.CDLL:
             "sge_last_kernel_ms": (I32, [P, ctypes.POINTER(ctypes.c_double)]),
             "sge_set_count_bytes": (I32, [P, I32]),
             "sge_set_checks": (I32, [P, I32]),
+            "sge_count_noalloc": (I32, [P, U32, U32, ctypes.POINTER(c_result)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -346,6 +347,14 @@ class Context:
         st = self._L.sge_count(self._h, target, pattern, ctypes.byref(r))
         if st not in allow:
             self._check(st, "sge_count")
+        return Result.of(st, r)
+
+    def count_noalloc(self, target: int, pattern: int, allow=(OK,)) -> Result:
+        """sge_count with every device buffer in the library's static scratch array."""
+        r = c_result()
+        st = self._L.sge_count_noalloc(self._h, target, pattern, ctypes.byref(r))
+        if st not in allow:
+            self._check(st, "sge_count_noalloc")
         return Result.of(st, r)
 
     def enumerate(self, target: int, pattern: int, k: int, cap_rows: int = 1 << 20, rows=None, allow=(OK,)):
