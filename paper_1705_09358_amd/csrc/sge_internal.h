@@ -292,7 +292,7 @@ struct DevWork {
 };
 
 // How a plan launch splits its requests (sorted by decreasing estimated
-// work): the first `big` get 1024-thread workgroups, the rest 256-thread
+// work): the first `big` get 1024-thread workgroups, the rest 512-thread
 // ones, launched on stream s2 beside the large ones (fork and join events
 // order them with the launch's stream; without s2 they follow on it).
 struct PlanSplit {

@@ -564,7 +564,7 @@ sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std
             }
             hipGraph_t g = nullptr;
             hipGraphExec_t ge = nullptr;
-            // with the small plans on a second stream beside the largest (one
+            // with the small plans on a second stream beside the largest (two
             // per CU) and event-record nodes right before and after the search
             // kernel's node; should the runtime refuse either, the graph is
             // captured again without them (the events then time nothing) and
@@ -583,7 +583,7 @@ sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std
                 if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
                     return hip_fail(c, e, "hipStreamBeginCapture");
                 PlanSplit split;
-                split.big = (uint32_t)c->num_cus;
+                split.big = 2u * (uint32_t)c->num_cus;
                 split.s2 = c->plan_s2;
                 split.fork = c->plan_fork;
                 split.join = c->plan_join;

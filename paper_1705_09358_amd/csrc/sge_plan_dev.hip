@@ -39,7 +39,7 @@ namespace {
 // 1 ms and the batch about 2 ms, bound by the one workgroup per CU that
 // resides at a time.
 constexpr int PLAN_THREADS = 1024;
-constexpr int SMALL_PLAN_THREADS = 256;   // the small plans of a large batch
+constexpr int SMALL_PLAN_THREADS = 512;   // the small plans of a large batch
 
 // Device memory in the global address space: the pointers a plan request
 // holds are loaded from memory, so the compiler would treat them as generic
@@ -551,9 +551,13 @@ hipError_t launch_plan(const PlanIn *reqs, uint32_t m, uint32_t wmax, uint32_t k
         (uint32_t)std::min<uint64_t>((uint64_t)std::max<uint32_t>(wmax, 1) * std::max<uint32_t>(kmax, 1), PLAN_LDS_WORDS);
     // The largest plans in 1024-thread workgroups (one resides per CU, its
     // latency-bound phases spread over 16 waves); the many small plans of a
-    // large batch in 256-thread workgroups, several per CU, which with
-    // 1024-thread workgroups would hold 16 waves each mostly waiting at
-    // barriers.  With a second stream the two launches run side by side.
+    // large batch in 512-thread workgroups, which with 1024-thread
+    // workgroups would hold 16 waves each mostly waiting at barriers.  With
+    // a second stream the two launches run side by side.  On the 4096-pair
+    // batch: one 1024-thread launch 1.89 ms; the 512 largest in 1024-thread
+    // and the rest in 512-thread workgroups side by side 1.12 and 0.88 ms
+    // (the rest in 256-thread workgroups: 2.36 ms; one after the other:
+    // 2.38 ms).
     const uint32_t big = split ? std::min(split->big, m) : m;
     const bool beside = split && split->s2 && split->fork && split->join && big < m && big > 0;
     hipError_t e;
