@@ -120,7 +120,10 @@ def c3_full(procs, log_path):
                         matches=sum(p["matches"] for p in parts), states=sum(p["states"] for p in parts),
                         candidates=sum(p["candidates"] for p in parts),
                         alg_bytes=sum(p["alg_bytes"] for p in parts),
-                        dense_bytes=sum(p["dense_bytes"] for p in parts),
+                        # the bitset model charges a search's root expansion (one
+                        # domain row of W words) once; every shard is a search
+                        # of its own and charges it again
+                        dense_bytes=sum(p["dense_bytes"] for p in parts) - (len(parts) - 1) * 8 * ((n + 63) // 64),
                         sha256=oracle.rows_digest(rows, inst.pattern.n), shards=len(parts),
                         oracle_s=round(sum(p["oracle_s"] for p in parts), 1)))
     return out

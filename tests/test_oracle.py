@@ -440,3 +440,21 @@ def test_bytes_exclude_rows(orc):
         b = orc.run(inst.pattern, inst.target, mode, True, rows=True)
         assert b["matches"] > 0
         assert (a["alg_bytes"], a["dense_bytes"]) == (b["alg_bytes"], b["dense_bytes"])
+
+
+def test_bytes_over_root_shards(orc):
+    """Disjoint root ranges partition a search: states, matches and the
+    sparse bytes add up exactly; the bitset model charges each search's root
+    expansion (one domain row) once, so the shards' dense bytes exceed the
+    whole search's by one row per extra shard (the rule the full-size dense
+    golden values are summed by)."""
+    inst = synth.c1_instance(7)
+    T, P = inst.target, inst.pattern
+    W = (T.n + 63) // 64
+    for mode in (0, 3):
+        whole = orc.run(P, T, mode, True)
+        cuts = [0, 37, 90, 150, T.n]
+        parts = [orc.run(P, T, mode, True, root_range=(a, b)) for a, b in zip(cuts, cuts[1:])]
+        for key in ("states", "matches", "alg_bytes"):
+            assert sum(p[key] for p in parts) == whole[key]
+        assert sum(p["dense_bytes"] for p in parts) - (len(parts) - 1) * 8 * W == whole["dense_bytes"]
