@@ -137,11 +137,13 @@ void launch_config(const sge_ctx *c, const InstanceSpec *const *specs, size_t m,
     }
     cfg.donate = c->donate;
     cfg.per_cu = c->per_cu;
-    // a used-node bitset per search unit (n bits of LDS) while a block of
-    // four waves still fits; larger targets compare candidates with the
-    // mapped prefix instead (at most 63 entries), which fits any n
+    // a used-node bitset per search unit (n bits of LDS) unless it would
+    // shrink the block; larger targets compare candidates with the mapped
+    // prefix instead (at most 63 entries), which fits any n
+    cfg.used_bitset = 0;
+    const int without = search_block_threads(cfg);
     cfg.used_bitset = 1;
-    if (!dense && search_block_threads(cfg) < 256) cfg.used_bitset = 0;
+    if (!dense && search_block_threads(cfg) < without) cfg.used_bitset = 0;
     cfg.count_bytes = c->count_bytes;
     cfg.check_uniform = c->check_uniform;
     cfg.root_lo = c->root_lo;

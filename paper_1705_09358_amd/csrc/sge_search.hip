@@ -163,10 +163,16 @@ struct UnitLds {
     unsigned *cur, *end, *lb;     // frame: next candidate index, list length, list start
     unsigned *eb, *dn;            // frame: first stack entry, entries given away from the bottom
     unsigned *ev, *ebg, *edg;     // stack of accepted candidates: node, row start, degree
+    unsigned long long *tim;      // this unit's task start, time holding tasks, last task finish
     unsigned *used;               // bitset of mapped target nodes
 };
 
-__device__ __forceinline__ UnitLds carve(unsigned *base, unsigned kmax, unsigned E) {
+// The layout is fixed at KMAX positions and KMAX + G stack entries, so
+// every array is the unit's base plus a compile-time offset: one register
+// addresses all of them (immediate offsets of the LDS instructions).
+template <int G>
+__device__ __forceinline__ UnitLds carve(unsigned *base) {
+    constexpr unsigned kmax = KMAX, E = KMAX + G;
     UnitLds u;
     u.pback = reinterpret_cast<unsigned long long *>(base);   // the unit's area starts 8-byte aligned
     u.pp = reinterpret_cast<int *>(base + 2 * kmax);
@@ -183,7 +189,8 @@ __device__ __forceinline__ UnitLds carve(unsigned *base, unsigned kmax, unsigned
     u.ev = u.dn + kmax;
     u.ebg = u.ev + E;
     u.edg = u.ebg + E;
-    u.used = u.edg + E;
+    u.tim = reinterpret_cast<unsigned long long *>(u.edg + E);   // 8-byte aligned: 13 kmax + 3 E is even
+    u.used = u.edg + E + 6;
     return u;
 }
 
@@ -194,6 +201,7 @@ struct DenseLds {
     unsigned *hw;                 // frame: words at or above this index were given away
     unsigned long long *cand;     // frame: candidate set, kmax rows of W words
     unsigned long long *used;     // bitset of mapped target nodes (W words)
+    unsigned long long *tim;      // this unit's task start, time holding tasks, last task finish
 };
 
 __host__ __device__ inline unsigned even(unsigned x) { return x + (x & 1u); }
@@ -205,6 +213,7 @@ __device__ __forceinline__ DenseLds carve_dense(unsigned *base, unsigned kmax, u
     u.hw = u.fc + even(kmax);
     u.cand = reinterpret_cast<unsigned long long *>(u.hw + even(kmax));
     u.used = u.cand + (size_t)kmax * W;
+    u.tim = u.used + W;
     return u;
 }
 
@@ -307,10 +316,13 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
         D = carve_dense(lds + (size_t)unit * a.unit_words, a.kmax, a.W);
         for (unsigned i = gl; i < a.W; i += G) D.used[i] = 0;
         L.M = D.M;
+        L.tim = D.tim;
     } else {
-        L = carve(lds + (size_t)unit * a.unit_words, a.kmax, a.E);
+        L = carve<G>(lds + (size_t)unit * a.unit_words);
         for (unsigned i = gl; i < a.UW; i += G) L.used[i] = 0;
     }
+    // the unit's timing words live in LDS (written once per task)
+    if (gl < 3) L.tim[gl] = 0;
     const unsigned WS = a.W;   // LDS row stride of the dense frames
 
     Sched *S = a.sched;
@@ -352,24 +364,28 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
     unsigned inst = NO_TASK, cinst = NO_TASK, lvl = 0, base = 0, etop = 0, k = 0, W = 0;
     GDesc d{};
     gp<const DevPlan> P = nullptr;
-    unsigned long long c_states = 0, c_matches = 0, c_cands = 0, c_steals = 0, c_steps = 0;
+    // counts not yet added to the instance's counters: 32 bits, flushed at
+    // 8192 states or 2^20 steps (so no count can wrap)
+    unsigned c_states = 0, c_matches = 0, c_cands = 0, c_steals = 0, c_steps = 0;
     // algorithmic bytes (counted when a.count_bytes): c_bytes per unit (the
-    // same in its lanes), lane_bytes per lane, summed over the unit at a flush
-    unsigned long long c_bytes = 0, lane_bytes = 0;
+    // same in its lanes), lane_bytes per lane (at most 2^20 steps of under
+    // 600 bytes), summed over the unit at a flush
+    unsigned long long c_bytes = 0;
+    unsigned lane_bytes = 0;
     bool roots_done = false;
     unsigned since_donate = 0;     // steps since this unit's task began or it last gave work away
     unsigned iter = 0, backoff = 0, polls = 0;
     bool donate_hint = false;
     unsigned cn_seen = 0;          // the root chunk counter as this wave last read it
-    unsigned long long last_finish = 0;   // device clock of this wave's last task finish
-    unsigned long long busy_ticks = 0, task_t0 = 0;   // this unit's time holding tasks
+    // timing of this unit's tasks, in LDS: tim[0] start of the current task,
+    // tim[1] ticks spent holding tasks, tim[2] the last task's finish
     // every wave ends by the deadline, whatever the state of the search
     const unsigned long long deadline = a.limit_ticks ? now_ticks() + a.limit_ticks : ~0ull;
 
-    // `fold`: every lane of the unit is here, so the per-lane bytes can be summed
-    auto flush = [&](bool fold) {
-        if (fold && a.count_bytes) {
-            c_bytes += group_sum64<G>(lane_bytes);
+    // every lane of the unit is here, so the per-lane bytes can be summed
+    auto flush = [&]() {
+        if (a.count_bytes) {
+            c_bytes += group_sum64<G>((unsigned long long)lane_bytes);
             lane_bytes = 0;
         }
         if (cinst != NO_TASK && gl == 0) {
@@ -512,8 +528,11 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
         // a unit that gave work away during the task has already waited for
         // that task's `created` count to complete
         if (gl == 0) fadd(&HG->finished, 1);
-        last_finish = now_ticks();
-        busy_ticks += last_finish - task_t0;
+        const unsigned long long fin = now_ticks();
+        if (gl == 0) {
+            L.tim[1] += fin - L.tim[0];
+            L.tim[2] = fin;
+        }
         inst = NO_TASK;
         etop = 0;
     };
@@ -690,7 +709,7 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                     }
                     // start the task
                     if (ti != cinst) {
-                        flush(true);
+                        flush();
                         cinst = ti;
                         d = gdesc(glob(a.inst) + ti);
                         P = d.plan;
@@ -707,7 +726,7 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                         }
                     }
                     inst = ti;
-                    task_t0 = now_ticks();
+                    if (gl == 0) L.tim[0] = now_ticks();
                     since_donate = 0;
                     if (kind == 1) c_steals++;
                     etop = 0;
@@ -833,7 +852,7 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                 if (gl == 0) unmark(D.M[lvl]);
             }
             if (task_done) {
-                if (c_states >= 4096) flush(true);
+                if (c_states >= 4096) flush();
                 drop_task(base);
                 continue;
             }
@@ -862,7 +881,7 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                 if (gl == 0) unmark(L.M[lvl]);
             }
             if (task_done) {
-                if (c_states >= 4096) flush(true);
+                if (c_states >= 4096) flush();
                 drop_task(base);
                 continue;
             }
@@ -1054,9 +1073,10 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
             }
         }
 
-        // counters: flush now and then so a state cap takes effect
-        if (c_states >= 8192) {
-            flush(true);
+        // counters: flush now and then so a state cap takes effect (and no
+        // 32-bit count wraps)
+        if (c_states >= 8192 || c_steps >= (1u << 20)) {
+            flush();
             if (a.state_cap && inst_aborted(inst)) {
                 drop_task(lvl);
                 continue;
@@ -1198,11 +1218,12 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
     // holding the same last instance, and atomics on one word serialise).
     // Every wave of the block reaches this point (the loop is left only by
     // `break`), and the units' LDS areas are free: each unit's area (at least
-    // 16 words) takes its exit record.
+    // 18 words) takes its exit record.
     if (a.count_bytes) {   // every lane is here: fold the per-lane bytes into the unit's
-        c_bytes += group_sum64<G>(lane_bytes);
+        c_bytes += group_sum64<G>((unsigned long long)lane_bytes);
         lane_bytes = 0;
     }
+    const unsigned long long busy_ticks = L.tim[1], last_finish = L.tim[2];   // before the record covers them
     __syncthreads();
     unsigned long long *rec = reinterpret_cast<unsigned long long *>(lds + (size_t)unit * a.unit_words);
     if (gl == 0) {
@@ -1226,17 +1247,24 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
         bool first = true;
         for (unsigned u = 0; u < (unsigned)unit && first; u++) first = rec_of(u)[0] != cinst;
         if (first) {
+            unsigned long long t[6] = {c_states, c_matches, c_cands, c_steals, c_steps, c_bytes};
             for (unsigned u = unit + 1; u < nunits; u++) {
                 const unsigned long long *r = rec_of(u);
                 if (r[0] != cinst) continue;
-                c_states += r[1];
-                c_matches += r[2];
-                c_cands += r[3];
-                c_steals += r[4];
-                c_steps += r[5];
-                c_bytes += r[8];
+                for (int i = 0; i < 5; i++) t[i] += r[1 + i];
+                t[5] += r[8];
             }
-            flush(false);
+            InstCounters *c = a.ctr + cinst;
+            if (t[5]) fadd64(&c->bytes, t[5]);
+            if (t[1]) fadd64(&c->matches, t[1]);
+            if (t[2]) fadd64(&c->candidates, t[2]);
+            if (t[3]) fadd64(&c->steals, t[3]);
+            if (t[4]) fadd64(&c->steps, t[4]);
+            if (t[0]) {
+                unsigned long long before = fadd64(&c->states, t[0]);
+                if (a.state_cap && before + t[0] > a.state_cap)
+                    __hip_atomic_store(&c->pad0, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
     }
     if (threadIdx.x == 0) {
@@ -1287,10 +1315,10 @@ hipError_t launch_g(SearchArgs args, int blocks, int per_cu_cap, int threads, si
 unsigned unit_words(const LaunchCfg &cfg) {
     // even: every unit's area starts 8-byte aligned; at least 18 words: the
     // area takes the unit's exit record (nine 64-bit values)
-    if (cfg.dense) return std::max(18u, 3 * even(cfg.kmax) + 2 * cfg.kmax * cfg.wmax + 2 * cfg.wmax);
-    unsigned E = cfg.kmax + cfg.lanes;
+    if (cfg.dense) return std::max(18u, 3 * even(cfg.kmax) + 2 * cfg.kmax * cfg.wmax + 2 * cfg.wmax + 6);
+    unsigned E = KMAX + cfg.lanes;
     unsigned UW = cfg.used_bitset ? (cfg.nmax + 31) / 32 : 0;
-    return std::max(18u, even(13 * cfg.kmax + 3 * E + UW));
+    return std::max(18u, even(13 * KMAX + 3 * E + 6 + UW));
 }
 
 // Largest block (256, 128 or 64 threads) whose units fit in 64 KiB of LDS.
@@ -1349,7 +1377,7 @@ hipError_t launch_search(const LaunchCfg &cfg, DevWork &w, uint32_t ninst, uint6
     a.queue = w.queue;
     a.ninst = ninst;
     a.kmax = cfg.kmax;
-    a.E = cfg.kmax + cfg.lanes;
+    a.E = cfg.dense ? cfg.kmax + cfg.lanes : KMAX + cfg.lanes;
     a.UW = cfg.used_bitset ? (cfg.nmax + 31) / 32 : 0;
     a.W = cfg.dense ? cfg.wmax : 0;
     a.unit_words = unit_words(cfg);
