@@ -23,7 +23,7 @@ sge_status sge_set_batch_policy(sge_ctx *c, int policy) {
 sge_status sge_batch_run(sge_ctx *c, uint32_t njobs, const sge_job *jobs, sge_result *results) {
     if (!c || (njobs && (!jobs || !results))) return SGE_E_INVAL;
     (void)hipSetDevice(c->device);
-    std::vector<InstanceSpec> specs(njobs);
+    std::vector<InstanceSpec> job_specs(njobs);
     for (uint32_t i = 0; i < njobs; i++) {
         auto it = c->targets.find(jobs[i].target);
         if (it == c->targets.end()) return fail(c, SGE_E_HANDLE, "job " + std::to_string(i) + ": unknown target");
@@ -31,28 +31,52 @@ sge_status sge_batch_run(sge_ctx *c, uint32_t njobs, const sge_job *jobs, sge_re
         if (ip == c->patterns.end()) return fail(c, SGE_E_HANDLE, "job " + std::to_string(i) + ": unknown pattern");
         if (jobs[i].mode < SGE_RI || jobs[i].mode > SGE_RIDS_SI_FC)
             return fail(c, SGE_E_INVAL, "job " + std::to_string(i) + ": unknown mode");
-        specs[i].t = it->second.get();
-        specs[i].p = ip->second.get();
-        specs[i].mode = jobs[i].mode;
-        specs[i].labelled = jobs[i].labelled != 0;
+        job_specs[i].t = it->second.get();
+        job_specs[i].p = ip->second.get();
+        job_specs[i].mode = jobs[i].mode;
+        job_specs[i].labelled = jobs[i].labelled != 0;
     }
+    std::vector<InstanceSpec> specs = job_specs;   // in launch order
     std::vector<InstanceOut> out;
     double mp = 0, ms = 0;
     int policy = c->batch_policy;
     const int saved_lanes = c->lanes, saved_donate = c->donate, saved_per_cu = c->per_cu;
+    // repeated runs of one batch (the same jobs) reuse the autotuner's choice
+    // and the steps each job took last time
+    uint64_t key = 1469598103934665603ull;   // a multiplicative hash of the job list, word by word
+    auto mix = [&](uint64_t v) {
+        key = (key ^ v) * 0x9E3779B97F4A7C15ull;
+        key ^= key >> 29;
+    };
+    mix(njobs);
+    for (uint32_t i = 0; i < njobs; i++) {
+        mix(jobs[i].target);
+        mix(jobs[i].pattern);
+        mix(((uint64_t)(uint32_t)jobs[i].mode << 1) | (jobs[i].labelled ? 1u : 0u));
+    }
+    // Longest first: root chunks are claimed in the order of the launch's
+    // instances, so an expensive instance late in the list starts late and
+    // finishes alone.  Once a job list has run, its next launches order the
+    // instances by the steps each took last time, most first (the first
+    // launch keeps the caller's order); results go back to job order.
+    std::vector<uint32_t> perm(njobs);
+    for (uint32_t i = 0; i < njobs; i++) perm[i] = i;
+    auto apply_order = [&](const std::vector<uint64_t> &steps) {
+        for (uint32_t i = 0; i < njobs; i++) perm[i] = i;
+        std::stable_sort(perm.begin(), perm.end(), [&](uint32_t a, uint32_t b) { return steps[a] > steps[b]; });
+        for (uint32_t i = 0; i < njobs; i++) specs[i] = job_specs[perm[i]];
+    };
+    auto record_steps = [&](const std::vector<InstanceOut> &o) {
+        std::vector<uint64_t> &steps = c->batch_steps[key];
+        steps.assign(njobs, 0);
+        for (uint32_t i = 0; i < njobs; i++) steps[perm[i]] = o[i].steps;
+    };
+    if (c->batch_steps.size() >= 256) c->batch_steps.clear();
+    {
+        auto hs = c->batch_steps.find(key);
+        if (hs != c->batch_steps.end() && hs->second.size() == njobs) apply_order(hs->second);
+    }
     if (policy == 0) {
-        // repeated runs of one batch (the same jobs) reuse the choice
-        uint64_t key = 1469598103934665603ull;   // a multiplicative hash of the job list, word by word
-        auto mix = [&](uint64_t v) {
-            key = (key ^ v) * 0x9E3779B97F4A7C15ull;
-            key ^= key >> 29;
-        };
-        mix(njobs);
-        for (uint32_t i = 0; i < njobs; i++) {
-            mix(jobs[i].target);
-            mix(jobs[i].pattern);
-            mix(((uint64_t)(uint32_t)jobs[i].mode << 1) | (jobs[i].labelled ? 1u : 0u));
-        }
         auto it = c->batch_tune.find(key);
         if (it == c->batch_tune.end()) {
             // autotune on this batch, starting from the default shape (root
@@ -96,10 +120,18 @@ sge_status sge_batch_run(sge_ctx *c, uint32_t njobs, const sge_job *jobs, sge_re
             double best = 1e300;
             BatchTune cur{2, saved_lanes, saved_donate, saved_per_cu};
             bool stop = false;
+            bool ordered_now = c->batch_steps.count(key) != 0;
             auto trial = [&](BatchTune t) -> sge_status {
                 if (stop || (t.lanes && timed_before(t))) return SGE_OK;
                 set_shape(t);
                 sge_status st = run_instances(c, specs, out, mp, ms, true, t.policy);
+                if (st == SGE_OK && !ordered_now) {
+                    // the trials time the order later launches will use
+                    record_steps(out);
+                    apply_order(c->batch_steps[key]);
+                    ordered_now = true;
+                    st = run_instances(c, specs, out, mp, ms, true, t.policy);
+                }
                 if (t.lanes == 0) t.lanes = c->last_lanes;   // the width the automatic choice resolved to
                 if (st == SGE_OK && timed_before(t)) {
                     restore_shape();
@@ -166,16 +198,18 @@ sge_status sge_batch_run(sge_ctx *c, uint32_t njobs, const sge_job *jobs, sge_re
     c->donate = saved_donate;
     c->per_cu = saved_per_cu;
     if (st != SGE_OK) return st;
+    record_steps(out);
     bool aborted = false, timed_out = false;
     for (uint32_t i = 0; i < njobs; i++) {
-        results[i].matches = out[i].matches;
-        results[i].states = out[i].states;
-        results[i].candidates = out[i].candidates;
-        results[i].alg_bytes = out[i].bytes;
-        results[i].steals = out[i].steals;
-        results[i].steps = out[i].steps;
-        results[i].ms_prep = mp;
-        results[i].ms_search = ms;
+        sge_result &r = results[perm[i]];
+        r.matches = out[i].matches;
+        r.states = out[i].states;
+        r.candidates = out[i].candidates;
+        r.alg_bytes = out[i].bytes;
+        r.steals = out[i].steals;
+        r.steps = out[i].steps;
+        r.ms_prep = mp;
+        r.ms_search = ms;
         aborted |= out[i].status == SGE_E_ABORTED;
         timed_out |= out[i].timed_out;
     }

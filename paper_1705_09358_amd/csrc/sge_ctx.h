@@ -82,6 +82,8 @@ struct sge_ctx {
     int check_uniform = 0; // search launches verify that a unit's lanes agree on its state
     // batch autotuner's choice by job list (hash); cleared when tuning changes
     std::map<uint64_t, sge::BatchTune> batch_tune;
+    // by job list (the same hash): the steps each job took in its last launch
+    std::map<uint64_t, std::vector<uint64_t>> batch_steps;
     int num_cus = 0;
     size_t lds_per_cu = 0;
     std::map<uint32_t, std::unique_ptr<sge::Target>> targets;
