@@ -936,7 +936,12 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                     r = ld_node(d.node + v);
                 }
             }
-            if (ok && d.bits) ok = (d.bits[(size_t)lvl * W + (v >> 6)] >> (v & 63)) & 1ull;
+            // the domain word needs only v, like the back-edge rows: with
+            // adjacency rows it is awaited together with their first round
+            const bool late_dom = (!GEN || !flags) && d.adj;
+            unsigned long long dword = ~0ull;
+            if (d.bits) dword = d.bits[(size_t)lvl * W + (v >> 6)];   // v is 0 for an idle lane
+            if (ok && !late_dom) ok = (dword >> (v & 63)) & 1ull;
             if (ok) {
                 if (a.UW) {
                     ok = !used_test(L.used, v);
@@ -984,6 +989,10 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                     }
                 }
                 ok = ok && ((hit >> (v & 63)) & 1ull);
+                if (!((dword >> (v & 63)) & 1ull)) {   // outside the domain: no check beyond it counts
+                    ok = false;
+                    probes = 0;
+                }
             } else if (!GEN || !flags) {
                 unsigned long long bm = L.pback[lvl];
                 while (bm) {
