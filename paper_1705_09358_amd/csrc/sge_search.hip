@@ -157,8 +157,8 @@ __device__ __forceinline__ unsigned long long group_sum64(unsigned long long x) 
 // Per-unit LDS arrays of the CSR variant.
 struct UnitLds {
     unsigned long long *pback;    // the current instance's plan by position: back-edge masks,
-    int *pp;                      //   parent positions,
-    unsigned *plab, *pdeg;        //   labels and degrees (copied when the unit changes instance)
+    int *ppd;                     //   parent positions (high half, -1: none) and degrees (low half),
+    unsigned *plab;               //   labels (copied when the unit changes instance)
     unsigned *M, *MB, *MD;        // mapping by position, row start and degree of M[i]
     unsigned *cur, *end, *lb;     // frame: next candidate index, list length, list start
     unsigned *eb, *dn;            // frame: first stack entry, entries given away from the bottom
@@ -175,10 +175,9 @@ __device__ __forceinline__ UnitLds carve(unsigned *base) {
     constexpr unsigned kmax = KMAX, E = KMAX + G;
     UnitLds u;
     u.pback = reinterpret_cast<unsigned long long *>(base);   // the unit's area starts 8-byte aligned
-    u.pp = reinterpret_cast<int *>(base + 2 * kmax);
+    u.ppd = reinterpret_cast<int *>(base + 2 * kmax);
     u.plab = base + 3 * kmax;
-    u.pdeg = base + 4 * kmax;
-    u.M = base + 5 * kmax;
+    u.M = base + 4 * kmax;
     u.MB = u.M + kmax;
     u.MD = u.MB + kmax;
     u.cur = u.MD + kmax;
@@ -189,7 +188,7 @@ __device__ __forceinline__ UnitLds carve(unsigned *base) {
     u.ev = u.dn + kmax;
     u.ebg = u.ev + E;
     u.edg = u.ebg + E;
-    u.tim = reinterpret_cast<unsigned long long *>(u.edg + E);   // 8-byte aligned: 13 kmax + 3 E is even
+    u.tim = reinterpret_cast<unsigned long long *>(u.edg + E);   // 8-byte aligned: 12 kmax + 3 E is even
     u.used = u.edg + E + 6;
     return u;
 }
@@ -408,10 +407,12 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
         if (gl == 0) f = __hip_atomic_load(&a.ctr[i].pad0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return __shfl(f, gbase) != 0;
     };
+    // the parent position packed with the pattern degree (-1: none)
+    auto parent_at = [](int ppd) -> int { return ppd >> 16; };
     // open the frame of position `pos` (lists follow the mapped parent)
     // returns the frame's end and list start (also kept in LDS)
     auto open_frame = [&](unsigned pos, unsigned lo, unsigned hi) -> uint2 {
-        int p = L.pp[pos];
+        const int p = parent_at(L.ppd[pos]);
         unsigned start, len;
         if (p >= 0) {
             if (GEN && (P->flags & PLAN_DIRECTED) && !((P->pdir_out >> pos) & 1ull) && d.irp) {
@@ -718,9 +719,9 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                         if constexpr (!DENSE) {
                             for (unsigned i = gl; i < k; i += G) {
                                 L.pback[i] = P->back[i];
-                                L.pp[i] = P->parent[i];
+                                // pattern degrees count bits of 64-bit neighbour masks (at most 64)
+                                L.ppd[i] = (int)((unsigned)P->parent[i] << 16 | min(P->pdeg[i], 0xFFFFu));
                                 L.plab[i] = P->plabel[i];
-                                L.pdeg[i] = P->pdeg[i];
                             }
                             WAVE_SYNC();
                         }
@@ -902,7 +903,7 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                     // are counted per candidate below); without a parent, the
                     // whole candidate set: 5 bytes per target node (RI) or 4 + 8
                     // per domain member (RI-DS)
-                    c_bytes += L.pp[lvl] >= 0 ? 8ull
+                    c_bytes += parent_at(L.ppd[lvl]) >= 0 ? 8ull
                                : d.bits ? 12ull * P->list_len[lvl] : 5ull * P->n;
                 }
                 c0 = 0;
@@ -916,7 +917,7 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
             // evaluate up to G candidates of the current frame
             const unsigned idx = c0 + gl;
             bool ok = idx < e;
-            const bool has_parent = L.pp[lvl] >= 0;
+            const bool has_parent = parent_at(L.ppd[lvl]) >= 0;
             const unsigned flags = GEN ? P->flags : 0u;
             // the pattern arc to the parent leaves the parent (pout), else it
             // points at it and candidates come from the image's in-row
@@ -953,7 +954,7 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
             }
             const unsigned pl = L.plab[lvl];
             if (ok && pl != LABEL_ANY) ok = r.label == pl;
-            if (ok) ok = r.deg >= L.pdeg[lvl];
+            if (ok) ok = r.deg >= ((unsigned)L.ppd[lvl] & 0xFFFFu);
             if ((!GEN || !flags) && d.adj) {
                 // one adjacency-row word per back edge, four rows per round with
                 // their loads issued together (every lane's address is in range:
@@ -1011,13 +1012,13 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                 const bool dir = flags & PLAN_DIRECTED;
                 if (ok) ok = r.pad >= P->pindeg[lvl];
                 if (ok && has_parent && lm) {
-                    const unsigned pp = (unsigned)L.pp[lvl];
+                    const unsigned pp = (unsigned)parent_at(L.ppd[lvl]);
                     const unsigned tl = in_row ? (d.ielab ? d.ielab[lb + idx] : 0u) : (d.elab ? d.elab[lb + idx] : 0u);
                     gen_extra += 4;   // the label of the arc the candidate came over
                     ok = tl == (pout ? lm[pp * k + lvl] : lm[lvl * k + pp]);
                 }
                 if (ok && dir && has_parent && ((P->pboth >> lvl) & 1ull)) {
-                    const unsigned pp = (unsigned)L.pp[lvl];
+                    const unsigned pp = (unsigned)parent_at(L.ppd[lvl]);
                     gen_extra += 8;   // the reverse arc to the parent
                     ok = arc_to(d, r.begin, r.deg, L.M[pp], lm != nullptr, lm ? lm[lvl * k + pp] : 0u);
                 }
@@ -1327,7 +1328,7 @@ unsigned unit_words(const LaunchCfg &cfg) {
     if (cfg.dense) return std::max(18u, 3 * even(cfg.kmax) + 2 * cfg.kmax * cfg.wmax + 2 * cfg.wmax + 6);
     unsigned E = KMAX + cfg.lanes;
     unsigned UW = cfg.used_bitset ? (cfg.nmax + 31) / 32 : 0;
-    return std::max(18u, even(13 * KMAX + 3 * E + 6 + UW));
+    return std::max(18u, even(12 * KMAX + 3 * E + 6 + UW));
 }
 
 // Largest block (256, 128 or 64 threads) whose units fit in 64 KiB of LDS.
