@@ -6,6 +6,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <unordered_map>
 
 #include "sge_internal.h"
 
@@ -86,8 +87,9 @@ struct sge_ctx {
     std::map<uint64_t, std::vector<uint64_t>> batch_steps;
     int num_cus = 0;
     size_t lds_per_cu = 0;
-    std::map<uint32_t, std::unique_ptr<sge::Target>> targets;
-    std::map<uint32_t, std::unique_ptr<sge::Pattern>> patterns;
+    // resident graphs by handle (hashed: a 4096-job batch looks up 8192 handles per call)
+    std::unordered_map<uint32_t, std::unique_ptr<sge::Target>> targets;
+    std::unordered_map<uint32_t, std::unique_ptr<sge::Pattern>> patterns;
     uint32_t next_handle = 1;
     sge::LaunchBufs bufs;
     sge::DevBuf d_rows;
