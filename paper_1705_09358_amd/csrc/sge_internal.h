@@ -217,6 +217,7 @@ constexpr uint32_t QUEUE_GROUPS = 8;                          // work-queue grou
 constexpr uint32_t QUEUE_GROUP_SLOTS = QUEUE_SLOTS / QUEUE_GROUPS;
 constexpr uint32_t TASK_ENTRIES = 16;                        // accepted candidates one task can carry
 constexpr uint32_t DEFAULT_DONATE_PERIOD = 32;               // steps between a unit's donations
+constexpr uint32_t HANDOFF_PERIOD = 4;                        // steps before a unit hands a piece to an idle wave-mate
 
 // Counters of one work-queue group, each on its own 128-byte line.
 struct QGroup {

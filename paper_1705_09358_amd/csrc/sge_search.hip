@@ -542,11 +542,70 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
         iter++;
         const unsigned long long idle_b = __ballot(inst == NO_TASK);
         const bool wave_idle = idle_b == ~0ull;
+        // ------------------------------------------------ a piece for an idle wave-mate (CSR)
+        // A unit whose wave-mate is idle hands it half of its shallowest
+        // spare frame directly: the piece goes through LDS, not the queue,
+        // and counts as a task given away (its `created` count completes
+        // before the receiver can finish it).  The receiver starts it below.
+        int ho_r = -1;   // the unit of this wave that receives a piece this iteration
+        if constexpr (!DENSE && G < 64) {
+            if (a.donate && idle_b != 0 && !wave_idle && (iter & 3) == 0) {
+                unsigned hf = 0, hkind = 0;
+                if (inst != NO_TASK && since_donate >= HANDOFF_PERIOD) {
+                    for (hf = base; hf <= lvl; hf++) {
+                        if (L.cur[hf] < L.end[hf]) { hkind = 1; break; }
+                        const unsigned top = hf < lvl ? L.eb[hf + 1] : etop;
+                        if (top - (L.eb[hf] + L.dn[hf]) > (hf == lvl ? 1u : 0u)) { hkind = 2; break; }
+                    }
+                }
+                const unsigned long long givers = __ballot(hkind != 0);
+                if (givers) {
+                    const int r = (int)((unsigned)__builtin_ctzll(idle_b) / G);
+                    if ((lane / G) == (int)((unsigned)__builtin_ctzll(givers) / G)) {
+                        UnitLds R = carve<G>(lds + (size_t)((threadIdx.x / 64) * (64 / G) + r) * a.unit_words);
+                        unsigned tlo = 0, thi = FULL_RANGE, tkind = TK_RANGE, tne = 0;
+                        if (hkind == 1) {
+                            // the untried upper half of the frame's candidate range
+                            const unsigned c = L.cur[hf], e = L.end[hf];
+                            tlo = c + (e - c) / 2;
+                            thi = e;
+                            L.end[hf] = tlo;
+                        } else {
+                            // accepted candidates from the bottom of the frame, as for the queue
+                            const unsigned top = hf < lvl ? L.eb[hf + 1] : etop;
+                            const unsigned live = top - (L.eb[hf] + L.dn[hf]);
+                            tne = hf < lvl ? (live + 1) / 2 : live / 2;
+                            tne = min(min(tne, TASK_ENTRIES), a.E + hf + 3 - k);
+                            const unsigned b0 = L.eb[hf] + L.dn[hf];
+                            for (unsigned i = gl; i < tne; i += G) R.ev[i] = L.ev[b0 + i];
+                            L.dn[hf] = L.dn[hf] + tne;
+                            tkind = TK_ENTRIES;
+                        }
+                        for (unsigned i = gl; i < hf; i += G) R.M[i] = L.M[i];
+                        if (gl == 0) {
+                            // the piece's header, in the receiver's (idle) frame words
+                            R.eb[0] = inst;
+                            R.eb[1] = hf;
+                            R.eb[2] = tlo;
+                            R.eb[3] = thi;
+                            R.eb[4] = tkind;
+                            R.eb[5] = tne;
+                            fadd(&HG->created, 1);
+                        }
+                        since_donate = 0;
+                    }
+                    vm_drain();
+                    WAVE_SYNC();
+                    ho_r = r;
+                }
+            }
+        }
         // ------------------------------------------------ poll the scheduler (one lane per wave)
         const bool poll = idle_b != 0 && (wave_idle || (iter & 31) == 0);
-        if (poll || (iter & 63) == 0) {
+        const bool polled = poll || (iter & 63) == 0;
+        if (polled || ho_r >= 0) {
             unsigned flags = 0, src = NO_GROUP, cn = 0;
-            if (lane == 0) {
+            if (lane == 0 && polled) {
                 polls++;
                 if (now_ticks() > deadline) {
                     st_rlx(&S->abort, 1u);
@@ -589,14 +648,18 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
             cn = __shfl(cn, 0);
             if (flags & 1) break;                    // time limit: every wave stops
             if ((flags & 2) && wave_idle) break;     // the search is complete
-            donate_hint = a.donate && (flags & 4);
-            cn_seen = max(cn_seen, cn);
-            if (poll && (src != NO_GROUP || cn < nchunks)) {
+            if (polled) {
+                donate_hint = a.donate && (flags & 4);
+                cn_seen = max(cn_seen, cn);
+            }
+            if ((poll && (src != NO_GROUP || cn < nchunks)) || ho_r >= 0) {
                 // ---------------------------------------- task acquisition, one unit at a time
                 for (int g = 0; g < 64 / G; g++) {
                     if (!(inst == NO_TASK && (lane / G) == g)) continue;
                     unsigned kind = 0, val = 0;
-                    if (gl == 0) {
+                    if (g == ho_r) {
+                        kind = 3;   // a piece from a wave-mate, already in this unit's LDS
+                    } else if (gl == 0 && poll) {
                         if (src != NO_GROUP && cas_dec_if_pos(&S->grp[src].avail)) {
                             unsigned t = fadd(&S->grp[src].head, 1);
                             QTask *q = a.queue + src * QUEUE_GROUP_SLOTS + t % QUEUE_GROUP_SLOTS;
@@ -623,7 +686,14 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                     roots_done = __shfl((int)roots_done, gbase) != 0;
                     if (kind == 0) continue;
                     unsigned ti = 0, tL = 0, tlo = 0, thi = 0, tkind = TK_RANGE, tne = 0;
-                    if (kind == 1) {
+                    if (kind == 3) {
+                        ti = L.eb[0];
+                        tL = L.eb[1];
+                        tlo = L.eb[2];
+                        thi = L.eb[3];
+                        tkind = L.eb[4];
+                        tne = L.eb[5];
+                    } else if (kind == 1) {
                         QTask *q = a.queue + src * QUEUE_GROUP_SLOTS + val % QUEUE_GROUP_SLOTS;
                         ti = ld_rlx(&q->inst);
                         tL = ld_rlx(&q->L);
@@ -693,7 +763,7 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                             }
                             continue;
                         }
-                    } else {
+                    } else if (kind == 2) {
                         unsigned lo = 0, hi = a.ninst;   // largest i with prefix[i] <= val
                         if (gl == 0) {
                             while (hi - lo > 1) {
@@ -729,7 +799,7 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                     inst = ti;
                     if (gl == 0) L.tim[0] = now_ticks();
                     since_donate = 0;
-                    if (kind == 1) c_steals++;
+                    if (kind != 2) c_steals++;
                     etop = 0;
                     if (a.state_cap && inst_aborted(inst)) {   // capped instance: drop the task
                         if (gl == 0) fadd(&HG->finished, 1);
@@ -787,7 +857,7 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                         }
                         WAVE_SYNC();
                         base = lvl = tL;
-                        if (kind == 1 && tkind == TK_ENTRIES) {
+                        if (kind != 2 && tkind == TK_ENTRIES) {
                             // accepted candidates of position tL, counted by the giver
                             open_frame(tL, 0, 0);
                             for (unsigned i = gl; i < tne; i += G) {
@@ -942,19 +1012,21 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
             const bool late_dom = (!GEN || !flags) && d.adj;
             unsigned long long dword = ~0ull;
             if (d.bits) dword = d.bits[(size_t)lvl * W + (v >> 6)];   // v is 0 for an idle lane
-            if (ok && !late_dom) ok = (dword >> (v & 63)) & 1ull;
-            if (ok) {
-                if (a.UW) {
-                    ok = !used_test(L.used, v);
-                } else {
-                    // targets too large for a used bitset in LDS: v against the
-                    // mapped prefix (the same address in every lane: a broadcast)
-                    for (unsigned j = 0; j < lvl; j++) ok = ok && L.M[j] != v;
-                }
-            }
+            // the label, degree and used tests read registers and LDS only (v
+            // is 0 for an idle lane), so they are combined without branches
             const unsigned pl = L.plab[lvl];
-            if (ok && pl != LABEL_ANY) ok = r.label == pl;
-            if (ok) ok = r.deg >= ((unsigned)L.ppd[lvl] & 0xFFFFu);
+            unsigned okb = ok ? 1u : 0u;
+            if (!late_dom) okb &= (unsigned)(dword >> (v & 63)) & 1u;
+            okb &= (unsigned)(pl == LABEL_ANY) | (unsigned)(r.label == pl);
+            okb &= (unsigned)(r.deg >= ((unsigned)L.ppd[lvl] & 0xFFFFu));
+            if (a.UW) {
+                okb &= used_test(L.used, v) ? 0u : 1u;
+            } else {
+                // targets too large for a used bitset in LDS: v against the
+                // mapped prefix (the same address in every lane: a broadcast)
+                for (unsigned j = 0; j < lvl; j++) okb &= (unsigned)(L.M[j] != v);
+            }
+            ok = okb != 0;
             if ((!GEN || !flags) && d.adj) {
                 // one adjacency-row word per back edge, four rows per round with
                 // their loads issued together (every lane's address is in range:
