@@ -62,8 +62,7 @@ sge_status sge_batch_run(sge_ctx *c, uint32_t njobs, const sge_job *jobs, sge_re
     std::vector<uint32_t> perm(njobs);
     for (uint32_t i = 0; i < njobs; i++) perm[i] = i;
     auto apply_order = [&](const std::vector<uint64_t> &steps) {
-        for (uint32_t i = 0; i < njobs; i++) perm[i] = i;
-        std::stable_sort(perm.begin(), perm.end(), [&](uint32_t a, uint32_t b) { return steps[a] > steps[b]; });
+        order_by_desc(steps.data(), njobs, perm.data());
         for (uint32_t i = 0; i < njobs; i++) specs[i] = job_specs[perm[i]];
     };
     auto record_steps = [&](const std::vector<InstanceOut> &o) {

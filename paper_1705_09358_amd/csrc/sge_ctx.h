@@ -177,6 +177,8 @@ constexpr size_t PLAN_DEVICE_MIN_INSTANCES = 64;
 bool plan_on_device(const sge_ctx *c, const std::vector<const InstanceSpec *> &specs);
 // A search with a directed graph, or edge labels that are compared.
 bool general_instance(const InstanceSpec &s);
+// Indices 0..n-1 by decreasing key, ties in increasing index (a stable order).
+void order_by_desc(const uint64_t *key, uint32_t n, uint32_t *perm);
 // Upload, plan, reset, search and read back on `s` (asynchronous).  With
 // events, e0 and e1 are recorded right before and after the search kernel
 // (not while the stream is being captured: a batch graph gets event nodes
