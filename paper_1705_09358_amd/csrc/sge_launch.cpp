@@ -617,7 +617,7 @@ sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std
                 if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
                     return hip_fail(c, e, "hipStreamBeginCapture");
                 PlanSplit split;
-                split.big = 2u * (uint32_t)c->num_cus;
+                split.big = 4u * (uint32_t)c->num_cus;
                 split.s2 = c->plan_s2;
                 split.fork = c->plan_fork;
                 split.join = c->plan_join;

@@ -554,10 +554,12 @@ hipError_t launch_plan(const PlanIn *reqs, uint32_t m, uint32_t wmax, uint32_t k
     // large batch in 512-thread workgroups, which with 1024-thread
     // workgroups would hold 16 waves each mostly waiting at barriers.  With
     // a second stream the two launches run side by side.  On the 4096-pair
-    // batch: one 1024-thread launch 1.89 ms; the 512 largest in 1024-thread
-    // and the rest in 512-thread workgroups side by side 1.12 and 0.88 ms
-    // (the rest in 256-thread workgroups: 2.36 ms; one after the other:
-    // 2.38 ms).
+    // batch, the time from the graph's launch to its end less the search
+    // kernel's (the plans, their upload, finalize, reset and read-back):
+    // the 128, 256, 512 and 1024 largest in 1024-thread workgroups and the
+    // rest beside them 2.39, 2.35, 2.01 and 1.78-1.84 ms; all 4096 in one
+    // 1024-thread launch 1.87-1.88 ms.  The caller sizes the split (four
+    // workgroups per CU).
     const uint32_t big = split ? std::min(split->big, m) : m;
     const bool beside = split && split->s2 && split->fork && split->join && big < m && big > 0;
     hipError_t e;
