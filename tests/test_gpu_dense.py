@@ -167,3 +167,30 @@ def test_c3_full_size_properties(ctx_auto, j):
     finally:
         ctx_auto.unload_pattern(ph)
         ctx_auto.unload_target(th)
+
+
+@pytest.mark.parametrize("i", range(4))
+def test_c3_full_size_against_oracle(ctx_auto, i):
+    """The four dense patterns the benchmark times, searched whole (2.7e9
+    states together): matches, states, the digest of the sorted rows and the
+    dense algorithmic bytes equal the oracle's full-size values (stored, each
+    the sum of the oracle's root shards)."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c3full.json")) as f:
+        w = json.load(f)["instances"][i]
+    T = synth.c3_target()
+    inst = synth.c3_instance(w["j"], w["attempt"])
+    th = ctx_auto.load_target(T)
+    ph = ctx_auto.load_pattern(inst.pattern)
+    ctx_auto.set_mode(w["mode"])
+    ctx_auto.set_labelled(w["labelled"])
+    try:
+        _note(f"c3 full/{w['j']} against the oracle")
+        res, rows = ctx_auto.enumerate(th, ph, inst.pattern.n, cap_rows=max(1, w["matches"]))
+        assert (res.matches, res.states) == (w["matches"], w["states"])
+        assert oracle.rows_digest(rows, inst.pattern.n) == w["sha256"]
+        cnt = ctx_auto.count(th, ph)
+        assert (cnt.matches, cnt.states) == (w["matches"], w["states"])
+        assert cnt.alg_bytes == w["dense_bytes"]
+    finally:
+        ctx_auto.unload_pattern(ph)
+        ctx_auto.unload_target(th)
