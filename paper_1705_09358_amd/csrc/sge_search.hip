@@ -201,6 +201,7 @@ struct DenseLds {
     unsigned long long *cand;     // frame: candidate set, kmax rows of W words
     unsigned long long *used;     // bitset of mapped target nodes (W words)
     unsigned long long *tim;      // this unit's task start, time holding tasks, last task finish
+    unsigned *hdr;                // the header of a piece handed over by a wave-mate
 };
 
 __host__ __device__ inline unsigned even(unsigned x) { return x + (x & 1u); }
@@ -213,6 +214,7 @@ __device__ __forceinline__ DenseLds carve_dense(unsigned *base, unsigned kmax, u
     u.cand = reinterpret_cast<unsigned long long *>(u.hw + even(kmax));
     u.used = u.cand + (size_t)kmax * W;
     u.tim = u.used + W;
+    u.hdr = reinterpret_cast<unsigned *>(u.tim + 3);
     return u;
 }
 
@@ -466,6 +468,63 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
         // disagree with its bits, stay on a valid node index
         return v == 0xFFFFFFFFu ? 0u : v;
     };
+    // dense: what a unit gives away from frame f, for the queue or a wave-mate:
+    // half of the frame's remaining words above its lowest nonzero word
+    // (within the words it still owns; TK_WINDOW over [tlo, thi) of position
+    // f), else its lowest candidate (`extra`, mapped at position f: the
+    // receiver expands position f + 1)
+    auto dense_split = [&](unsigned f, unsigned &tL, unsigned &tlo, unsigned &thi, unsigned &tkind,
+                           unsigned &extra) {
+        const unsigned hw = D.hw[f];
+        unsigned w0 = hw, nz_hi = 0;
+        for (unsigned r = 0; r * G < hw; r++) {
+            const unsigned w = r * G + gl;
+            const bool nz = w < hw && D.cand[(size_t)f * WS + w] != 0ull;
+            const unsigned long long b = group_mask<G>(__ballot(nz), gbase);
+            if (b && w0 == hw) w0 = r * G + (unsigned)__builtin_ctzll(b);
+        }
+        for (unsigned r = 0; r * G < hw; r++) {
+            const unsigned w = r * G + gl;
+            if (w < hw && w > w0 && D.cand[(size_t)f * WS + w] != 0ull) nz_hi++;
+        }
+        nz_hi = group_sum<G>(nz_hi);
+        tL = f;
+        tlo = 0;
+        thi = FULL_RANGE;
+        tkind = TK_RANGE;
+        extra = 0;
+        if (nz_hi) {
+            unsigned wmid = w0 + 1 + (hw - w0 - 1) / 2;
+            unsigned moved = 0;
+            for (unsigned r = 0; r * G < hw; r++) {
+                const unsigned w = r * G + gl;
+                if (w < hw && w >= wmid) moved += (unsigned)__popcll(D.cand[(size_t)f * WS + w]);
+            }
+            moved = group_sum<G>(moved);
+            if (!moved) {
+                wmid = w0 + 1;
+                for (unsigned r = 0; r * G < hw; r++) {
+                    const unsigned w = r * G + gl;
+                    if (w < hw && w >= wmid) moved += (unsigned)__popcll(D.cand[(size_t)f * WS + w]);
+                }
+                moved = group_sum<G>(moved);
+            }
+            WAVE_SYNC();
+            for (unsigned r = 0; r * G < hw; r++) {
+                const unsigned w = r * G + gl;
+                if (w < hw && w >= wmid) D.cand[(size_t)f * WS + w] = 0ull;
+            }
+            D.fc[f] = D.fc[f] - moved;
+            D.hw[f] = wmid;
+            tkind = TK_WINDOW;
+            tlo = wmid;
+            thi = hw;
+        } else {
+            extra = pick_lowest(f);
+            D.fc[f] = D.fc[f] - 1;
+            tL = f + 1;
+        }
+    };
     // dense: candidates of position `pos` given M[0..pos-1]; at the last position
     // they are counted (and emitted) as matches, otherwise they become frame pos.
     // `count` = false for a set that was counted by the unit that gave it away.
@@ -548,6 +607,43 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
         // and counts as a task given away (its `created` count completes
         // before the receiver can finish it).  The receiver starts it below.
         int ho_r = -1;   // the unit of this wave that receives a piece this iteration
+        if constexpr (DENSE && G < 64) {
+            // dense: the same split as for the queue; the header goes to the
+            // receiver's header words, the prefix (and a single candidate) to its M
+            if (a.donate && idle_b != 0 && !wave_idle && (iter & 3) == 0) {
+                unsigned hf = 0;
+                bool spare = false;
+                if (inst != NO_TASK && since_donate >= HANDOFF_PERIOD) {
+                    for (hf = base; hf <= lvl; hf++)
+                        if (D.fc[hf] > (hf == lvl ? 1u : 0u)) { spare = true; break; }
+                }
+                const unsigned long long givers = __ballot(spare);
+                if (givers) {
+                    const int r = (int)((unsigned)__builtin_ctzll(idle_b) / G);
+                    if ((lane / G) == (int)((unsigned)__builtin_ctzll(givers) / G)) {
+                        DenseLds R = carve_dense(lds + (size_t)((threadIdx.x / 64) * (64 / G) + r) * a.unit_words,
+                                                 a.kmax, a.W);
+                        unsigned tL, tlo, thi, tkind, extra;
+                        dense_split(hf, tL, tlo, thi, tkind, extra);
+                        for (unsigned i = gl; i < hf; i += G) R.M[i] = D.M[i];
+                        if (gl == 0) {
+                            if (tkind == TK_RANGE) R.M[hf] = extra;
+                            R.hdr[0] = inst;
+                            R.hdr[1] = tL;
+                            R.hdr[2] = tlo;
+                            R.hdr[3] = thi;
+                            R.hdr[4] = tkind;
+                            R.hdr[5] = 0;
+                            fadd(&HG->created, 1);
+                        }
+                        since_donate = 0;
+                    }
+                    vm_drain();
+                    WAVE_SYNC();
+                    ho_r = r;
+                }
+            }
+        }
         if constexpr (!DENSE && G < 64) {
             if (a.donate && idle_b != 0 && !wave_idle && (iter & 3) == 0) {
                 unsigned hf = 0, hkind = 0;
@@ -687,12 +783,15 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                     if (kind == 0) continue;
                     unsigned ti = 0, tL = 0, tlo = 0, thi = 0, tkind = TK_RANGE, tne = 0;
                     if (kind == 3) {
-                        ti = L.eb[0];
-                        tL = L.eb[1];
-                        tlo = L.eb[2];
-                        thi = L.eb[3];
-                        tkind = L.eb[4];
-                        tne = L.eb[5];
+                        const unsigned *hd;
+                        if constexpr (DENSE) hd = D.hdr;
+                        else hd = L.eb;
+                        ti = hd[0];
+                        tL = hd[1];
+                        tlo = hd[2];
+                        thi = hd[3];
+                        tkind = hd[4];
+                        tne = hd[5];
                     } else if (kind == 1) {
                         QTask *q = a.queue + src * QUEUE_GROUP_SLOTS + val % QUEUE_GROUP_SLOTS;
                         ti = ld_rlx(&q->inst);
@@ -1206,52 +1305,7 @@ __global__ void __launch_bounds__(256, DENSE ? 4 : 1) search_kernel(SearchArgs a
                 QTask *q = a.queue + home * QUEUE_GROUP_SLOTS + t % QUEUE_GROUP_SLOTS;
                 unsigned tL = f, tlo = 0, thi = FULL_RANGE, tkind = TK_RANGE, tne = 0, extra = 0;
                 if constexpr (DENSE) {
-                    // half of the frame's remaining words above its lowest nonzero
-                    // word (within the words it still owns), else its lowest candidate
-                    const unsigned hw = D.hw[f];
-                    unsigned w0 = hw, nz_hi = 0;
-                    for (unsigned r = 0; r * G < hw; r++) {
-                        const unsigned w = r * G + gl;
-                        const bool nz = w < hw && D.cand[(size_t)f * WS + w] != 0ull;
-                        const unsigned long long b = group_mask<G>(__ballot(nz), gbase);
-                        if (b && w0 == hw) w0 = r * G + (unsigned)__builtin_ctzll(b);
-                    }
-                    for (unsigned r = 0; r * G < hw; r++) {
-                        const unsigned w = r * G + gl;
-                        if (w < hw && w > w0 && D.cand[(size_t)f * WS + w] != 0ull) nz_hi++;
-                    }
-                    nz_hi = group_sum<G>(nz_hi);
-                    if (nz_hi) {
-                        unsigned wmid = w0 + 1 + (hw - w0 - 1) / 2;
-                        unsigned moved = 0;
-                        for (unsigned r = 0; r * G < hw; r++) {
-                            const unsigned w = r * G + gl;
-                            if (w < hw && w >= wmid) moved += (unsigned)__popcll(D.cand[(size_t)f * WS + w]);
-                        }
-                        moved = group_sum<G>(moved);
-                        if (!moved) {
-                            wmid = w0 + 1;
-                            for (unsigned r = 0; r * G < hw; r++) {
-                                const unsigned w = r * G + gl;
-                                if (w < hw && w >= wmid) moved += (unsigned)__popcll(D.cand[(size_t)f * WS + w]);
-                            }
-                            moved = group_sum<G>(moved);
-                        }
-                        WAVE_SYNC();
-                        for (unsigned r = 0; r * G < hw; r++) {
-                            const unsigned w = r * G + gl;
-                            if (w < hw && w >= wmid) D.cand[(size_t)f * WS + w] = 0ull;
-                        }
-                        D.fc[f] = D.fc[f] - moved;
-                        D.hw[f] = wmid;
-                        tkind = TK_WINDOW;
-                        tlo = wmid;
-                        thi = hw;
-                    } else {
-                        extra = pick_lowest(f);
-                        D.fc[f] = D.fc[f] - 1;
-                        tL = f + 1;
-                    }
+                    dense_split(f, tL, tlo, thi, tkind, extra);
                 } else if (kind == 1) {
                     // the untried upper half of the frame's candidate range
                     unsigned c = L.cur[f], e = L.end[f];
@@ -1397,7 +1451,7 @@ hipError_t launch_g(SearchArgs args, int blocks, int per_cu_cap, int threads, si
 unsigned unit_words(const LaunchCfg &cfg) {
     // even: every unit's area starts 8-byte aligned; at least 18 words: the
     // area takes the unit's exit record (nine 64-bit values)
-    if (cfg.dense) return std::max(18u, 3 * even(cfg.kmax) + 2 * cfg.kmax * cfg.wmax + 2 * cfg.wmax + 6);
+    if (cfg.dense) return std::max(18u, 3 * even(cfg.kmax) + 2 * cfg.kmax * cfg.wmax + 2 * cfg.wmax + 6 + 6);
     unsigned E = KMAX + cfg.lanes;
     unsigned UW = cfg.used_bitset ? (cfg.nmax + 31) / 32 : 0;
     return std::max(18u, even(12 * KMAX + 3 * E + 6 + UW));
