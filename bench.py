@@ -111,7 +111,8 @@ def run_batch_workload(ctx, torch, insts, man, steps, warmup, label):
     return dict(ms_per_step=1000 * el / steps, states_per_s=tot_states / el, matches_per_s=tot_matches / el,
                 kernel_ms=kernel_ms, kernel_ms_device_clock=sum(dev_ms) / len(dev_ms),
                 prep_ms=float(res.ms_prep[0]), jobs=jobs, tgt=tgt, model=model, alg_bytes=alg_bytes,
-                roofline=roofline(alg_bytes, kernel_ms), instances=len(jobs),
+                roofline=dict(roofline(alg_bytes, kernel_ms), alg_bytes_per_state=alg_bytes / int(want_states.sum())),
+                instances=len(jobs),
                 states_per_step=int(want_states.sum()), matches_per_step=int(want_matches.sum()))
 
 
@@ -245,11 +246,14 @@ def run_dense(ctx, torch, steps):
                       "frac": valu_ops / (kernel_ms / 1000.0) / 1e9 / VALU_PEAK_GOPS})
 
 
-def run_serve(torch, seconds, rate, plan_where=-1):
+def run_serve(torch, seconds, rate, plan_where=-1, plain=False):
     """Serving workload: resident contact targets (5k-20k nodes), queries of
     4-64 nodes arriving as a Poisson process; latency = result visible on the
     host - scheduled arrival.  Every result is checked against the oracle's
-    stored value for its query (status, matches, states, bytes)."""
+    stored value for its query (status, matches, states, bytes).  With
+    `plain`, the same queries are then searched one at a time (sge_count, all
+    CUs on each, host plans), every result checked again: the plain path on
+    the same instance set, with its per-query time."""
     from paper_1705_09358_amd import sge, synth
     man = load_manifest("c5")
     log("serve: generating 50 resident targets")
@@ -298,15 +302,39 @@ def run_serve(torch, seconds, rate, plan_where=-1):
         time.sleep(0.0002)
     el = time.perf_counter() - t0
     ctx.serve_stop()
-    for q, (r, w) in enumerate(zip(res, man["instances"])):
+
+    def check(q, r, w, what):
         if w["j"] != q:
             raise SystemExit("serve: the stored oracle values are not in arrival order")
         if w["status"] == "ok":
             if r.status != sge.OK or (r.matches, r.states, r.alg_bytes) != (w["matches"], w["states"],
                                                                            w["alg_bytes"]):
-                raise SystemExit(f"serve: query {q} differs from the oracle's stored value")
+                raise SystemExit(f"{what}: query {q} differs from the oracle's stored value")
         elif r.status != sge.E_ABORTED:
-            raise SystemExit(f"serve: query {q} should have been stopped at the state cap")
+            raise SystemExit(f"{what}: query {q} should have been stopped at the state cap")
+
+    for q, (r, w) in enumerate(zip(res, man["instances"])):
+        check(q, r, w, "serve")
+    plain_leg = None
+    if plain:
+        log(f"serve: the same {len(arrivals)} queries one at a time (plain path)")
+        ctx.set_mode(sge.RIDS_SI_FC)
+        ctx.set_labelled(True)
+        per = np.zeros(len(arrivals))
+        pst = 0
+        tp = time.perf_counter()
+        for q in range(len(arrivals)):
+            a0 = time.perf_counter()
+            r = ctx.count(th[queries[q][0]], ph[q], allow=(sge.OK, sge.E_ABORTED))
+            per[q] = time.perf_counter() - a0
+            check(q, r, man["instances"][q], "serve, plain path")
+            if r.status == sge.OK:
+                pst += r.states
+        pel = time.perf_counter() - tp
+        pms = per * 1000
+        plain_leg = dict(queries=len(arrivals), checked=len(arrivals), seconds=pel, states_per_s=pst / pel,
+                         p50_ms=float(np.percentile(pms, 50)), p99_ms=float(np.percentile(pms, 99)),
+                         note="per-query time of sge_count back to back (no arrivals, no queueing)")
     ctx.close()
     ok = [r for r in res if r.status == sge.OK]
     states = sum(r.states for r in ok)
@@ -318,7 +346,8 @@ def run_serve(torch, seconds, rate, plan_where=-1):
                 mean_prep_ms=float(np.mean([r.ms_prep for r in res])),
                 states_per_s=states / el, matches_per_s=sum(r.matches for r in ok) / el,
                 alg_bytes_per_s=sum(r.alg_bytes for r in ok) / el,
-                aborted=sum(r.status == sge.E_ABORTED for r in res), busy_retries=busy, max_in_flight=max_conc)
+                aborted=sum(r.status == sge.E_ABORTED for r in res), busy_retries=busy, max_in_flight=max_conc,
+                plain=plain_leg)
 
 
 def kernel_source_hash():
@@ -568,7 +597,7 @@ def main():
                     log("c2: variant study (four modes)")
                     variants = run_variants(ctx2, torch, e["jobs"], max(3, a.steps // 4))
             ctx2.close()
-    serve = run_serve(torch, a.serve_seconds, 200.0, -1) if a.serve_seconds > 0 else None
+    serve = run_serve(torch, a.serve_seconds, 200.0, -1, plain=not a.no_plain) if a.serve_seconds > 0 else None
     serve_dev = run_serve(torch, a.serve_device_seconds, 200.0, 1) if a.serve_device_seconds > 0 else None
     rl = dict(b["roofline"])
     rl["traffic"] = measured_traffic("c4")
