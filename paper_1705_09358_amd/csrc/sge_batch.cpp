@@ -162,7 +162,7 @@ sge_status sge_batch_run(sge_ctx *c, uint32_t njobs, const sge_job *jobs, sge_re
             // longer one, which gives fewer and larger tasks away), so they
             // are tried together
             const std::vector<int> widths = saved_lanes ? std::vector<int>{saved_lanes} : std::vector<int>{32, 64};
-            const std::vector<int> periods = saved_donate == 1 ? std::vector<int>{1, 16, 64} : std::vector<int>{saved_donate};
+            const std::vector<int> periods = saved_donate == 1 ? std::vector<int>{1, 16, 64, 128} : std::vector<int>{saved_donate};
             for (int l : widths)
                 for (int dn : periods)
                     if (st == SGE_OK) st = trial(BatchTune{after_blocks.policy, l, dn, after_blocks.per_cu});
