@@ -221,9 +221,6 @@ sge_status sge_create(int device, void *hip_stream, sge_ctx **out) {
     if (c->num_cus <= 0) c->num_cus = 1;
     (void)hipEventCreate(&c->ev0);
     (void)hipEventCreate(&c->ev1);
-    if (hipStreamCreateWithFlags(&c->plan_s2, hipStreamNonBlocking) != hipSuccess) c->plan_s2 = nullptr;
-    (void)hipEventCreateWithFlags(&c->plan_fork, hipEventDisableTiming);
-    (void)hipEventCreateWithFlags(&c->plan_join, hipEventDisableTiming);
     // the allocation-free count's scratch array: its address on this device
     // (a failure leaves that entry point reporting the error)
     (void)noalloc_init(device);
@@ -248,9 +245,6 @@ void sge_destroy(sge_ctx *c) {
     c->d_rows.release();
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
-    if (c->plan_fork) (void)hipEventDestroy(c->plan_fork);
-    if (c->plan_join) (void)hipEventDestroy(c->plan_join);
-    if (c->plan_s2) (void)hipStreamDestroy(c->plan_s2);
     delete c;
 }
 

@@ -98,11 +98,7 @@ struct sge_ctx {
     uint32_t last_units = 0;         // last launch: units that entered the search loop
     int last_lanes = 0;              // last launch: lanes per search unit
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // around the search kernel of count, enumerate and batch launches
-    // a second stream and fork/join events: the small plans of a batch run
-    // beside the large ones (default priority, like the context's stream)
-    hipStream_t plan_s2 = nullptr;
-    hipEvent_t plan_fork = nullptr, plan_join = nullptr;
-    bool graph_extras = true;          // captures take the event nodes and the second plan stream
+    bool graph_extras = true;          // captures take the event nodes around the search kernel
     std::string graph_extras_error;    // why a capture refused them (then graph_extras is false)
     const char *enqueue_step = "";     // the step enqueue_pack was at (for error messages)
     double last_event_ms = 0;                  // last launch: the search kernel between ev0 and ev1
@@ -182,13 +178,11 @@ void order_by_desc(const uint64_t *key, uint32_t n, uint32_t *perm);
 // Upload, plan, reset, search and read back on `s` (asynchronous).  With
 // events, e0 and e1 are recorded right before and after the search kernel
 // (not while the stream is being captured: a batch graph gets event nodes
-// added after its capture).  With a split, the small plans of a large batch
-// run on a second stream beside the large ones.
+// added after its capture).
 hipError_t enqueue_pack(sge_ctx *c, const Pack &pk, LaunchBufs &bufs, hipStream_t s, hipEvent_t e0 = nullptr,
-                        hipEvent_t e1 = nullptr, const PlanSplit *split = nullptr);
+                        hipEvent_t e1 = nullptr);
 // Upload and plan only (the plan of instance 0 is then read back by the caller).
-hipError_t enqueue_plan_only(const Pack &pk, LaunchBufs &bufs, uint32_t root_chunk, hipStream_t s,
-                             const PlanSplit *split = nullptr);
+hipError_t enqueue_plan_only(const Pack &pk, LaunchBufs &bufs, uint32_t root_chunk, hipStream_t s);
 // After the stream has drained: per-instance results and the kernel time.
 void read_pack(const sge_ctx *c, Pack &pk, const LaunchBufs &bufs, const std::vector<const InstanceSpec *> &specs,
                std::vector<InstanceOut *> &out, double &ms_search);

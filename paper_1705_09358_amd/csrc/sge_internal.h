@@ -292,23 +292,12 @@ struct DevWork {
     size_t ctr_cap = 0;
 };
 
-// How a plan launch splits its requests (sorted by decreasing estimated
-// work): the first `big` get 1024-thread workgroups, the rest 512-thread
-// ones, launched on stream s2 beside the large ones (fork and join events
-// order them with the launch's stream; without s2 they follow on it).
-struct PlanSplit {
-    uint32_t big = 0;
-    hipStream_t s2 = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
-    const char **step = nullptr;   // when set: the step the launch was at (for error messages)
-};
-// Plan `m` instances (one workgroup each), then set every instance's root
-// chunks and the chunk prefix: `policy` 1 = one chunk per instance, else
-// `root_chunk` candidates per chunk, or (0) the total roots over 4 * `units`.
-// Without a split every request gets a 1024-thread workgroup.
+// Plan `m` instances (one workgroup each, requests in decreasing order of
+// estimated work), then set every instance's root chunks and the chunk
+// prefix: `policy` 1 = one chunk per instance, else `root_chunk` candidates
+// per chunk, or (0) the total roots over 4 * `units`.
 hipError_t launch_plan(const PlanIn *reqs, uint32_t m, uint32_t wmax, uint32_t kmax, InstDesc *desc, unsigned *chunk_prefix,
-                       int policy, uint32_t root_chunk, uint64_t units, hipStream_t s,
-                       const PlanSplit *split = nullptr);
+                       int policy, uint32_t root_chunk, uint64_t units, hipStream_t s);
 // LDS words of the plan kernel's support buffer (larger W uses PlanIn::support).
 constexpr uint32_t PLAN_LDS_WORDS = 2048;
 

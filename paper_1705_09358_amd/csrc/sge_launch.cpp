@@ -378,20 +378,18 @@ sge_status pack_host_planned(sge_ctx *c, const std::vector<const InstanceSpec *>
     return SGE_OK;
 }
 
-hipError_t enqueue_plan_only(const Pack &pk, LaunchBufs &bufs, uint32_t root_chunk, hipStream_t s,
-                             const PlanSplit *split) {
+hipError_t enqueue_plan_only(const Pack &pk, LaunchBufs &bufs, uint32_t root_chunk, hipStream_t s) {
     hipError_t r;
     if ((r = hipMemcpyAsync(bufs.d_blob.p, bufs.h_blob.p, pk.upload, hipMemcpyHostToDevice, s)) != hipSuccess)
         return r;
     return launch_plan((const PlanIn *)((char *)bufs.d_blob.p + pk.off_req), pk.m, pk.cfg.wmax, pk.cfg.kmax,
-                       bufs.work.inst, bufs.work.chunk_prefix, pk.policy, root_chunk, pk.units, s, split);
+                       bufs.work.inst, bufs.work.chunk_prefix, pk.policy, root_chunk, pk.units, s);
 }
 
-hipError_t enqueue_pack(sge_ctx *c, const Pack &pk, LaunchBufs &bufs, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
-                        const PlanSplit *split) {
+hipError_t enqueue_pack(sge_ctx *c, const Pack &pk, LaunchBufs &bufs, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     hipError_t r;
     c->enqueue_step = pk.device_plan ? "upload and plan kernels" : "upload";
-    if (pk.device_plan) r = enqueue_plan_only(pk, bufs, c->root_chunk, s, split);
+    if (pk.device_plan) r = enqueue_plan_only(pk, bufs, c->root_chunk, s);
     else r = hipMemcpyAsync(bufs.d_blob.p, bufs.h_blob.p, pk.upload, hipMemcpyHostToDevice, s);
     if (r != hipSuccess) return r;
     c->enqueue_step = "reset kernel";
@@ -598,9 +596,8 @@ sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std
             }
             hipGraph_t g = nullptr;
             hipGraphExec_t ge = nullptr;
-            // with the small plans on a second stream beside the largest (two
-            // per CU) and event-record nodes right before and after the search
-            // kernel's node; should the runtime refuse either, the graph is
+            // with event-record nodes right before and after the search
+            // kernel's node; should the runtime refuse them, the graph is
             // captured again without them (the events then time nothing) and
             // later captures leave them out
             if (c->gev0) (void)hipEventDestroy(c->gev0);
@@ -616,13 +613,7 @@ sge_status run_instances(sge_ctx *c, const std::vector<InstanceSpec> &specs, std
                 (void)hipGetLastError();
                 if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
                     return hip_fail(c, e, "hipStreamBeginCapture");
-                PlanSplit split;
-                split.big = 4u * (uint32_t)c->num_cus;
-                split.s2 = c->plan_s2;
-                split.fork = c->plan_fork;
-                split.join = c->plan_join;
-                split.step = &c->enqueue_step;
-                er = enqueue_pack(c, pk, c->bufs, s, nullptr, nullptr, attempt == 0 ? &split : nullptr);
+                er = enqueue_pack(c, pk, c->bufs, s, nullptr, nullptr);
                 e = hipStreamEndCapture(s, &g);
                 if (er == hipSuccess && e == hipSuccess && attempt == 0) {
                     c->enqueue_step = "event nodes around the search kernel";

@@ -38,8 +38,10 @@ namespace {
 // plan alone took 2.9 ms; with 1024 threads the largest plan takes about
 // 1 ms and the batch about 2 ms, bound by the one workgroup per CU that
 // resides at a time.
-constexpr int PLAN_THREADS = 1024;
-constexpr int SMALL_PLAN_THREADS = 512;   // the small plans of a large batch
+// Twelve waves per workgroup: two of them reside per CU (twenty-four waves,
+// what this kernel's launches reach: 1024-thread workgroups reside one per
+// CU, 512-thread ones three).
+constexpr int PLAN_THREADS = 768;
 
 // Device memory in the global address space: the pointers a plan request
 // holds are loaded from memory, so the compiler would treat them as generic
@@ -543,54 +545,22 @@ __global__ void __launch_bounds__(FIN_THREADS)
 }  // namespace
 
 hipError_t launch_plan(const PlanIn *reqs, uint32_t m, uint32_t wmax, uint32_t kmax, InstDesc *desc, unsigned *chunk_prefix,
-                       int policy, uint32_t root_chunk, uint64_t units, hipStream_t s, const PlanSplit *split) {
+                       int policy, uint32_t root_chunk, uint64_t units, hipStream_t s) {
     if (m == 0) return hipSuccess;
     // support rows of one batch: up to PLAN_LDS_WORDS words (the widest
     // instance's rows times the largest pattern, when that is smaller)
     const uint32_t words =
         (uint32_t)std::min<uint64_t>((uint64_t)std::max<uint32_t>(wmax, 1) * std::max<uint32_t>(kmax, 1), PLAN_LDS_WORDS);
-    // The largest plans in 1024-thread workgroups (one resides per CU, its
-    // latency-bound phases spread over 16 waves); the many small plans of a
-    // large batch in 512-thread workgroups, which with 1024-thread
-    // workgroups would hold 16 waves each mostly waiting at barriers.  With
-    // a second stream the two launches run side by side.  On the 4096-pair
-    // batch, the time from the graph's launch to its end less the search
-    // kernel's (the plans, their upload, finalize, reset and read-back):
-    // the 128, 256, 512 and 1024 largest in 1024-thread workgroups and the
-    // rest beside them 2.39, 2.35, 2.01 and 1.78-1.84 ms; all 4096 in one
-    // 1024-thread launch 1.87-1.88 ms.  The caller sizes the split (four
-    // workgroups per CU).
-    const uint32_t big = split ? std::min(split->big, m) : m;
-    const bool beside = split && split->s2 && split->fork && split->join && big < m && big > 0;
-    hipError_t e;
-    const char *dummy = nullptr;
-    const char *&step = split && split->step ? *split->step : dummy;
-    if (beside) {
-        step = "plan fork";
-        if ((e = hipEventRecord(split->fork, s)) != hipSuccess) return e;
-        step = "second plan stream waits";
-        if ((e = hipStreamWaitEvent(split->s2, split->fork, 0)) != hipSuccess) return e;
-        step = "small plans";
-        hipLaunchKernelGGL(plan_kernel<SMALL_PLAN_THREADS>, dim3(m - big), dim3(SMALL_PLAN_THREADS),
-                           (size_t)words * 8, split->s2, reqs + big, words);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        step = "plan join";
-        if ((e = hipEventRecord(split->join, split->s2)) != hipSuccess) return e;
-    }
-    step = "large plans";
-    if (big > 0) {
-        hipLaunchKernelGGL(plan_kernel<PLAN_THREADS>, dim3(big), dim3(PLAN_THREADS), (size_t)words * 8, s, reqs,
-                           words);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    step = "wait for the small plans";
-    if (beside) {
-        if ((e = hipStreamWaitEvent(s, split->join, 0)) != hipSuccess) return e;
-    } else if (big < m) {
-        hipLaunchKernelGGL(plan_kernel<SMALL_PLAN_THREADS>, dim3(m - big), dim3(SMALL_PLAN_THREADS),
-                           (size_t)words * 8, s, reqs + big, words);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
+    // One launch, the largest plans first.  Per-workgroup start and end
+    // stamps on the 4096-pair batch (a timing build): 768-thread workgroups,
+    // two per CU, finish all plans in 1.35-1.38 ms; the 1024 largest in
+    // 1024-thread workgroups (one per CU) and the rest in 512-thread ones
+    // took 1.84-1.86 ms, because the second launch, on a second stream of
+    // the captured graph, ran only after the first; 640, 896 and 512
+    // threads for all: 1.51, 2.05 and 1.78 ms.
+    hipLaunchKernelGGL(plan_kernel<PLAN_THREADS>, dim3(m), dim3(PLAN_THREADS), (size_t)words * 8, s, reqs, words);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(FIN_THREADS), 0, s, desc, chunk_prefix, m, policy, root_chunk,
                        (unsigned long long)units);
     return hipGetLastError();
