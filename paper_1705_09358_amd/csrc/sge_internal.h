@@ -298,8 +298,10 @@ struct DevWork {
 // per chunk, or (0) the total roots over 4 * `units`.
 hipError_t launch_plan(const PlanIn *reqs, uint32_t m, uint32_t wmax, uint32_t kmax, InstDesc *desc, unsigned *chunk_prefix,
                        int policy, uint32_t root_chunk, uint64_t units, hipStream_t s);
-// LDS words of the plan kernel's support buffer (larger W uses PlanIn::support).
-constexpr uint32_t PLAN_LDS_WORDS = 2048;
+// LDS words of the plan kernel's support buffer (larger W uses PlanIn::support):
+// 64 KB, so two plan workgroups reside per CU, and a target of up to 8192
+// nodes keeps one support word per node.
+constexpr uint32_t PLAN_LDS_WORDS = 8192;
 
 // Launch one persistent search over `ninst` planned instances.  The grid is
 // the resident maximum (or cfg.blocks); blocks beyond what the root chunks

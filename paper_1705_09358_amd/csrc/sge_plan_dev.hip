@@ -8,13 +8,16 @@
 //    with one ballot per pattern node.
 //  * Arc-consistency (Section 4.1) to the greatest fixpoint.  The first round
 //    (all domains still label-and-degree sets) reads the target's
-//    neighbour-degree table; later rounds work in support form:
-//    v stays in D(u) iff for each pattern neighbour w of u some target
-//    neighbour of v lies in D(w), i.e. v lies in the support set S(w), the
-//    union of the target rows of D(w).  S(w) is scattered into LDS with atomic
-//    ORs, one lane per member of D(w); the pattern neighbours of w are then
-//    intersected with it.  A round recomputes S(w) only for the w whose domain
-//    changed in the previous round.
+//    neighbour-degree table, in the same pass that builds the domains; later
+//    rounds work in support form: v stays in D(u) iff for each pattern
+//    neighbour w of u some target neighbour of v lies in D(w), i.e. v lies in
+//    the support set S(w), the union of the target rows of D(w).  A round
+//    recomputes S(w) only for the w whose domain changed in the previous
+//    round.  For targets of up to 64 W <= the LDS budget the supports are
+//    kept by target node (word y: bit j set when y supports the round's j-th
+//    changed node), so each target node's list is read once per round and
+//    scattered with one atomic OR per entry; otherwise S(w) is a bit row per
+//    w, scattered one lane per member of D(w).
 //  * Forward checking (Section 4.2.2): while a domain is a singleton {t} that
 //    has not been used, t leaves every other domain.
 //  * The constraint-first order (Section "RI"; singletons first and the
@@ -42,6 +45,11 @@ namespace {
 // what this kernel's launches reach: 1024-thread workgroups reside one per
 // CU, 512-thread ones three).
 constexpr int PLAN_THREADS = 768;
+
+// Neighbour-degree table columns the first arc-consistency round packs per
+// target node (more distinct labels among a pattern's nodes read the table
+// column by column).
+constexpr uint32_t TAB_COLS = 24;
 
 // Device memory in the global address space: the pointers a plan request
 // holds are loaded from memory, so the compiler would treat them as generic
@@ -92,13 +100,16 @@ __device__ __forceinline__ unsigned long long range_mask(uint32_t t, uint32_t lo
 }
 
 template <int PLAN_THREADS>
-__global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, uint32_t lds_words) {
+__global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *reqs, uint32_t lds_words) {
     constexpr int PLAN_WAVES = PLAN_THREADS / 64;
     extern __shared__ unsigned long long s_support[];
     __shared__ unsigned long long s_nb[KMAX];
     __shared__ uint32_t s_lab[KMAX], s_deg[KMAX], s_dsize[KMAX], s_order[KMAX], s_pos[KMAX];
     __shared__ uint32_t s_bw[KMAX], s_aff[KMAX];
     __shared__ int32_t s_par[KMAX];
+    __shared__ unsigned long long s_mu[KMAX];
+    __shared__ unsigned long long s_need[KMAX * (TAB_COLS / 8)];
+    __shared__ uint32_t s_cols[TAB_COLS], s_cix[KMAX], s_ncols;
     __shared__ unsigned long long s_next;
     __shared__ int s_empty;
 
@@ -121,33 +132,111 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
         s_deg[tid] = pat->deg[tid];
         s_lab[tid] = R.labelled ? label_id(glob(R.label_keys), R.nlabels, pat->label[tid]) : LABEL_ANY;
     }
-    if (tid == 0) s_empty = 0;
+    if (tid == 0) {
+        s_empty = 0;
+        s_next = 0;
+    }
     __syncthreads();
+
+    // The first arc-consistency round of RI-DS against the neighbour-degree
+    // table: v keeps its place in D(u) when, for every column c (a label, or
+    // "any"), its largest neighbour degree of that column reaches need(u, c),
+    // the largest degree among u's pattern neighbours of that column.  Up to
+    // TAB_COLS columns are read per target node, each byte clamped to 127 and
+    // packed eight to a word, so one word subtraction compares eight columns
+    // (no borrow crosses a byte: pattern degrees are below 128).
+    bool table = use_dom && R.nbr_deg != nullptr;
+    for (uint32_t u = 0; u < k; u++) table &= s_lab[u] != LABEL_NONE;   // (an absent label empties a domain anyway)
+    if (table && tid == 0) {
+        unsigned long long nbs = 0;   // the pattern nodes that are someone's neighbour
+        for (uint32_t u = 0; u < k; u++) nbs |= s_nb[u];
+        uint32_t nc = 0;
+        bool fits = true;
+        for (; nbs && fits; nbs &= nbs - 1) {
+            const uint32_t w = (uint32_t)__builtin_ctzll(nbs);
+            const uint32_t c = s_lab[w] == LABEL_ANY ? R.nbr_cols - 1 : s_lab[w];
+            uint32_t x = 0;
+            while (x < nc && s_cols[x] != c) x++;
+            if (x == nc) {
+                if (nc == TAB_COLS) fits = false;
+                else s_cols[nc++] = c;
+            }
+            s_cix[w] = x;
+            fits &= s_deg[w] < 128;
+        }
+        for (uint32_t x = nc; x < TAB_COLS; x++) s_cols[x] = nc ? s_cols[0] : 0;   // read, never required
+        s_ncols = fits ? nc : TAB_COLS + 1;
+    }
+    __syncthreads();
+    const bool packed = table && s_ncols <= TAB_COLS;
+    if (packed && (uint32_t)tid < k) {
+        for (uint32_t q = 0; q < TAB_COLS / 8; q++) s_need[tid * (TAB_COLS / 8) + q] = 0;
+        for (unsigned long long m = s_nb[tid]; m; m &= m - 1) {
+            const uint32_t w = (uint32_t)__builtin_ctzll(m), x = s_cix[w];
+            unsigned long long &nd = s_need[tid * (TAB_COLS / 8) + (x >> 3)];
+            const uint32_t sh = 8 * (x & 7), cur = (uint32_t)(nd >> sh) & 0xFFu;
+            if (s_deg[w] > cur) nd = (nd & ~(0xFFull << sh)) | ((unsigned long long)s_deg[w] << sh);
+        }
+    }
+    if (packed) __syncthreads();
 
     // pattern node data by lane (lane u: node u)
     const bool mine = (uint32_t)lane < k;
     const unsigned long long mynb = mine ? s_nb[lane] : 0ull;
     const uint32_t mydeg = mine ? s_deg[lane] : 0u;
 
-    // label and degree domains; lane l of a wave decides node 64 i + l
+    // label and degree domains, with the table round when packed; lane l of a
+    // wave decides node 64 i + l
+    const uint32_t ngroups = packed ? (s_ncols + 7) / 8 : 0;
+    bool first_changed = false;   // lane u: the table round removed a node from D(u)
     for (uint32_t i = wave; i < W; i += PLAN_WAVES) {
         const uint32_t v = i * 64 + lane;
         const bool valid = v < n;
         uint32_t vl = LABEL_NONE, vd = 0;
+        unsigned long long A[TAB_COLS / 8] = {};
         if (valid) {
             const NodeRec r = ld_node(node + v);
             vl = r.label;
             vd = r.deg;
+            const gp<const uint8_t> tab = glob(R.nbr_deg) + v;
+#pragma unroll
+            for (uint32_t g = 0; g < TAB_COLS / 8; g++) {
+                if (g < ngroups) {
+                    uint32_t b[8];
+#pragma unroll
+                    for (uint32_t x = 0; x < 8; x++) {
+                        // (a volatile read: hoisted out of the loop, the column
+                        // offsets would spill)
+                        const uint32_t c = ((volatile uint32_t *)s_cols)[g * 8 + x];
+                        b[x] = tab[(size_t)c * R.nbr_stride];
+                    }
+#pragma unroll
+                    for (uint32_t x = 0; x < 8; x++) A[g] |= (unsigned long long)min(b[x], 127u) << (8 * x);
+                }
+            }
         }
-        unsigned long long row = 0;
-        // the pattern node's label and degree are uniform LDS reads (broadcasts)
+        unsigned long long row = 0, lrow = 0;
+        // the pattern node's label, degree and needs are uniform LDS reads (broadcasts)
         for (uint32_t u = 0; u < k; u++) {
             const uint32_t lu = s_lab[u], du = s_deg[u];
             const bool p = valid && (lu == LABEL_ANY || vl == lu) && vd >= du;
-            const unsigned long long b = __ballot(p);
-            if ((uint32_t)lane == u) row = b;
+            bool q = p;
+            constexpr unsigned long long H = 0x8080808080808080ull;
+#pragma unroll
+            for (uint32_t g = 0; g < TAB_COLS / 8; g++)
+                if (g < ngroups) q = q && (((A[g] | H) - s_need[u * (TAB_COLS / 8) + g]) & H) == H;
+            const unsigned long long b = __ballot(p), bq = __ballot(q);
+            if ((uint32_t)lane == u) {
+                lrow = b;
+                row = bq;
+            }
         }
         if (mine) D[(size_t)lane * W + i] = row;
+        first_changed |= row != lrow;
+    }
+    if (packed) {
+        const unsigned long long ch = __ballot(mine && first_changed);
+        if (lane == 0 && ch) atomicOr(&s_next, ch);
     }
     __syncthreads();
 
@@ -248,14 +337,94 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
             __syncthreads();
         }
     };
+    // arc-consistency with the supports kept by target node: T[y] bit j is set
+    // when target node y has a neighbour in D(w_j), w_j the j-th node of the
+    // round's dirty set (all of them: k <= 64).  A round clears T, scatters
+    // the list of every node of the union of those domains (lane l of a wave:
+    // node 64 i + l, which reads its list once for all the w_j it belongs to),
+    // then revises every pattern neighbour u of the set: v stays in D(u) iff
+    // T[v] holds the bits of all w_j adjacent to u.
+    auto arc_consistency_by_node = [&](unsigned long long dirty) {
+        unsigned long long *T = s_support;
+        while (dirty) {
+            const uint32_t nd = (uint32_t)__popcll(dirty);
+            unsigned long long aff = 0;
+            for (unsigned long long m = dirty; m; m &= m - 1) aff |= s_nb[__builtin_ctzll(m)];
+            const uint32_t naff = (uint32_t)__popcll(aff);
+            if (tid == 0) {
+                s_next = 0;
+                uint32_t j = 0;
+                for (unsigned long long m = dirty; m; m &= m - 1) s_bw[j++] = (uint32_t)__builtin_ctzll(m);
+                j = 0;
+                for (unsigned long long m = aff; m; m &= m - 1) {
+                    const uint32_t u = (uint32_t)__builtin_ctzll(m);
+                    unsigned long long mu = 0;
+                    for (unsigned long long x = s_nb[u] & dirty; x; x &= x - 1)
+                        mu |= 1ull << __popcll(dirty & ((1ull << __builtin_ctzll(x)) - 1));
+                    s_aff[j] = u;
+                    s_mu[j++] = mu;
+                }
+            }
+            for (uint32_t idx = tid; idx < W * 64; idx += PLAN_THREADS) T[idx] = 0;
+            __syncthreads();
+            for (uint32_t i = wave; i < W; i += PLAN_WAVES) {
+                const uint32_t v = i * 64 + lane;
+                // lane j: word i of D(w_j); its bit l goes to lane l's mask bit j
+                const uint64_t wj = (uint32_t)lane < nd ? D[(size_t)s_bw[lane] * W + i] : 0;
+                NodeRec r{0, 0, 0, 0};
+                if (v < n) r = ld_node(node + v);
+                unsigned long long mask = 0;
+                for (uint32_t j = 0; j < nd; j++) {
+                    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)wj, (int)j);
+                    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(wj >> 32), (int)j);
+                    const uint32_t bit = lane < 32 ? (lo >> lane) & 1u : (hi >> (lane - 32)) & 1u;
+                    mask |= (unsigned long long)bit << j;
+                }
+                if (mask) {
+                    uint32_t e = r.begin;
+                    const uint32_t end = r.begin + r.deg;
+                    for (; e + 4 <= end; e += 4) {
+                        const uint32_t y0 = col[e], y1 = col[e + 1], y2 = col[e + 2], y3 = col[e + 3];
+                        __hip_atomic_fetch_or(&T[y0], mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        __hip_atomic_fetch_or(&T[y1], mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        __hip_atomic_fetch_or(&T[y2], mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        __hip_atomic_fetch_or(&T[y3], mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                    for (; e < end; e++)
+                        __hip_atomic_fetch_or(&T[col[e]], mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            }
+            __syncthreads();
+            // revise: lane a holds word i of D(u_a), u_a the a-th pattern neighbour of the set
+            bool changed = false;
+            for (uint32_t i = wave; i < W; i += PLAN_WAVES) {
+                const unsigned long long t = T[i * 64 + lane];
+                const uint64_t old = (uint32_t)lane < naff ? D[(size_t)s_aff[lane] * W + i] : 0;
+                uint64_t nw = old;
+                for (uint32_t a = 0; a < naff; a++) {
+                    const unsigned long long mu = s_mu[a];
+                    const unsigned long long b = __ballot((t & mu) == mu);
+                    if ((uint32_t)lane == a) nw = old & b;
+                }
+                if (nw != old) {
+                    D[(size_t)s_aff[lane] * W + i] = nw;
+                    changed = true;
+                }
+            }
+            if (changed) atomicOr(&s_next, 1ull << s_aff[lane]);
+            __syncthreads();
+            dirty = s_next;
+            __syncthreads();
+        }
+    };
     if (use_dom) {
         unsigned long long dirty = 0;   // the nodes to revise the neighbours of
-        bool table = R.nbr_deg != nullptr;
-        for (uint32_t u = 0; u < k; u++) {
+        for (uint32_t u = 0; u < k; u++)
             if (s_nb[u]) dirty |= 1ull << u;
-            table &= s_lab[u] != LABEL_NONE;   // (an absent label empties a domain anyway)
-        }
-        if (table) {
+        if (packed) {
+            dirty = s_next;   // the nodes the table round changed
+            __syncthreads();
+        } else if (table) {
             // the first round, against the label-and-degree domains: v has a
             // neighbour in D(w) iff it has a neighbour of w's label whose
             // degree is at least w's, which the target's neighbour-degree table
@@ -292,7 +461,9 @@ __global__ void __launch_bounds__(PLAN_THREADS) plan_kernel(const PlanIn *reqs, 
             dirty = s_next;
             __syncthreads();
         }
-        if (W <= lds_words)
+        if (!R.rows && W * 64 <= lds_words)
+            arc_consistency_by_node(dirty);
+        else if (W <= lds_words)
             arc_consistency(s_support, max(1u, min(k, lds_words / max(W, 1u))), dirty);
         else
             arc_consistency(glob(reinterpret_cast<unsigned long long *>(R.support)), 1u, dirty);
@@ -547,10 +718,11 @@ __global__ void __launch_bounds__(FIN_THREADS)
 hipError_t launch_plan(const PlanIn *reqs, uint32_t m, uint32_t wmax, uint32_t kmax, InstDesc *desc, unsigned *chunk_prefix,
                        int policy, uint32_t root_chunk, uint64_t units, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    // support rows of one batch: up to PLAN_LDS_WORDS words (the widest
-    // instance's rows times the largest pattern, when that is smaller)
+    // support words: up to PLAN_LDS_WORDS (one per node of the widest target,
+    // or its rows times the largest pattern, when that is smaller)
+    const uint64_t w1 = std::max<uint32_t>(wmax, 1);
     const uint32_t words =
-        (uint32_t)std::min<uint64_t>((uint64_t)std::max<uint32_t>(wmax, 1) * std::max<uint32_t>(kmax, 1), PLAN_LDS_WORDS);
+        (uint32_t)std::min<uint64_t>(std::max<uint64_t>(w1 * 64, w1 * std::max<uint32_t>(kmax, 1)), PLAN_LDS_WORDS);
     // One launch, the largest plans first.  Per-workgroup start and end
     // stamps on the 4096-pair batch (a timing build): 768-thread workgroups,
     // two per CU, finish all plans in 1.35-1.38 ms; the 1024 largest in
