@@ -51,6 +51,11 @@ constexpr int PLAN_THREADS = 768;
 // column by column).
 constexpr uint32_t TAB_COLS = 24;
 
+// Target words (64 nodes each) one wave keeps the domain memberships of in
+// registers during arc-consistency: targets of up to PLAN_WAVES * DT_WORDS
+// words take that path.
+constexpr uint32_t DT_WORDS = 8;
+
 // Device memory in the global address space: the pointers a plan request
 // holds are loaded from memory, so the compiler would treat them as generic
 // and emit flat accesses, whose completion counter is shared with LDS.
@@ -77,17 +82,39 @@ __device__ uint32_t label_id(gp<const uint32_t> keys, uint32_t nl, uint32_t raw)
     return (lo < nl && keys[lo] == raw) ? lo : LABEL_NONE;
 }
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    return x;
+// Wave-wide reductions with DPP moves (register to register, no LDS round
+// trip): row shifts by 1, 2, 4 and 8 leave each 16-lane row's total in its
+// last lane, two row broadcasts (15: rows 1 and 3; 31: rows 2 and 3) carry
+// them on, and lane 63 ends with the total of all 64 lanes.  A lane whose
+// source is outside the row or the masked rows takes 0, the identity of both
+// reductions (the values are unsigned).
+template <class Op>
+__device__ __forceinline__ uint32_t wave_reduce(uint32_t x, Op op) {
+    x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false));   // row_shr:1
+    x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false));   // row_shr:2
+    x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false));   // row_shr:4
+    x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false));   // row_shr:8
+    x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false));   // row_bcast:15
+    x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false));   // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
-__device__ __forceinline__ unsigned long long wave_max(unsigned long long x) {
-    for (int o = 32; o > 0; o >>= 1) {
-        const unsigned long long y = __shfl_xor(x, o);
-        x = y > x ? y : x;
-    }
-    return x;
+__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
+    return wave_reduce(x, [](uint32_t a, uint32_t b) { return a + b; });
+}
+
+__device__ __forceinline__ unsigned long long wave_or64(unsigned long long x) {
+    const auto o = [](uint32_t a, uint32_t b) { return a | b; };
+    return ((unsigned long long)wave_reduce((uint32_t)(x >> 32), o) << 32) | wave_reduce((uint32_t)x, o);
+}
+
+// the lane holding the largest 64-bit key (keys distinct, or all zero: lane 0)
+__device__ __forceinline__ uint32_t wave_argmax(unsigned long long key) {
+    const auto mx = [](uint32_t a, uint32_t b) { return a > b ? a : b; };
+    const uint32_t hi = (uint32_t)(key >> 32), lo = (uint32_t)key;
+    const uint32_t hmax = wave_reduce(hi, mx);
+    const uint32_t lmax = wave_reduce(hi == hmax ? lo : 0u, mx);
+    return (uint32_t)__builtin_ctzll(__ballot(hi == hmax && lo == lmax));
 }
 
 // bits of word t (nodes 64t .. 64t+63) that lie in [lo, hi)
@@ -109,7 +136,7 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
     __shared__ int32_t s_par[KMAX];
     __shared__ unsigned long long s_mu[KMAX];
     __shared__ unsigned long long s_need[KMAX * (TAB_COLS / 8)];
-    __shared__ uint32_t s_cols[TAB_COLS], s_cix[KMAX], s_ncols;
+    __shared__ uint32_t s_coff[TAB_COLS], s_cix[KMAX], s_ncols;   // column byte offsets in the table
     __shared__ unsigned long long s_next;
     __shared__ int s_empty;
 
@@ -128,6 +155,7 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
     const gp<DevPlan> pl = glob(R.plan);
 
     if ((uint32_t)tid < k) {
+        s_dsize[tid] = 0;
         s_nb[tid] = pat->nb[tid];
         s_deg[tid] = pat->deg[tid];
         s_lab[tid] = R.labelled ? label_id(glob(R.label_keys), R.nlabels, pat->label[tid]) : LABEL_ANY;
@@ -154,17 +182,17 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
         bool fits = true;
         for (; nbs && fits; nbs &= nbs - 1) {
             const uint32_t w = (uint32_t)__builtin_ctzll(nbs);
-            const uint32_t c = s_lab[w] == LABEL_ANY ? R.nbr_cols - 1 : s_lab[w];
+            const uint32_t c = (s_lab[w] == LABEL_ANY ? R.nbr_cols - 1 : s_lab[w]) * R.nbr_stride;
             uint32_t x = 0;
-            while (x < nc && s_cols[x] != c) x++;
+            while (x < nc && s_coff[x] != c) x++;
             if (x == nc) {
                 if (nc == TAB_COLS) fits = false;
-                else s_cols[nc++] = c;
+                else s_coff[nc++] = c;
             }
             s_cix[w] = x;
             fits &= s_deg[w] < 128;
         }
-        for (uint32_t x = nc; x < TAB_COLS; x++) s_cols[x] = nc ? s_cols[0] : 0;   // read, never required
+        for (uint32_t x = nc; x < TAB_COLS; x++) s_coff[x] = nc ? s_coff[0] : 0;   // read, never required
         s_ncols = fits ? nc : TAB_COLS + 1;
     }
     __syncthreads();
@@ -188,55 +216,115 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
     // label and degree domains, with the table round when packed; lane l of a
     // wave decides node 64 i + l
     const uint32_t ngroups = packed ? (s_ncols + 7) / 8 : 0;
-    bool first_changed = false;   // lane u: the table round removed a node from D(u)
-    for (uint32_t i = wave; i < W; i += PLAN_WAVES) {
-        const uint32_t v = i * 64 + lane;
-        const bool valid = v < n;
-        uint32_t vl = LABEL_NONE, vd = 0;
+    const gp<const uint8_t> tab = glob(R.nbr_deg);
+    constexpr unsigned long long H = 0x8080808080808080ull;
+    static_assert(TAB_COLS == 24, "three column groups");
+    // node v's label, degree and (packed) table bytes, ORed with H (all H when
+    // not packed or v >= n)
+    auto node_facts = [&](uint32_t v, uint32_t &vl, uint32_t &vd, unsigned long long &A0, unsigned long long &A1,
+                          unsigned long long &A2) {
         unsigned long long A[TAB_COLS / 8] = {};
-        if (valid) {
+        vl = LABEL_NONE;
+        vd = 0;
+        if (v < n) {
             const NodeRec r = ld_node(node + v);
             vl = r.label;
             vd = r.deg;
-            const gp<const uint8_t> tab = glob(R.nbr_deg) + v;
+            // the offsets are read in the loop (an opaque pointer keeps the
+            // compiler from hoisting all of them into registers), the loads of a
+            // group issued together
+            __attribute__((address_space(3))) const uint32_t *coff =
+                (__attribute__((address_space(3))) const uint32_t *)s_coff;
+            asm volatile("" : "+v"(coff));
 #pragma unroll
             for (uint32_t g = 0; g < TAB_COLS / 8; g++) {
                 if (g < ngroups) {
                     uint32_t b[8];
 #pragma unroll
-                    for (uint32_t x = 0; x < 8; x++) {
-                        // (a volatile read: hoisted out of the loop, the column
-                        // offsets would spill)
-                        const uint32_t c = ((volatile uint32_t *)s_cols)[g * 8 + x];
-                        b[x] = tab[(size_t)c * R.nbr_stride];
-                    }
+                    for (uint32_t x = 0; x < 8; x++) b[x] = tab[v + coff[g * 8 + x]];
 #pragma unroll
                     for (uint32_t x = 0; x < 8; x++) A[g] |= (unsigned long long)min(b[x], 127u) << (8 * x);
                 }
             }
         }
-        unsigned long long row = 0, lrow = 0;
-        // the pattern node's label, degree and needs are uniform LDS reads (broadcasts)
-        for (uint32_t u = 0; u < k; u++) {
-            const uint32_t lu = s_lab[u], du = s_deg[u];
-            const bool p = valid && (lu == LABEL_ANY || vl == lu) && vd >= du;
-            bool q = p;
-            constexpr unsigned long long H = 0x8080808080808080ull;
+        A0 = A[0] | H;
+        A1 = A[1] | H;
+        A2 = A[2] | H;
+    };
+    // RI-DS on a target of up to PLAN_WAVES * DT_WORDS words (and not by
+    // adjacency rows): each lane keeps, for its nodes v = 64 i + lane
+    // (i = wave + PLAN_WAVES t), dt[t] = the pattern nodes whose domain holds
+    // v, in registers through the arc-consistency rounds; the domain rows are
+    // written once, at the end
+    const bool reg_ac = use_dom && !R.rows && W <= PLAN_WAVES * DT_WORDS && W * 64 <= lds_words;
+    unsigned long long dt[DT_WORDS];
+    if (reg_ac) {
+        unsigned long long chg = 0;   // pattern nodes the table round removed a node from
 #pragma unroll
-            for (uint32_t g = 0; g < TAB_COLS / 8; g++)
-                if (g < ngroups) q = q && (((A[g] | H) - s_need[u * (TAB_COLS / 8) + g]) & H) == H;
-            const unsigned long long b = __ballot(p), bq = __ballot(q);
-            if ((uint32_t)lane == u) {
-                lrow = b;
-                row = bq;
+        for (uint32_t t = 0; t < DT_WORDS; t++) {
+            dt[t] = 0;
+            const uint32_t i = wave + t * PLAN_WAVES;
+            if (i < W) {
+                const uint32_t v = i * 64 + lane;
+                uint32_t vl, vd;
+                unsigned long long A0, A1, A2;
+                node_facts(v, vl, vd, A0, A1, A2);
+                const bool valid = v < n;
+                unsigned long long pm = 0, qm = 0;
+                for (uint32_t u = 0; u < k; u++) {
+                    const uint32_t lu = s_lab[u], du = s_deg[u];
+                    const bool p = valid && (lu == LABEL_ANY || vl == lu) && vd >= du;
+                    const unsigned long long *nd = &s_need[u * (TAB_COLS / 8)];
+                    const bool q = p && (ngroups == 0 || ((A0 - nd[0]) & (A1 - nd[1]) & (A2 - nd[2]) & H) == H);
+                    pm |= (unsigned long long)p << u;
+                    qm |= (unsigned long long)q << u;
+                }
+                dt[t] = qm;
+                chg |= pm & ~qm;
             }
         }
-        if (mine) D[(size_t)lane * W + i] = row;
-        first_changed |= row != lrow;
-    }
-    if (packed) {
-        const unsigned long long ch = __ballot(mine && first_changed);
-        if (lane == 0 && ch) atomicOr(&s_next, ch);
+        if (packed) {
+            chg = wave_or64(chg);
+            if (lane == 0 && chg) atomicOr(&s_next, chg);
+        }
+    } else {
+        bool first_changed = false;   // lane u: the table round removed a node from D(u)
+        for (uint32_t i = wave; i < W; i += PLAN_WAVES) {
+            const uint32_t v = i * 64 + lane;
+            const bool valid = v < n;
+            uint32_t vl, vd;
+            unsigned long long A0, A1, A2;
+            node_facts(v, vl, vd, A0, A1, A2);
+            unsigned long long row = 0, lrow = 0;
+            // the pattern node's label, degree and needs are uniform LDS reads (broadcasts)
+            if (ngroups == 0) {
+                for (uint32_t u = 0; u < k; u++) {
+                    const uint32_t lu = s_lab[u], du = s_deg[u];
+                    const bool p = valid && (lu == LABEL_ANY || vl == lu) && vd >= du;
+                    const unsigned long long b = __ballot(p);
+                    if ((uint32_t)lane == u) row = b;
+                }
+                lrow = row;
+            } else {
+                for (uint32_t u = 0; u < k; u++) {
+                    const uint32_t lu = s_lab[u], du = s_deg[u];
+                    const bool p = valid && (lu == LABEL_ANY || vl == lu) && vd >= du;
+                    const unsigned long long *nd = &s_need[u * (TAB_COLS / 8)];
+                    const bool q = p && ((A0 - nd[0]) & (A1 - nd[1]) & (A2 - nd[2]) & H) == H;
+                    const unsigned long long b = __ballot(p), bq = __ballot(q);
+                    if ((uint32_t)lane == u) {
+                        lrow = b;
+                        row = bq;
+                    }
+                }
+            }
+            if (mine) D[(size_t)lane * W + i] = row;
+            first_changed |= row != lrow;
+        }
+        if (packed) {
+            const unsigned long long ch = __ballot(mine && first_changed);
+            if (lane == 0 && ch) atomicOr(&s_next, ch);
+        }
     }
     __syncthreads();
 
@@ -337,86 +425,6 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
             __syncthreads();
         }
     };
-    // arc-consistency with the supports kept by target node: T[y] bit j is set
-    // when target node y has a neighbour in D(w_j), w_j the j-th node of the
-    // round's dirty set (all of them: k <= 64).  A round clears T, scatters
-    // the list of every node of the union of those domains (lane l of a wave:
-    // node 64 i + l, which reads its list once for all the w_j it belongs to),
-    // then revises every pattern neighbour u of the set: v stays in D(u) iff
-    // T[v] holds the bits of all w_j adjacent to u.
-    auto arc_consistency_by_node = [&](unsigned long long dirty) {
-        unsigned long long *T = s_support;
-        while (dirty) {
-            const uint32_t nd = (uint32_t)__popcll(dirty);
-            unsigned long long aff = 0;
-            for (unsigned long long m = dirty; m; m &= m - 1) aff |= s_nb[__builtin_ctzll(m)];
-            const uint32_t naff = (uint32_t)__popcll(aff);
-            if (tid == 0) {
-                s_next = 0;
-                uint32_t j = 0;
-                for (unsigned long long m = dirty; m; m &= m - 1) s_bw[j++] = (uint32_t)__builtin_ctzll(m);
-                j = 0;
-                for (unsigned long long m = aff; m; m &= m - 1) {
-                    const uint32_t u = (uint32_t)__builtin_ctzll(m);
-                    unsigned long long mu = 0;
-                    for (unsigned long long x = s_nb[u] & dirty; x; x &= x - 1)
-                        mu |= 1ull << __popcll(dirty & ((1ull << __builtin_ctzll(x)) - 1));
-                    s_aff[j] = u;
-                    s_mu[j++] = mu;
-                }
-            }
-            for (uint32_t idx = tid; idx < W * 64; idx += PLAN_THREADS) T[idx] = 0;
-            __syncthreads();
-            for (uint32_t i = wave; i < W; i += PLAN_WAVES) {
-                const uint32_t v = i * 64 + lane;
-                // lane j: word i of D(w_j); its bit l goes to lane l's mask bit j
-                const uint64_t wj = (uint32_t)lane < nd ? D[(size_t)s_bw[lane] * W + i] : 0;
-                NodeRec r{0, 0, 0, 0};
-                if (v < n) r = ld_node(node + v);
-                unsigned long long mask = 0;
-                for (uint32_t j = 0; j < nd; j++) {
-                    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)wj, (int)j);
-                    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(wj >> 32), (int)j);
-                    const uint32_t bit = lane < 32 ? (lo >> lane) & 1u : (hi >> (lane - 32)) & 1u;
-                    mask |= (unsigned long long)bit << j;
-                }
-                if (mask) {
-                    uint32_t e = r.begin;
-                    const uint32_t end = r.begin + r.deg;
-                    for (; e + 4 <= end; e += 4) {
-                        const uint32_t y0 = col[e], y1 = col[e + 1], y2 = col[e + 2], y3 = col[e + 3];
-                        __hip_atomic_fetch_or(&T[y0], mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        __hip_atomic_fetch_or(&T[y1], mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        __hip_atomic_fetch_or(&T[y2], mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        __hip_atomic_fetch_or(&T[y3], mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    }
-                    for (; e < end; e++)
-                        __hip_atomic_fetch_or(&T[col[e]], mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                }
-            }
-            __syncthreads();
-            // revise: lane a holds word i of D(u_a), u_a the a-th pattern neighbour of the set
-            bool changed = false;
-            for (uint32_t i = wave; i < W; i += PLAN_WAVES) {
-                const unsigned long long t = T[i * 64 + lane];
-                const uint64_t old = (uint32_t)lane < naff ? D[(size_t)s_aff[lane] * W + i] : 0;
-                uint64_t nw = old;
-                for (uint32_t a = 0; a < naff; a++) {
-                    const unsigned long long mu = s_mu[a];
-                    const unsigned long long b = __ballot((t & mu) == mu);
-                    if ((uint32_t)lane == a) nw = old & b;
-                }
-                if (nw != old) {
-                    D[(size_t)s_aff[lane] * W + i] = nw;
-                    changed = true;
-                }
-            }
-            if (changed) atomicOr(&s_next, 1ull << s_aff[lane]);
-            __syncthreads();
-            dirty = s_next;
-            __syncthreads();
-        }
-    };
     if (use_dom) {
         unsigned long long dirty = 0;   // the nodes to revise the neighbours of
         for (uint32_t u = 0; u < k; u++)
@@ -424,7 +432,87 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
         if (packed) {
             dirty = s_next;   // the nodes the table round changed
             __syncthreads();
-        } else if (table) {
+        }
+        if (reg_ac) {
+            // rounds with the supports kept by target node: T[y] bit w is set
+            // when target node y has a neighbour in D(w), for the w of the
+            // round's dirty set.  A round clears T, scatters the list of every
+            // node in the union of those domains (lane l: its nodes, each list
+            // read once for all the w whose domain holds the node), then
+            // revises every pattern neighbour u of the set: v stays in D(u) iff
+            // T[v] holds every dirty neighbour of u.  (Without the packed table
+            // round the first round starts from every node with a neighbour,
+            // which reaches the same fixpoint.)
+            unsigned long long *T = s_support;
+            while (dirty) {
+                unsigned long long aff = 0;
+                for (unsigned long long m = dirty; m; m &= m - 1) aff |= s_nb[__builtin_ctzll(m)];
+                if ((uint32_t)tid < k) s_mu[tid] = s_nb[tid] & dirty;
+                if (tid == 0) s_next = 0;
+                for (uint32_t idx = tid; idx < W * 64; idx += PLAN_THREADS) T[idx] = 0;
+                __syncthreads();
+#pragma unroll
+                for (uint32_t t = 0; t < DT_WORDS; t++) {
+                    const uint32_t i = wave + t * PLAN_WAVES;
+                    const unsigned long long mask = i < W ? dt[t] & dirty : 0ull;
+                    if (mask) {   // a member of some dirty domain: node i * 64 + lane < n
+                        const NodeRec r = ld_node(node + i * 64 + lane);
+                        uint32_t e = r.begin;
+                        const uint32_t end = r.begin + r.deg;
+                        for (; e + 4 <= end; e += 4) {
+                            const uint32_t y0 = col[e], y1 = col[e + 1], y2 = col[e + 2], y3 = col[e + 3];
+                            __hip_atomic_fetch_or(&T[y0], mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                            __hip_atomic_fetch_or(&T[y1], mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                            __hip_atomic_fetch_or(&T[y2], mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                            __hip_atomic_fetch_or(&T[y3], mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }
+                        for (; e < end; e++)
+                            __hip_atomic_fetch_or(&T[col[e]], mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                }
+                __syncthreads();
+                unsigned long long removed = 0;   // pattern nodes whose domain lost a node
+#pragma unroll
+                for (uint32_t t = 0; t < DT_WORDS; t++) {
+                    const uint32_t i = wave + t * PLAN_WAVES;
+                    if (i < W) {
+                        const unsigned long long tv = T[i * 64 + lane];
+                        unsigned long long fail = 0;
+                        for (unsigned long long m = dt[t] & aff; m; m &= m - 1) {
+                            const uint32_t u = (uint32_t)__builtin_ctzll(m);
+                            const unsigned long long mu = s_mu[u];
+                            if ((tv & mu) != mu) fail |= 1ull << u;
+                        }
+                        dt[t] &= ~fail;
+                        removed |= fail;
+                    }
+                }
+                removed = wave_or64(removed);
+                if (lane == 0 && removed) atomicOr(&s_next, removed);
+                __syncthreads();
+                dirty = s_next;
+                __syncthreads();
+            }
+            // the domain rows (lane u: row u of each of the wave's words) and sizes
+            uint32_t cnt = 0;
+#pragma unroll
+            for (uint32_t t = 0; t < DT_WORDS; t++) {
+                const uint32_t i = wave + t * PLAN_WAVES;
+                if (i < W) {
+                    unsigned long long row = 0;
+                    for (uint32_t u = 0; u < k; u++) {
+                        const unsigned long long b = __ballot((dt[t] >> u) & 1ull);
+                        if ((uint32_t)lane == u) row = b;
+                    }
+                    if (mine) {
+                        D[(size_t)lane * W + i] = row;
+                        cnt += (uint32_t)__popcll(row);
+                    }
+                }
+            }
+            if (mine && cnt) atomicAdd(&s_dsize[lane], cnt);
+            __syncthreads();
+        } else if (!packed && table) {
             // the first round, against the label-and-degree domains: v has a
             // neighbour in D(w) iff it has a neighbour of w's label whose
             // degree is at least w's, which the target's neighbour-degree table
@@ -461,16 +549,16 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
             dirty = s_next;
             __syncthreads();
         }
-        if (!R.rows && W * 64 <= lds_words)
-            arc_consistency_by_node(dirty);
-        else if (W <= lds_words)
-            arc_consistency(s_support, max(1u, min(k, lds_words / max(W, 1u))), dirty);
-        else
-            arc_consistency(glob(reinterpret_cast<unsigned long long *>(R.support)), 1u, dirty);
+        if (!reg_ac) {
+            if (W <= lds_words)
+                arc_consistency(s_support, max(1u, min(k, lds_words / max(W, 1u))), dirty);
+            else
+                arc_consistency(glob(reinterpret_cast<unsigned long long *>(R.support)), 1u, dirty);
+        }
     }
 
-    // domain sizes; an empty domain leaves nothing to search
-    for (uint32_t u = wave; u < k; u += PLAN_WAVES) {
+    // domain sizes (RI-DS); an empty domain leaves nothing to search
+    for (uint32_t u = wave; use_dom && !reg_ac && u < k; u += PLAN_WAVES) {
         uint32_t c = 0;
         for (uint32_t i = lane; i < W; i += 64) c += (uint32_t)__popcll(D[(size_t)u * W + i]);
         c = wave_sum(c);
@@ -525,7 +613,7 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
 
     // the constraint-first order (one wave; lane u scores pattern node u)
     if (!empty && wave == 0) {
-        const uint32_t mysz = mine ? s_dsize[lane] : 0u;
+        const uint32_t mysz = mine && use_dom ? s_dsize[lane] : 0u;
         const unsigned long long all = k == 64 ? ~0ull : ((1ull << k) - 1);
         unsigned long long placed = 0;
         uint32_t len = 0;
@@ -540,24 +628,16 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
         while (len < k) {
             // w_n(u) counts the placed w sharing an unplaced neighbour x with u:
             // the placed members of the union of N(x) over unplaced x in N(u).
-            // N(x) comes from LDS at a uniform address (one broadcast read),
-            // four unplaced x at a time so that the reads overlap; a repeated
-            // x at the end of the set adds nothing to the union
+            // Only the frontier (unplaced x with a placed neighbour) adds
+            // anything; N(x) is lane x's row, read into scalar registers
+            const unsigned long long front = __ballot(mine && !((placed >> lane) & 1ull) && (mynb & placed) != 0ull);
             unsigned long long two_hop = 0;
-            for (unsigned long long m = all & ~placed; m;) {
-                const uint32_t x0 = (uint32_t)__builtin_ctzll(m);
-                m &= m - 1;
-                const uint32_t x1 = m ? (uint32_t)__builtin_ctzll(m) : x0;
-                m &= m ? m - 1 : 0ull;
-                const uint32_t x2 = m ? (uint32_t)__builtin_ctzll(m) : x0;
-                m &= m ? m - 1 : 0ull;
-                const uint32_t x3 = m ? (uint32_t)__builtin_ctzll(m) : x0;
-                m &= m ? m - 1 : 0ull;
-                const unsigned long long n0 = s_nb[x0], n1 = s_nb[x1], n2 = s_nb[x2], n3 = s_nb[x3];
-                two_hop |= n0 & (0ull - ((mynb >> x0) & 1ull));
-                two_hop |= n1 & (0ull - ((mynb >> x1) & 1ull));
-                two_hop |= n2 & (0ull - ((mynb >> x2) & 1ull));
-                two_hop |= n3 & (0ull - ((mynb >> x3) & 1ull));
+            for (unsigned long long m = front; m; m &= m - 1) {
+                const int x = (int)__builtin_ctzll(m);
+                const unsigned long long nx =
+                    ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mynb >> 32), x) << 32) |
+                    (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mynb, x);
+                two_hop |= nx & (0ull - ((mynb >> x) & 1ull));
             }
             unsigned long long key = 0;
             if (mine && !((placed >> lane) & 1ull)) {
@@ -572,8 +652,7 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
             // the keys are distinct (their lowest bits are the lane), so one
             // lane holds the maximum; its ballot names it as a wave-uniform
             // value, which keeps `placed` and the loop above scalar
-            const unsigned long long best = wave_max(key);
-            const uint32_t u = (uint32_t)__builtin_ctzll(__ballot(key == best));
+            const uint32_t u = wave_argmax(key);
             if (lane == 0) s_order[len] = u;
             len++;
             placed |= 1ull << u;
