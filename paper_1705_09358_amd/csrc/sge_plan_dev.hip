@@ -4,8 +4,8 @@
 // (sge_plan.cpp) builds, step for step:
 //
 //  * Domains (Section 4.1): D(u) starts as the target nodes passing the label
-//    and degree rules for pattern node u, built a word (64 nodes) at a time
-//    with one ballot per pattern node.
+//    and degree rules for pattern node u; lane l of a wave decides target
+//    node 64 i + l for every pattern node.
 //  * Arc-consistency (Section 4.1) to the greatest fixpoint.  The first round
 //    (all domains still label-and-degree sets) reads the target's
 //    neighbour-degree table, in the same pass that builds the domains; later
@@ -13,11 +13,13 @@
 //    neighbour w of u some target neighbour of v lies in D(w), i.e. v lies in
 //    the support set S(w), the union of the target rows of D(w).  A round
 //    recomputes S(w) only for the w whose domain changed in the previous
-//    round.  For targets of up to 64 W <= the LDS budget the supports are
-//    kept by target node (word y: bit j set when y supports the round's j-th
-//    changed node), so each target node's list is read once per round and
-//    scattered with one atomic OR per entry; otherwise S(w) is a bit row per
-//    w, scattered one lane per member of D(w).
+//    round.  On targets of up to PLAN_WAVES * DT_WORDS words each lane keeps
+//    its nodes' domain memberships (a 64-bit set of pattern nodes per target
+//    node) in registers, the supports are kept by target node in LDS (one
+//    word per node: the dirty w it supports), each list is read once per
+//    round and scattered with one atomic OR per entry, and the domain rows
+//    are written once at the end; otherwise S(w) is a bit row per w in LDS
+//    or device memory, scattered one lane per member of D(w).
 //  * Forward checking (Section 4.2.2): while a domain is a singleton {t} that
 //    has not been used, t leaves every other domain.
 //  * The constraint-first order (Section "RI"; singletons first and the
@@ -29,21 +31,17 @@
 //    position 0 limited to the root range).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "sge_internal.h"
 
 namespace sge {
 
 namespace {
 
-// Workgroup size: 1024 threads, so each plan's latency-bound phases spread
-// over 16 waves.  With 256-thread workgroups (more plans resident per CU) a
-// 4096-plan batch took as long as its largest plan, 2.96 ms of which that
-// plan alone took 2.9 ms; with 1024 threads the largest plan takes about
-// 1 ms and the batch about 2 ms, bound by the one workgroup per CU that
-// resides at a time.
-// Twelve waves per workgroup: two of them reside per CU (twenty-four waves,
-// what this kernel's launches reach: 1024-thread workgroups reside one per
-// CU, 512-thread ones three).
+// Workgroup size: twelve waves, so each plan's latency-bound phases spread
+// over twelve waves, and two workgroups reside per CU (twenty-four waves, what
+// this kernel's launches reach; the kernel is held to 80 VGPRs for it).
 constexpr int PLAN_THREADS = 768;
 
 // Neighbour-degree table columns the first arc-consistency round packs per
@@ -227,25 +225,27 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
         vl = LABEL_NONE;
         vd = 0;
         if (v < n) {
-            const NodeRec r = ld_node(node + v);
-            vl = r.label;
-            vd = r.deg;
             // the offsets are read in the loop (an opaque pointer keeps the
-            // compiler from hoisting all of them into registers), the loads of a
-            // group issued together
+            // compiler from hoisting all of them into registers); the loads of
+            // all groups are issued before the first is used
             __attribute__((address_space(3))) const uint32_t *coff =
                 (__attribute__((address_space(3))) const uint32_t *)s_coff;
             asm volatile("" : "+v"(coff));
+            // one variant per group count, so that no branch separates the loads
+            auto load_groups = [&](auto ng) {
+                constexpr uint32_t NG = decltype(ng)::value;
+                uint32_t b[NG * 8];
 #pragma unroll
-            for (uint32_t g = 0; g < TAB_COLS / 8; g++) {
-                if (g < ngroups) {
-                    uint32_t b[8];
+                for (uint32_t x = 0; x < NG * 8; x++) b[x] = tab[v + coff[x]];
 #pragma unroll
-                    for (uint32_t x = 0; x < 8; x++) b[x] = tab[v + coff[g * 8 + x]];
-#pragma unroll
-                    for (uint32_t x = 0; x < 8; x++) A[g] |= (unsigned long long)min(b[x], 127u) << (8 * x);
-                }
-            }
+                for (uint32_t x = 0; x < NG * 8; x++) A[x / 8] |= (unsigned long long)min(b[x], 127u) << (8 * (x % 8));
+            };
+            if (ngroups == 1) load_groups(std::integral_constant<uint32_t, 1>{});
+            else if (ngroups == 2) load_groups(std::integral_constant<uint32_t, 2>{});
+            else if (ngroups == 3) load_groups(std::integral_constant<uint32_t, 3>{});
+            const NodeRec r = ld_node(node + v);
+            vl = r.label;
+            vd = r.deg;
         }
         A0 = A[0] | H;
         A1 = A[1] | H;
@@ -272,10 +272,11 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
                 const bool valid = v < n;
                 unsigned long long pm = 0, qm = 0;
                 for (uint32_t u = 0; u < k; u++) {
+                    // (bitwise, not short-circuit: no branch per node)
                     const uint32_t lu = s_lab[u], du = s_deg[u];
-                    const bool p = valid && (lu == LABEL_ANY || vl == lu) && vd >= du;
                     const unsigned long long *nd = &s_need[u * (TAB_COLS / 8)];
-                    const bool q = p && (ngroups == 0 || ((A0 - nd[0]) & (A1 - nd[1]) & (A2 - nd[2]) & H) == H);
+                    const bool p = valid & ((lu == LABEL_ANY) | (vl == lu)) & (vd >= du);
+                    const bool q = p & ((ngroups == 0) | (((A0 - nd[0]) & (A1 - nd[1]) & (A2 - nd[2]) & H) == H));
                     pm |= (unsigned long long)p << u;
                     qm |= (unsigned long long)q << u;
                 }
@@ -298,9 +299,10 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
             unsigned long long row = 0, lrow = 0;
             // the pattern node's label, degree and needs are uniform LDS reads (broadcasts)
             if (ngroups == 0) {
+#pragma unroll 4
                 for (uint32_t u = 0; u < k; u++) {
                     const uint32_t lu = s_lab[u], du = s_deg[u];
-                    const bool p = valid && (lu == LABEL_ANY || vl == lu) && vd >= du;
+                    const bool p = valid & ((lu == LABEL_ANY) | (vl == lu)) & (vd >= du);
                     const unsigned long long b = __ballot(p);
                     if ((uint32_t)lane == u) row = b;
                 }
@@ -308,9 +310,9 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
             } else {
                 for (uint32_t u = 0; u < k; u++) {
                     const uint32_t lu = s_lab[u], du = s_deg[u];
-                    const bool p = valid && (lu == LABEL_ANY || vl == lu) && vd >= du;
                     const unsigned long long *nd = &s_need[u * (TAB_COLS / 8)];
-                    const bool q = p && ((A0 - nd[0]) & (A1 - nd[1]) & (A2 - nd[2]) & H) == H;
+                    const bool p = valid & ((lu == LABEL_ANY) | (vl == lu)) & (vd >= du);
+                    const bool q = p & ((((A0 - nd[0]) & (A1 - nd[1]) & (A2 - nd[2]) & H) == H));
                     const unsigned long long b = __ballot(p), bq = __ballot(q);
                     if ((uint32_t)lane == u) {
                         lrow = b;
@@ -802,13 +804,12 @@ hipError_t launch_plan(const PlanIn *reqs, uint32_t m, uint32_t wmax, uint32_t k
     const uint64_t w1 = std::max<uint32_t>(wmax, 1);
     const uint32_t words =
         (uint32_t)std::min<uint64_t>(std::max<uint64_t>(w1 * 64, w1 * std::max<uint32_t>(kmax, 1)), PLAN_LDS_WORDS);
-    // One launch, the largest plans first.  Per-workgroup start and end
-    // stamps on the 4096-pair batch (a timing build): 768-thread workgroups,
-    // two per CU, finish all plans in 1.35-1.38 ms; the 1024 largest in
-    // 1024-thread workgroups (one per CU) and the rest in 512-thread ones
-    // took 1.84-1.86 ms, because the second launch, on a second stream of
-    // the captured graph, ran only after the first; 640, 896 and 512
-    // threads for all: 1.51, 2.05 and 1.78 ms.
+    // One launch, the largest plans first (the requests come ordered by
+    // estimated work).  Per-workgroup start and end stamps on the 4096-pair
+    // batch (a timing build) show about 440 of the 512 resident slots busy
+    // until the last requests; the largest plan takes under half the launch.
+    // A split into two launches on two streams of the captured graph ran them
+    // back to back; 640, 896 and 512 threads were slower than 768.
     hipLaunchKernelGGL(plan_kernel<PLAN_THREADS>, dim3(m), dim3(PLAN_THREADS), (size_t)words * 8, s, reqs, words);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
