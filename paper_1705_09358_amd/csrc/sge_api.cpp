@@ -180,6 +180,9 @@ sge_status upload_pattern(sge_ctx *c, Pattern &p) {
         dp.deg[u] = g.rp[u + 1] - g.rp[u];
         dp.label[u] = g.lab[u];
     }
+    // the RI order depends on the pattern alone: the plan kernel copies it
+    // (it is the one that kernel computes for an undirected pattern)
+    constraint_first_order(dp.nb, dp.deg, nullptr, g.n, false, false, dp.ri_order);
     p.ncomp = dp.ncomp;
     hipError_t e;
     if ((e = hipMalloc(&p.d_pat, sizeof(DevPattern))) != hipSuccess) return hip_fail(c, e, "hipMalloc(pattern)");

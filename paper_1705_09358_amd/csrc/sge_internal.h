@@ -98,6 +98,7 @@ struct DevPattern {
     uint64_t nb[KMAX];            // bit w of nb[u]: {u, w} is a pattern edge
     uint32_t label[KMAX];         // raw labels
     uint32_t deg[KMAX];
+    uint32_t ri_order[KMAX];      // the RI order (pattern structure only), computed when the pattern is loaded
 };
 
 struct Pattern {
@@ -136,6 +137,14 @@ struct Plan {
 // Build the plan.  When want_pos_bitsets is set, `pos_bits` receives k * W
 // words by position: the domain (RI-DS) or the label/degree-compatible set
 // (RI), as the dense search reads them.
+// The constraint-first order (Section "RI"; with domains, singletons first,
+// and with SI the domain-size tie-break of Section 4.2.1): repeatedly the
+// unplaced node with the most placed neighbours (w_m), then the most placed
+// nodes sharing an unplaced neighbour with it (w_n), then the largest degree
+// `odeg`, then (use_si) the smallest domain `dsize`, then the lowest id.
+// `dsize` may be null when neither use_dom nor use_si is set.
+void constraint_first_order(const uint64_t *nb, const uint32_t *odeg, const uint32_t *dsize, uint32_t k, bool use_dom,
+                            bool use_si, uint32_t *order);
 void build_plan(const Target &t, const HostGraph &p, int mode, bool labelled, uint32_t root_lo, uint32_t root_hi,
                 Plan &plan, bool want_pos_bitsets, std::vector<uint64_t> &pos_bits);
 

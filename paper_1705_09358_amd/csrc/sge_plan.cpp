@@ -45,6 +45,38 @@ static inline uint64_t bytes_at_least(const uint8_t *p, uint8_t d) {
 #endif
 }
 
+void constraint_first_order(const uint64_t *nb, const uint32_t *odeg, const uint32_t *dsize, uint32_t k, bool use_dom,
+                            bool use_si, uint32_t *order) {
+    uint64_t placed = 0;
+    uint32_t len = 0;
+    if (use_dom)
+        for (uint32_t u = 0; u < k; u++)
+            if (dsize[u] == 1) { order[len++] = u; placed |= 1ull << u; }
+    while (len < k) {
+        int best = -1;
+        uint32_t bwm = 0, bwn = 0, bdeg = 0, bdom = 0;
+        for (uint32_t u = 0; u < k; u++) {
+            if ((placed >> u) & 1) continue;
+            uint32_t wm = (uint32_t)__builtin_popcountll(nb[u] & placed);
+            uint32_t wn = 0;
+            for (uint64_t m = placed; m; m &= m - 1) {
+                uint32_t w = (uint32_t)__builtin_ctzll(m);
+                if (nb[u] & nb[w] & ~placed) wn++;
+            }
+            const uint32_t du = use_si ? dsize[u] : 0;
+            bool take;
+            if (best < 0) take = true;
+            else if (wm != bwm) take = wm > bwm;
+            else if (wn != bwn) take = wn > bwn;
+            else if (odeg[u] != bdeg) take = odeg[u] > bdeg;
+            else take = use_si && du < bdom;
+            if (take) { best = (int)u; bwm = wm; bwn = wn; bdeg = odeg[u]; bdom = du; }
+        }
+        order[len++] = (uint32_t)best;
+        placed |= 1ull << best;
+    }
+}
+
 void build_plan(const Target &t, const HostGraph &p, int mode, bool labelled, uint32_t root_lo, uint32_t root_hi,
                 Plan &pl, bool want_pos_bits, std::vector<uint64_t> &pos_bits) {
     const HostGraph &tg = t.g;
@@ -296,33 +328,7 @@ void build_plan(const Target &t, const HostGraph &p, int mode, bool labelled, ui
 
     // constraint-first order
     const bool use_si = mode == SGE_RIDS_SI || mode == SGE_RIDS_SI_FC;
-    uint64_t placed = 0;
-    uint32_t len = 0;
-    if (use_dom)
-        for (uint32_t u = 0; u < k; u++)
-            if (dsize[u] == 1) { pl.order[len++] = u; placed |= 1ull << u; }
-    while (len < k) {
-        int best = -1;
-        uint32_t bwm = 0, bwn = 0, bdeg = 0, bdom = 0;
-        for (uint32_t u = 0; u < k; u++) {
-            if ((placed >> u) & 1) continue;
-            uint32_t wm = (uint32_t)__builtin_popcountll(nb[u] & placed);
-            uint32_t wn = 0;
-            for (uint64_t m = placed; m; m &= m - 1) {
-                uint32_t w = (uint32_t)__builtin_ctzll(m);
-                if (nb[u] & nb[w] & ~placed) wn++;
-            }
-            bool take;
-            if (best < 0) take = true;
-            else if (wm != bwm) take = wm > bwm;
-            else if (wn != bwn) take = wn > bwn;
-            else if (odeg[u] != bdeg) take = odeg[u] > bdeg;
-            else take = use_si && dsize[u] < bdom;
-            if (take) { best = (int)u; bwm = wm; bwn = wn; bdeg = odeg[u]; bdom = dsize[u]; }
-        }
-        pl.order[len++] = (uint32_t)best;
-        placed |= 1ull << best;
-    }
+    constraint_first_order(nb, odeg, dsize, k, use_dom, use_si, pl.order);
 
     uint32_t pos_of[KMAX];
     for (uint32_t i = 0; i < k; i++) pos_of[pl.order[i]] = i;

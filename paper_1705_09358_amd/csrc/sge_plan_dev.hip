@@ -299,7 +299,6 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
             unsigned long long row = 0, lrow = 0;
             // the pattern node's label, degree and needs are uniform LDS reads (broadcasts)
             if (ngroups == 0) {
-#pragma unroll 4
                 for (uint32_t u = 0; u < k; u++) {
                     const uint32_t lu = s_lab[u], du = s_deg[u];
                     const bool p = valid & ((lu == LABEL_ANY) | (vl == lu)) & (vd >= du);
@@ -613,19 +612,19 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
     }
     const bool empty = s_empty != 0;
 
-    // the constraint-first order (one wave; lane u scores pattern node u)
-    if (!empty && wave == 0) {
-        const uint32_t mysz = mine && use_dom ? s_dsize[lane] : 0u;
-        const unsigned long long all = k == 64 ? ~0ull : ((1ull << k) - 1);
+    // the constraint-first order.  RI's depends on the pattern alone and was
+    // computed when the pattern was loaded; with domains one wave scores the
+    // pattern nodes (lane u: node u)
+    if (!use_dom && (uint32_t)tid < k) s_order[tid] = pat->ri_order[tid];
+    if (use_dom && !empty && wave == 0) {
+        const uint32_t mysz = mine ? s_dsize[lane] : 0u;
         unsigned long long placed = 0;
         uint32_t len = 0;
-        if (use_dom) {
-            for (unsigned long long single = __ballot(mine && mysz == 1); single; single &= single - 1) {
-                const uint32_t u = (uint32_t)__builtin_ctzll(single);
-                if (lane == 0) s_order[len] = u;
-                len++;
-                placed |= 1ull << u;
-            }
+        for (unsigned long long single = __ballot(mine && mysz == 1); single; single &= single - 1) {
+            const uint32_t u = (uint32_t)__builtin_ctzll(single);
+            if (lane == 0) s_order[len] = u;
+            len++;
+            placed |= 1ull << u;
         }
         while (len < k) {
             // w_n(u) counts the placed w sharing an unplaced neighbour x with u:
