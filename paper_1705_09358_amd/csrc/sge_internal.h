@@ -208,6 +208,7 @@ struct PlanIn {
     const uint8_t *nbr_deg;       // the target's neighbour-degree table (nbr_cols columns), or null
     uint32_t nbr_cols, nbr_stride;
     uint32_t rows;                // build support sets from adjacency rows (dense targets), not lists
+    uint32_t deg_mean;            // the target's mean degree, rounded up
     InstDesc *desc;               // the instance's search descriptor (col, node read; nroot written)
     DevPlan *plan;                // written
     uint64_t *dom;                // k*W words: domains by pattern node (written)

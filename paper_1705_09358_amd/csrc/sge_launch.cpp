@@ -277,6 +277,7 @@ sge_status pack_instances(sge_ctx *c, const std::vector<const InstanceSpec *> &s
         // an adjacency row (W words) is cheaper than a neighbour list once the
         // mean degree reaches W
         r.rows = sp.t->d_adj && sp.t->g.n && sp.t->g.col.size() >= (uint64_t)sp.t->g.n * sp.t->W ? 1u : 0u;
+        r.deg_mean = sp.t->g.n ? (uint32_t)std::min<uint64_t>((sp.t->g.col.size() + sp.t->g.n - 1) / sp.t->g.n, 0xFFFFFFFFull) : 0u;
     }
     bufs.work.inst = (InstDesc *)(db + off_desc);
     bufs.work.chunk_prefix = (unsigned *)(db + pk.off_pref);

@@ -148,6 +148,7 @@ extern "C" sge_status sge_count_noalloc(sge_ctx *c, uint32_t target, uint32_t pa
     r.list_cap = (uint32_t)std::min<uint64_t>(list_entries(s), 0xFFFFFFFFull);
     r.support = s.t->W > PLAN_LDS_WORDS ? (uint64_t *)(base + L.support) : nullptr;
     r.rows = s.t->d_adj && s.t->g.n && s.t->g.col.size() >= (uint64_t)s.t->g.n * s.t->W ? 1u : 0u;
+    r.deg_mean = s.t->g.n ? (uint32_t)std::min<uint64_t>((s.t->g.col.size() + s.t->g.n - 1) / s.t->g.n, 0xFFFFFFFFull) : 0u;
 
     DevWork w;
     w.sched = (Sched *)(base + L.sched);

@@ -106,15 +106,6 @@ __device__ __forceinline__ unsigned long long wave_or64(unsigned long long x) {
     return ((unsigned long long)wave_reduce((uint32_t)(x >> 32), o) << 32) | wave_reduce((uint32_t)x, o);
 }
 
-// the lane holding the largest 64-bit key (keys distinct, or all zero: lane 0)
-__device__ __forceinline__ uint32_t wave_argmax(unsigned long long key) {
-    const auto mx = [](uint32_t a, uint32_t b) { return a > b ? a : b; };
-    const uint32_t hi = (uint32_t)(key >> 32), lo = (uint32_t)key;
-    const uint32_t hmax = wave_reduce(hi, mx);
-    const uint32_t lmax = wave_reduce(hi == hmax ? lo : 0u, mx);
-    return (uint32_t)__builtin_ctzll(__ballot(hi == hmax && lo == lmax));
-}
-
 // bits of word t (nodes 64t .. 64t+63) that lie in [lo, hi)
 __device__ __forceinline__ unsigned long long range_mask(uint32_t t, uint32_t lo, uint32_t hi) {
     const unsigned long long base = (unsigned long long)t * 64;
@@ -132,7 +123,8 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
     __shared__ uint32_t s_lab[KMAX], s_deg[KMAX], s_dsize[KMAX], s_order[KMAX], s_pos[KMAX];
     __shared__ uint32_t s_bw[KMAX], s_aff[KMAX];
     __shared__ int32_t s_par[KMAX];
-    __shared__ unsigned long long s_mu[KMAX];
+    __shared__ unsigned long long s_mu[KMAX], s_fix_m[KMAX];
+    __shared__ uint32_t s_first[KMAX], s_fix_t[KMAX], s_nfix;
     __shared__ unsigned long long s_need[KMAX * (TAB_COLS / 8)];
     __shared__ uint32_t s_coff[TAB_COLS], s_cix[KMAX], s_ncols;   // column byte offsets in the table
     __shared__ unsigned long long s_next;
@@ -154,6 +146,7 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
 
     if ((uint32_t)tid < k) {
         s_dsize[tid] = 0;
+        s_first[tid] = 0xFFFFFFFFu;
         s_nb[tid] = pat->nb[tid];
         s_deg[tid] = pat->deg[tid];
         s_lab[tid] = R.labelled ? label_id(glob(R.label_keys), R.nlabels, pat->label[tid]) : LABEL_ANY;
@@ -251,12 +244,14 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
         A1 = A[1] | H;
         A2 = A[2] | H;
     };
-    // RI-DS on a target of up to PLAN_WAVES * DT_WORDS words (and not by
-    // adjacency rows): each lane keeps, for its nodes v = 64 i + lane
-    // (i = wave + PLAN_WAVES t), dt[t] = the pattern nodes whose domain holds
-    // v, in registers through the arc-consistency rounds; the domain rows are
-    // written once, at the end
-    const bool reg_ac = use_dom && !R.rows && W <= PLAN_WAVES * DT_WORDS && W * 64 <= lds_words;
+    // RI-DS on a target of up to PLAN_WAVES * DT_WORDS words: each lane
+    // keeps, for its nodes v = 64 i + lane (i = wave + PLAN_WAVES t), dt[t] =
+    // the pattern nodes whose domain holds v, in registers through the
+    // arc-consistency rounds; the domain rows are written once, at the end.
+    // A round reads each node's list once, so adjacency rows (ORed a word at
+    // a time per member of every dirty domain) pay only on targets whose mean
+    // degree exceeds 8 W
+    const bool reg_ac = use_dom && (!R.rows || R.deg_mean <= 8 * W) && W <= PLAN_WAVES * DT_WORDS && W * 64 <= lds_words;
     unsigned long long dt[DT_WORDS];
     if (reg_ac) {
         unsigned long long chg = 0;   // pattern nodes the table round removed a node from
@@ -494,12 +489,15 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
                 dirty = s_next;
                 __syncthreads();
             }
-            // the domain rows (lane u: row u of each of the wave's words) and sizes
+            // the domain rows (lane u: row u of each of the wave's words) and
+            // sizes; the memberships stay in LDS (T[v], for forward checking)
+            // with a member of each domain
             uint32_t cnt = 0;
 #pragma unroll
             for (uint32_t t = 0; t < DT_WORDS; t++) {
                 const uint32_t i = wave + t * PLAN_WAVES;
                 if (i < W) {
+                    T[i * 64 + lane] = dt[t];
                     unsigned long long row = 0;
                     for (uint32_t u = 0; u < k; u++) {
                         const unsigned long long b = __ballot((dt[t] >> u) & 1ull);
@@ -508,6 +506,7 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
                     if (mine) {
                         D[(size_t)lane * W + i] = row;
                         cnt += (uint32_t)__popcll(row);
+                        if (row) atomicMin(&s_first[lane], i * 64 + (uint32_t)__builtin_ctzll(row));
                     }
                 }
             }
@@ -572,7 +571,79 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
     __syncthreads();
 
     // forward checking (one wave; lane u holds |D(u)|)
-    if (R.mode == SGE_RIDS_SI_FC && !s_empty) {
+    if (R.mode == SGE_RIDS_SI_FC && !s_empty && reg_ac) {
+        // with the memberships in LDS (T[v]: the pattern nodes whose domain
+        // holds v), every singleton of a cascade level at once (the removals
+        // of distinct members commute, and a member shared by two singletons
+        // empties both): lane u of a singleton finds its member (the
+        // recorded first member of D(u) unless a removal took it, then T is
+        // scanned), T tells which domains lose it, and the domain words that
+        // changed are rewritten from T afterwards
+        unsigned long long *T = s_support;
+        if (wave == 0) {
+            unsigned long long done = 0;
+            uint32_t mysize = (uint32_t)lane < k ? s_dsize[lane] : 0;
+            bool emp = false;
+            uint32_t nfix = 0;
+            while (!emp) {
+                const unsigned long long cand = __ballot((uint32_t)lane < k && !((done >> lane) & 1ull) && mysize == 1);
+                if (!cand) break;
+                done |= cand;
+                const bool single = (cand >> lane) & 1ull;
+                uint32_t t = single ? s_first[lane] : 0u;
+                const bool none = t == 0xFFFFFFFFu;
+                if (none) t = 0;   // (every T index stays in range)
+                const bool lost = single && (none || !((T[t] >> lane) & 1ull));
+                for (unsigned long long m = __ballot(lost); m; m &= m - 1) {   // (rare) scan for the member
+                    const uint32_t u = (uint32_t)__builtin_ctzll(m);
+                    uint32_t found = 0;
+                    for (uint32_t i0 = 0; i0 < W * 64; i0 += 64) {
+                        const unsigned long long b = __ballot((T[i0 + lane] >> u) & 1ull);
+                        if (b) {
+                            found = i0 + (uint32_t)__builtin_ctzll(b);
+                            break;
+                        }
+                    }
+                    if ((uint32_t)lane == u) t = found;   // (|D(u)| = 1: a member exists)
+                }
+                const unsigned long long lose = single ? T[t] & ~(1ull << lane) : 0ull;
+                // lane w: one node less for every singleton whose member lies in D(w)
+                uint32_t dec = 0;
+                for (unsigned long long m = cand; m; m &= m - 1) {
+                    const int u = (int)__builtin_ctzll(m);
+                    const unsigned long long lu =
+                        ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(lose >> 32), u) << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)lose, u);
+                    dec += (uint32_t)((lu >> lane) & 1ull);
+                }
+                mysize -= dec;
+                if (single) {
+                    const uint32_t f = nfix + (uint32_t)__popcll(cand & ((1ull << lane) - 1));
+                    s_fix_t[f] = t;
+                    s_fix_m[f] = lose;
+                    T[t] = 1ull << lane;
+                }
+                nfix += (uint32_t)__popcll(cand);
+                emp = __ballot((uint32_t)lane < k && mysize == 0) != 0ull;
+            }
+            if ((uint32_t)lane < k) s_dsize[lane] = mysize;
+            if (lane == 0) {
+                s_nfix = nfix;
+                if (emp) s_empty = 1;
+            }
+        }
+        __syncthreads();
+        for (uint32_t f = wave; f < s_nfix; f += PLAN_WAVES) {
+            const uint32_t i = s_fix_t[f] >> 6;
+            const unsigned long long tv = T[i * 64 + lane];
+            for (unsigned long long m = s_fix_m[f]; m; m &= m - 1) {
+                const uint32_t w = (uint32_t)__builtin_ctzll(m);
+                const unsigned long long b = __ballot((tv >> w) & 1ull);
+                if (lane == 0) D[(size_t)w * W + i] = b;
+            }
+        }
+        __syncthreads();
+    } else if (R.mode == SGE_RIDS_SI_FC && !s_empty) {
         if (wave == 0) {
             unsigned long long done = 0;
             uint32_t mysize = (uint32_t)lane < k ? s_dsize[lane] : 0;
@@ -618,6 +689,13 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
     if (!use_dom && (uint32_t)tid < k) s_order[tid] = pat->ri_order[tid];
     if (use_dom && !empty && wave == 0) {
         const uint32_t mysz = mine ? s_dsize[lane] : 0u;
+        // with SI, the key holds u's rank among the domain sizes (the number
+        // of pattern nodes with a smaller domain: the same order and the same
+        // ties as the sizes, in six bits)
+        uint32_t srank = 0;
+        if (use_si)
+            for (uint32_t w = 0; w < k; w++)
+                srank += (uint32_t)__builtin_amdgcn_readlane((int)mysz, (int)w) < mysz ? 1u : 0u;
         unsigned long long placed = 0;
         uint32_t len = 0;
         for (unsigned long long single = __ballot(mine && mysz == 1); single; single &= single - 1) {
@@ -640,20 +718,18 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
                     (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mynb, x);
                 two_hop |= nx & (0ull - ((mynb >> x) & 1ull));
             }
-            unsigned long long key = 0;
+            uint32_t key = 0;
             if (mine && !((placed >> lane) & 1ull)) {
                 const uint32_t wm = (uint32_t)__popcll(mynb & placed);
                 const uint32_t wn = (uint32_t)__popcll(two_hop & placed);
-                // w_m, w_n and degree are below 64; the smaller domain and then
-                // the lower id win the remaining ties
-                key = (1ull << 62) | ((unsigned long long)wm << 50) | ((unsigned long long)wn << 44) |
-                      ((unsigned long long)mydeg << 38) | ((unsigned long long)(use_si ? ~mysz : 0u) << 6) |
-                      (unsigned long long)(63 - lane);
+                // w_m, w_n and degree are below 64; the smaller domain (a
+                // larger 63 - rank) and then the lower id win the remaining ties
+                key = (1u << 30) | (wm << 24) | (wn << 18) | (mydeg << 12) | ((63u - srank) << 6) | (63u - lane);
             }
-            // the keys are distinct (their lowest bits are the lane), so one
-            // lane holds the maximum; its ballot names it as a wave-uniform
-            // value, which keeps `placed` and the loop above scalar
-            const uint32_t u = wave_argmax(key);
+            // the keys are distinct (their lowest bits are the lane), so the
+            // wave-wide maximum, a wave-uniform value, names the node, which
+            // keeps `placed` and the loop above scalar
+            const uint32_t u = 63u - (wave_reduce(key, [](uint32_t a, uint32_t b) { return a > b ? a : b; }) & 63u);
             if (lane == 0) s_order[len] = u;
             len++;
             placed |= 1ull << u;

@@ -149,3 +149,41 @@ def test_plan_wide_target_support_in_global_memory(planner, orc):
     P = G.from_edges(4, [(0, 1), (1, 2), (2, 3), (3, 0)], [0, 1, 0, 2])
     for mode in (sge.RIDS, sge.RIDS_SI_FC):
         planner.check(orc, P, T, mode, True)
+
+
+def _many_label_instance(seed: int, n: int, nlab: int, k: int):
+    # a contact-like target with `nlab` uniformly drawn labels and a
+    # random-walk pattern on it, so that more pattern labels occur than the
+    # plan kernel packs per target node (24 table columns)
+    g = np.random.default_rng(seed)
+    T = synth.contact_target(g, n)
+    T = synth.Graph(T.n, T.row_ptr, T.col, g.integers(0, nlab, size=T.n).astype(np.uint32))
+    P, _ = synth.induced_pattern(g, T, synth.walk_selection(g, T, k))
+    return T, P
+
+
+@pytest.mark.parametrize("n", [1500, 7000])
+def test_plan_more_pattern_labels_than_packed_columns(planner, orc, n):
+    # over 24 distinct labels among the pattern's nodes: the first
+    # arc-consistency round cannot use the packed table bytes; on the
+    # register path (n <= 6144) the rounds start from every node with a
+    # neighbour, on the row path the table round reads column by column
+    T, P = _many_label_instance(91 + n, n, 48, 56)
+    distinct = len(set(P.labels.tolist()))
+    _note(f"plan many labels: n={T.n} k={P.n} distinct pattern labels {distinct}")
+    assert distinct > 24
+    for mode in range(4):
+        planner.check(orc, P, T, mode, True)
+
+
+@pytest.mark.parametrize("n", [64 * 96, 64 * 96 + 1])
+def test_plan_register_path_boundary(planner, orc, n):
+    # 96 words (6144 nodes) is the widest target whose domain memberships the
+    # plan kernel keeps in registers; one node more takes the support-row path
+    g = np.random.default_rng(5000 + n)
+    T = synth.contact_target(g, n)
+    P, _ = synth.induced_pattern(g, T, synth.walk_selection(g, T, 40))
+    _note(f"plan register boundary: n={T.n} k={P.n}")
+    for mode in (sge.RIDS, sge.RIDS_SI_FC):
+        planner.check(orc, P, T, mode, True)
+        planner.check(orc, P, T, mode, False)
