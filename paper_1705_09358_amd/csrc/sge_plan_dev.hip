@@ -440,6 +440,14 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
             // round the first round starts from every node with a neighbour,
             // which reaches the same fixpoint.)
             unsigned long long *T = s_support;
+            // a node index recomputed where it is used (an opaque copy of the
+            // lane): hoisted out of the unrolled loops below, the addresses of
+            // all DT_WORDS words spill
+            auto node_of = [&](uint32_t i) {
+                uint32_t l = (uint32_t)lane;
+                asm volatile("" : "+v"(l));
+                return i * 64 + l;
+            };
             while (dirty) {
                 unsigned long long aff = 0;
                 for (unsigned long long m = dirty; m; m &= m - 1) aff |= s_nb[__builtin_ctzll(m)];
@@ -452,7 +460,7 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
                     const uint32_t i = wave + t * PLAN_WAVES;
                     const unsigned long long mask = i < W ? dt[t] & dirty : 0ull;
                     if (mask) {   // a member of some dirty domain: node i * 64 + lane < n
-                        const NodeRec r = ld_node(node + i * 64 + lane);
+                        const NodeRec r = ld_node(node + node_of(i));
                         uint32_t e = r.begin;
                         const uint32_t end = r.begin + r.deg;
                         for (; e + 4 <= end; e += 4) {
@@ -472,7 +480,7 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
                 for (uint32_t t = 0; t < DT_WORDS; t++) {
                     const uint32_t i = wave + t * PLAN_WAVES;
                     if (i < W) {
-                        const unsigned long long tv = T[i * 64 + lane];
+                        const unsigned long long tv = T[node_of(i)];
                         unsigned long long fail = 0;
                         for (unsigned long long m = dt[t] & aff; m; m &= m - 1) {
                             const uint32_t u = (uint32_t)__builtin_ctzll(m);
@@ -497,7 +505,7 @@ __global__ void __launch_bounds__(PLAN_THREADS, 6) plan_kernel(const PlanIn *req
             for (uint32_t t = 0; t < DT_WORDS; t++) {
                 const uint32_t i = wave + t * PLAN_WAVES;
                 if (i < W) {
-                    T[i * 64 + lane] = dt[t];
+                    T[node_of(i)] = dt[t];
                     unsigned long long row = 0;
                     for (uint32_t u = 0; u < k; u++) {
                         const unsigned long long b = __ballot((dt[t] >> u) & 1ull);
