@@ -101,6 +101,11 @@ def run_batch_workload(ctx, torch, insts, man, steps, warmup, label):
             raise SystemExit(f"{label}: counts differ from the oracle's stored values")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    # the last launch's search units and the share of their time spent holding
+    # tasks (the shape the autotuner picked shows in the unit count)
+    busy_ms, units = ctx.last_launch_occupancy()
+    launch = dict(units=int(units),
+                  busy_fraction=busy_ms / (units * ev_ms[-1]) if units and ev_ms[-1] > 0 else None)
     if int(res.alg_bytes.sum()) != alg_bytes:
         raise SystemExit(f"{label}: algorithmic bytes changed between launches")
     tot_states = int(want_states.sum()) * steps
@@ -110,7 +115,7 @@ def run_batch_workload(ctx, torch, insts, man, steps, warmup, label):
         raise SystemExit(f"{label}: the search kernel's events recorded nothing ({ctx.last_error()})")
     return dict(ms_per_step=1000 * el / steps, states_per_s=tot_states / el, matches_per_s=tot_matches / el,
                 kernel_ms=kernel_ms, kernel_ms_device_clock=sum(dev_ms) / len(dev_ms),
-                prep_ms=float(res.ms_prep[0]), jobs=jobs, tgt=tgt, model=model, alg_bytes=alg_bytes,
+                prep_ms=float(res.ms_prep[0]), launch=launch, jobs=jobs, tgt=tgt, model=model, alg_bytes=alg_bytes,
                 roofline=dict(roofline(alg_bytes, kernel_ms), alg_bytes_per_state=alg_bytes / int(want_states.sum())),
                 instances=len(jobs),
                 states_per_step=int(want_states.sum()), matches_per_step=int(want_matches.sum()))
@@ -622,6 +627,7 @@ def main():
         "matches_per_s": b["matches_per_s"],
         "kernel_ms_per_step": b["kernel_ms"],
         "kernel_ms_device_clock": b["kernel_ms_device_clock"],
+        "search_launch": b["launch"],
         "prep_ms_per_step": b["prep_ms"],
         "plain": plain,
         "vs_plain": None if plain is None else b["states_per_s"] / plain["states_per_s"],
