@@ -136,17 +136,20 @@ def test_plan_disconnected_pattern(planner, orc):
         assert (b["parent"] < 0).sum() == 4   # components {0,1}, {2,3}, {4}, {5}
 
 
-def test_plan_wide_target_support_in_global_memory(planner, orc):
-    # more than 4096 bitset words per domain row: the support set of the
-    # arc-consistency rounds lives in device memory instead of LDS
+@pytest.mark.parametrize("words", [4112, 8208])
+def test_plan_wide_target_support_in_global_memory(planner, orc, words):
+    # rows of 4112 words: the bit-row support sets live in LDS, one dirty
+    # node per batch; more than 8192 words (the plan kernel's LDS budget):
+    # they live in device memory
     g = np.random.default_rng(77)
-    n = 64 * 4096 + 1000
+    n = 64 * words - 24
     src = g.integers(0, n, size=3 * n)
     dst = g.integers(0, n, size=3 * n)
     keep = src != dst
     rp, col = synth.csr_from_edges(n, src[keep], dst[keep])
     T = synth.Graph(n, rp, col, g.integers(0, 3, size=n).astype(np.uint32))
     P = G.from_edges(4, [(0, 1), (1, 2), (2, 3), (3, 0)], [0, 1, 0, 2])
+    _note(f"plan wide target: n={n}, {(n + 63) // 64} words per row")
     for mode in (sge.RIDS, sge.RIDS_SI_FC):
         planner.check(orc, P, T, mode, True)
 
